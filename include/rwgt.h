@@ -1,0 +1,107 @@
+/*
+ * rwgt.h - C ABI of the MI355X matrix-element reweighting library (librwgt.so).
+ *
+ * The operation is the parameter-reweighting rule of the paper's teaRex
+ * section: for events with weights w sampled under an original parameter card
+ * theta, a new card theta' gives
+ *
+ *     w'_i = (w_i * (1 / |M|^2(p_i; theta))) * |M|^2(p_i; theta'),   1/0 -> 0
+ *
+ * (the normaliser / backlog order of procReweightor, the ratio of the teaRex
+ * introduction), where |M|^2 is the tree-level squared matrix element summed
+ * over helicities and colours and averaged over initial spins and colours
+ * (MadtRex section: leading order, helicity-summed).  The per-event evaluation
+ * of |M|^2 is the data-parallel hot path the MadtRex section hands to the
+ * CUDACPP kernels; here it runs in hand-written HIP kernels on one gfx950 GPU.
+ *
+ * Conventions shared by every entry point:
+ *  - momenta: [nevt][npart][4] doubles (E, px, py, pz) in GeV, particle order
+ *    as in the process string, incoming first, DEVICE memory;
+ *  - weights_in [nevt], weights_out [nsets][nevt], me2_out [nsets][nevt]:
+ *    doubles in DEVICE memory;
+ *  - param_sets [nsets][npar]: doubles in HOST memory, one row per new card,
+ *    columns in the order reported by rwgt_param_layout;
+ *  - the caller owns every array; the library never frees caller memory;
+ *  - work is enqueued on the context's stream (rwgt_set_stream; default the
+ *    null stream) and the call returns after enqueueing: synchronise the
+ *    stream before reading outputs;
+ *  - return value 0 on success, a negative RWGT_E* code on error, with a
+ *    message in rwgt_last_error(ctx); no C++ exception crosses the ABI;
+ *  - a context must not be used from two host threads at once; calls on one
+ *    context are ordered by its stream.
+ */
+#ifndef RWGT_H
+#define RWGT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rwgt_ctx rwgt_ctx;
+
+enum {
+  RWGT_OK = 0,
+  RWGT_EINVAL = -1,   /* null pointer, negative size, nsets < 1 */
+  RWGT_EPROCESS = -2, /* process string not supported */
+  RWGT_ECARD = -3,    /* parameter card unparsable or missing an entry */
+  RWGT_EDEVICE = -4,  /* HIP runtime error (launch, copy) */
+  RWGT_ENOMEM = -5,   /* device or pinned allocation failed */
+  RWGT_EPARAM = -6    /* a card changes a parameter fixed by the momenta (external mass) */
+};
+
+enum {
+  RWGT_FP64 = 0,        /* every amplitude in double precision */
+  RWGT_MIXED_FP16 = 1,  /* float amplitudes, FP16 hi/lo MFMA colour sum, double ratio */
+  RWGT_MIXED_BF16 = 2   /* float amplitudes, BF16 hi/mid/lo MFMA colour sum, double ratio */
+};
+
+/* Create a context for one process on the current HIP device.
+ *  process:    "e+ e- > mu+ mu-", "u u~ > e+ e- g" or "g g > t t~ g g"
+ *              (whitespace-insensitive);
+ *  param_card: SLHA text of the ORIGINAL card (blocks SMINPUTS 1 = 1/alpha,
+ *              SMINPUTS 3 = alpha_s, RWGTEW 1 = sin^2 theta_W, MASS 6, MASS 23,
+ *              DECAY 23); only the entries the process uses are required;
+ *  precision:  RWGT_FP64 / RWGT_MIXED_FP16 / RWGT_MIXED_BF16.
+ * On success *out owns device buffers until rwgt_destroy; on error *out = NULL.
+ * Errors: RWGT_EINVAL, RWGT_EPROCESS, RWGT_ECARD, RWGT_EDEVICE, RWGT_ENOMEM. */
+int rwgt_create(const char *process, const char *param_card, int precision, rwgt_ctx **out);
+
+/* Free the context and its device buffers (after its queued work).  NULL is a no-op. */
+void rwgt_destroy(rwgt_ctx *ctx);
+
+/* Number of columns of a param_sets row and their names ("SMINPUTS 3", ...).
+ * names may be NULL; otherwise it receives npar pointers owned by ctx. */
+int rwgt_param_layout(const rwgt_ctx *ctx, int32_t *npar, const char **names);
+
+/* The original card's values in layout order (host array of npar doubles). */
+int rwgt_original_params(const rwgt_ctx *ctx, double *values);
+
+/* Stream for subsequent calls: a hipStream_t passed as void* (NULL = null stream). */
+int rwgt_set_stream(rwgt_ctx *ctx, void *stream);
+
+/* Reweight: weights_out[k][i] = (weights_in[i] * (1/|M|^2_orig[i])) * |M|^2_k[i]
+ * for the nsets cards in param_sets.  nevt = 0 is a no-op.
+ * Errors: RWGT_EINVAL, RWGT_EPARAM, RWGT_EDEVICE, RWGT_ENOMEM. */
+int rwgt_eval(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const double *weights_in,
+              const double *param_sets, int32_t nsets, double *weights_out);
+
+/* |M|^2 itself for each card of param_sets: me2_out[k][i].  Same rules as rwgt_eval. */
+int rwgt_me2(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const double *param_sets, int32_t nsets,
+             double *me2_out);
+
+/* Message of the last failed call on ctx (empty string if none). */
+const char *rwgt_last_error(const rwgt_ctx *ctx);
+
+/* Message of the last failed rwgt_create on this thread (no context exists then). */
+const char *rwgt_create_error(void);
+
+/* Process constants: particles, helicity combinations kept, colour flows, diagrams. */
+int rwgt_process_info(const rwgt_ctx *ctx, int32_t *npart, int32_t *nhel_kept, int32_t *ncol, int32_t *ndiag);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RWGT_H */

@@ -1,0 +1,43 @@
+"""MI355X-native matrix-element reweighting (paper: parameter reweighting
+w' = w |M'|^2 / |M|^2 with the per-event |M|^2 as the data-parallel hot path).
+
+The compute path lives in librwgt.so (HIP kernels for gfx950 behind the C ABI
+of include/rwgt.h); this package only marshals arguments to it.
+"""
+from ._abi import (  # noqa: F401
+    RWGT_FP64, RWGT_MIXED_BF16, RWGT_MIXED_FP16, RwgtError, load, rwgt_create, rwgt_destroy, rwgt_eval,
+    rwgt_me2, rwgt_original_params, rwgt_param_layout, rwgt_process_info, rwgt_set_stream,
+)
+
+
+class Reweighter:
+    """Context manager owning one rwgt context (calls rwgt_create/rwgt_destroy)."""
+
+    def __init__(self, process: str, param_card: str, precision: int = RWGT_FP64):
+        self.ctx = rwgt_create(process, param_card, precision)
+        self.layout = rwgt_param_layout(self.ctx)
+
+    def eval(self, momenta, weights_in, param_sets, weights_out, stream=None):
+        rwgt_set_stream(self.ctx, stream)
+        rwgt_eval(self.ctx, momenta, weights_in, param_sets, weights_out)
+
+    def me2(self, momenta, param_sets, me2_out, stream=None):
+        rwgt_set_stream(self.ctx, stream)
+        rwgt_me2(self.ctx, momenta, param_sets, me2_out)
+
+    def close(self):
+        if self.ctx:
+            rwgt_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,163 @@
+"""ctypes binding of librwgt.so (include/rwgt.h): argument marshalling only.
+
+Every function has the name of the C entry point it calls.  Device arrays are
+torch tensors on the GPU (their data pointers are passed); param_sets is a
+host array.  The library must have been built (``python -m
+paper_2510_05100_amd.build``); there is no fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librwgt.so")
+
+RWGT_FP64, RWGT_MIXED_FP16, RWGT_MIXED_BF16 = 0, 1, 2
+ERRORS = {-1: "RWGT_EINVAL", -2: "RWGT_EPROCESS", -3: "RWGT_ECARD", -4: "RWGT_EDEVICE",
+          -5: "RWGT_ENOMEM", -6: "RWGT_EPARAM"}
+
+# symbol name -> (restype, argtypes), exactly as declared in include/rwgt.h
+SIGNATURES = {
+    "rwgt_create": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    "rwgt_destroy": (None, [ctypes.c_void_p]),
+    "rwgt_param_layout": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_char_p)]),
+    "rwgt_original_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "rwgt_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rwgt_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                  ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_void_p]),
+    "rwgt_me2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                 ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_void_p]),
+    "rwgt_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "rwgt_create_error": (ctypes.c_char_p, []),
+    "rwgt_process_info": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int32)] * 4),
+}
+
+_lib = None
+
+
+class RwgtError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"{ERRORS.get(code, code)}: {message}")
+        self.code = code
+
+
+def load():
+    """Load librwgt.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2510_05100_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _check_device(t, name, shape_prefix=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 tensor")
+
+
+def _host_params(param_sets):
+    a = np.ascontiguousarray(np.asarray(param_sets, dtype=np.float64))
+    if a.ndim == 1:
+        a = a[None, :]
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _raise(code, ctx=None):
+    lib = load()
+    msg = lib.rwgt_last_error(ctx) if ctx is not None else lib.rwgt_create_error()
+    raise RwgtError(code, (msg or b"").decode())
+
+
+def rwgt_create(process: str, param_card: str, precision: int = RWGT_FP64):
+    lib = load()
+    out = ctypes.c_void_p()
+    rc = lib.rwgt_create(process.encode(), param_card.encode(), int(precision), ctypes.byref(out))
+    if rc != 0:
+        _raise(rc)
+    return out
+
+
+def rwgt_destroy(ctx):
+    if ctx:
+        load().rwgt_destroy(ctx)
+
+
+def rwgt_param_layout(ctx):
+    lib = load()
+    n = ctypes.c_int32()
+    rc = lib.rwgt_param_layout(ctx, ctypes.byref(n), None)
+    if rc != 0:
+        _raise(rc, ctx)
+    names = (ctypes.c_char_p * n.value)()
+    lib.rwgt_param_layout(ctx, ctypes.byref(n), names)
+    return [s.decode() for s in names]
+
+
+def rwgt_original_params(ctx):
+    n = len(rwgt_param_layout(ctx))
+    out = (ctypes.c_double * n)()
+    rc = load().rwgt_original_params(ctx, out)
+    if rc != 0:
+        _raise(rc, ctx)
+    return np.array(out[:], dtype=np.float64)
+
+
+def rwgt_set_stream(ctx, stream=None):
+    """stream: a torch.cuda.Stream, a raw hipStream_t integer, or None (current torch stream)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    rc = load().rwgt_set_stream(ctx, ctypes.c_void_p(handle))
+    if rc != 0:
+        _raise(rc, ctx)
+
+
+def rwgt_eval(ctx, momenta, weights_in, param_sets, weights_out):
+    """weights_out[k, i] = weights_in[i] / |M|^2_orig[i] * |M|^2_k[i] (enqueued on the set stream)."""
+    _check_device(momenta, "momenta")
+    _check_device(weights_in, "weights_in")
+    _check_device(weights_out, "weights_out")
+    nevt = momenta.shape[0] if momenta.dim() > 0 else 0
+    params, pptr = _host_params(param_sets)
+    if weights_out.numel() != params.shape[0] * nevt or weights_in.numel() != nevt:
+        raise ValueError("weights_in must be [nevt] and weights_out [nsets, nevt]")
+    rc = load().rwgt_eval(ctx, _ptr(momenta), nevt, _ptr(weights_in), pptr, params.shape[0], _ptr(weights_out))
+    if rc != 0:
+        _raise(rc, ctx)
+
+
+def rwgt_me2(ctx, momenta, param_sets, me2_out):
+    _check_device(momenta, "momenta")
+    _check_device(me2_out, "me2_out")
+    nevt = momenta.shape[0]
+    params, pptr = _host_params(param_sets)
+    if me2_out.numel() != params.shape[0] * nevt:
+        raise ValueError("me2_out must be [nsets, nevt]")
+    rc = load().rwgt_me2(ctx, _ptr(momenta), nevt, pptr, params.shape[0], _ptr(me2_out))
+    if rc != 0:
+        _raise(rc, ctx)
+
+
+def rwgt_process_info(ctx):
+    vals = [ctypes.c_int32() for _ in range(4)]
+    rc = load().rwgt_process_info(ctx, *[ctypes.byref(v) for v in vals])
+    if rc != 0:
+        _raise(rc, ctx)
+    return dict(zip(("npart", "nhel_kept", "ncol", "ndiag"), (v.value for v in vals)))

@@ -1,0 +1,85 @@
+"""Build librwgt.so in-tree for gfx950: generate the per-process headers, then
+compile every translation unit with hipcc in parallel and link.
+
+    python -m paper_2510_05100_amd.build [--jobs N] [--verbose]
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "librwgt.so")
+ARCH = "gfx950"
+
+SOURCES = ["kernels.hip", "proc_ee_mumu.hip", "proc_uu_eeg.hip", "proc_gg_ttgg.hip", "rwgt_abi.cpp"]
+
+# -packed-fp32-ops: no v_pk_{add,mul,fma}_f32 in generated code.
+HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-I" + CSRC,
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Wno-unused-command-line-argument"]
+
+
+def hipcc():
+    exe = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(exe):
+        raise RuntimeError("hipcc not found")
+    return exe
+
+
+def _newest_input(src):
+    paths = [os.path.join(CSRC, src)]
+    for root, _, files in os.walk(CSRC):
+        paths += [os.path.join(root, f) for f in files if f.endswith(".h")]
+    paths.append(os.path.join(os.path.dirname(CSRC), "..", "include", "rwgt.h"))
+    return max(os.path.getmtime(p) for p in paths if os.path.exists(p))
+
+
+def _compile(src, verbose, incremental=False):
+    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+    if incremental and os.path.exists(obj) and os.path.getmtime(obj) > _newest_input(src):
+        return obj
+    cmd = [hipcc()] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    t0 = time.time()
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{res.stderr[-4000:]}")
+    if verbose:
+        print(f"  {src}: {time.time() - t0:.1f}s", flush=True)
+    return obj
+
+
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (or, with incremental=True, those whose inputs
+    changed) and link librwgt.so."""
+    from .procgen.__main__ import main as procgen_main
+    procgen_main(os.path.join(CSRC, "generated"))
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose, incremental), SOURCES))
+    tmp = LIB + ".tmp"
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"link failed:\n{res.stderr[-4000:]}")
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--incremental", action="store_true", help="recompile only changed translation units")
+    a = ap.parse_args()
+    t = time.time()
+    print(build(a.jobs, a.verbose, a.incremental), f"({time.time() - t:.0f}s)")
+    sys.exit(0)

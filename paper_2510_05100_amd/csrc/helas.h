@@ -1,0 +1,329 @@
+// Per-lane helicity-amplitude building blocks for gfx950 (one event per lane).
+//
+// The paper names the roles of these routines only (external wavefunctions
+// ixxxxx / oxxxxx / vxxxxx, vertex amplitude FFV1_0, off-shell currents such as
+// VVV1P0_1); what they compute here is written from the textbook Feynman rules:
+//
+//   metric diag(+,-,-,-), chiral Dirac basis psi = (psi_L, psi_R),
+//   gamma^mu V_mu = [[0, V.sigma], [V.sigmabar, 0]],
+//     V.sigma    = [[V0 - V3, -(V1 - i V2)], [-(V1 + i V2), V0 + V3]],
+//     V.sigmabar = [[V0 + V3,   V1 - i V2 ], [  V1 + i V2,  V0 - V3]],
+//   fermion-boson vertex  Gamma(V) = V-slash (cL P_L + cR P_R)  (vertex factors
+//   i g_s, -i e Q, -i e/(s_W c_W) g_{L,R} are folded into the complex cL, cR),
+//   fermion propagator    i (q-slash + m) / (q^2 - m^2),
+//   massless vector       -i g_{mu nu} / q^2,
+//   massive vector        -i (g_{mu nu} - q_mu q_nu / M^2) / (q^2 - M^2 + i M W),
+//   three-gluon vertex    g f^{abc} [g^{mn}(k-p)^r + g^{nr}(p-q)^m + g^{rm}(q-k)^n],
+//   four-gluon vertex     -i g^2 [f^{abe} f^{cde} (g^{mr} g^{ns} - g^{ms} g^{nr}) + 2 more].
+//
+// R is the amplitude precision (double, or float in the mixed mode).  Momenta,
+// propagator denominators and the resonant Z denominator are always formed in
+// double and only their reciprocals are rounded to R.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace rwgt {
+
+template <class R> struct cx { R re, im; };
+
+template <class R> __host__ __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <class R> __host__ __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <class R> __host__ __device__ __forceinline__ cx<R> operator-(cx<R> a) { return {-a.re, -a.im}; }
+template <class R> __host__ __device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class R> __host__ __device__ __forceinline__ cx<R> operator*(cx<R> a, R s) { return {a.re * s, a.im * s}; }
+template <class R> __host__ __device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {a.re * s, a.im * s}; }
+template <class R> __host__ __device__ __forceinline__ cx<R> conj(cx<R> a) { return {a.re, -a.im}; }
+template <class R> __host__ __device__ __forceinline__ cx<R> times_i(cx<R> a) { return {-a.im, a.re}; }
+template <class R> __host__ __device__ __forceinline__ cx<R> times_minus_i(cx<R> a) { return {a.im, -a.re}; }
+
+template <class R> struct Spinor { cx<R> c[4]; };   // column (flowing in) or row (flowing out)
+template <class R> struct Vec { cx<R> c[4]; };      // vector field, upper index
+
+template <class R> __host__ __device__ __forceinline__ cx<R> mdot(const Vec<R>& a, const Vec<R>& b) {
+  return a.c[0] * b.c[0] - a.c[1] * b.c[1] - a.c[2] * b.c[2] - a.c[3] * b.c[3];
+}
+template <class R> __host__ __device__ __forceinline__ cx<R> mdot(const double* k, const Vec<R>& a) {
+  return a.c[0] * R(k[0]) - a.c[1] * R(k[1]) - a.c[2] * R(k[2]) - a.c[3] * R(k[3]);
+}
+__host__ __device__ __forceinline__ double msq(const double* k) {
+  return k[0] * k[0] - k[1] * k[1] - k[2] * k[2] - k[3] * k[3];
+}
+
+// ------------------------------------------------------------ external states
+// Helicity 2-spinors along p: chi_+ = (cos t/2, e^{if} sin t/2),
+// chi_- = (-e^{-if} sin t/2, cos t/2), written with |p| + pz instead of angles.
+template <class R>
+__host__ __device__ __forceinline__ void helicity_basis(const double* p, double pabs, cx<R>& a0, cx<R>& a1, int lam) {
+  const double pt2 = p[1] * p[1] + p[2] * p[2];
+  // |p| + pz without cancellation when pz < 0
+  const double ppz = p[3] >= 0.0 ? pabs + p[3] : (pt2 > 0.0 ? pt2 / (pabs - p[3]) : 0.0);
+  if (ppz > 0.0) {
+    const double nrm = 1.0 / sqrt(2.0 * pabs * ppz);
+    if (lam > 0) {
+      a0 = {R(ppz * nrm), R(0)};
+      a1 = {R(p[1] * nrm), R(p[2] * nrm)};
+    } else {
+      a0 = {R(-p[1] * nrm), R(p[2] * nrm)};
+      a1 = {R(ppz * nrm), R(0)};
+    }
+  } else {  // along -z
+    if (lam > 0) { a0 = {R(0), R(0)}; a1 = {R(1), R(0)}; }
+    else         { a0 = {R(-1), R(0)}; a1 = {R(0), R(0)}; }
+  }
+}
+
+// ixxxxx role: spinor flowing into the diagram.  nsf = +1: u(p, h) of an
+// incoming fermion; nsf = -1: v(p, h) of an outgoing antifermion.
+//   u = (sqrt(E - h|p|) chi_h, sqrt(E + h|p|) chi_h)
+//   v = (sqrt(E + h|p|) chi_-h, -sqrt(E - h|p|) chi_-h)
+template <class R>
+__host__ __device__ __forceinline__ Spinor<R> ixx(const double* p, double m, int h, int nsf) {
+  const double pabs = sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
+  const double big = sqrt(p[0] + pabs);
+  const double small = m / big;           // sqrt(E - |p|), exactly 0 for m = 0
+  Spinor<R> s;
+  cx<R> x0, x1;
+  if (nsf > 0) {
+    helicity_basis<R>(p, pabs, x0, x1, h);
+    const R lo = R(h > 0 ? small : big), hi = R(h > 0 ? big : small);
+    s.c[0] = x0 * lo; s.c[1] = x1 * lo; s.c[2] = x0 * hi; s.c[3] = x1 * hi;
+  } else {
+    helicity_basis<R>(p, pabs, x0, x1, -h);
+    const R lo = R(h > 0 ? big : small), hi = R(h > 0 ? small : big);
+    s.c[0] = x0 * lo; s.c[1] = x1 * lo; s.c[2] = -(x0 * hi); s.c[3] = -(x1 * hi);
+  }
+  return s;
+}
+
+// oxxxxx role: row spinor flowing out of the diagram, psi^dagger gamma^0.
+// nsf = +1: ubar(p, h) of an outgoing fermion; nsf = -1: vbar(p, h) of an
+// incoming antifermion.  gamma^0 swaps the chiral halves.
+template <class R>
+__host__ __device__ __forceinline__ Spinor<R> oxx(const double* p, double m, int h, int nsf) {
+  const Spinor<R> col = ixx<R>(p, m, h, nsf);
+  Spinor<R> s;
+  s.c[0] = conj(col.c[2]); s.c[1] = conj(col.c[3]);
+  s.c[2] = conj(col.c[0]); s.c[3] = conj(col.c[1]);
+  return s;
+}
+
+// vxxxxx role: massless vector polarisation eps(k, h) = (-h e1 - i e2)/sqrt 2,
+// e1 = (0, cos t cos f, cos t sin f, -sin t), e2 = (0, -sin f, cos f, 0);
+// nsv = -1 (outgoing) returns eps*.
+template <class R>
+__host__ __device__ __forceinline__ Vec<R> vxx(const double* k, int h, int nsv) {
+  const double pt = sqrt(k[1] * k[1] + k[2] * k[2]);
+  const double pabs = sqrt(pt * pt + k[3] * k[3]);
+  double cf = 1.0, sf = 0.0, ct = k[3] >= 0.0 ? 1.0 : -1.0, st = 0.0;
+  if (pt > 0.0) { cf = k[1] / pt; sf = k[2] / pt; ct = k[3] / pabs; st = pt / pabs; }
+  const double r = 0.70710678118654752440;
+  const double hr = -h * r;
+  const double im_sign = nsv > 0 ? -r : r;   // -i e2 for eps, +i e2 for eps*
+  Vec<R> e;
+  e.c[0] = {R(0), R(0)};
+  e.c[1] = {R(hr * ct * cf), R(im_sign * -sf)};
+  e.c[2] = {R(hr * ct * sf), R(im_sign * cf)};
+  e.c[3] = {R(hr * -st), R(0)};
+  return e;
+}
+
+// ------------------------------------------------------------- chiral blocks
+// (V.sigma) x and (V.sigmabar) x for a complex vector V and 2-spinor x.
+template <class R>
+__host__ __device__ __forceinline__ void vsigma(const Vec<R>& v, cx<R> x0, cx<R> x1, cx<R>& y0, cx<R>& y1) {
+  const cx<R> d = v.c[0] - v.c[3], u = v.c[0] + v.c[3];
+  const cx<R> m = v.c[1] - times_i(v.c[2]), p = v.c[1] + times_i(v.c[2]);
+  y0 = d * x0 - m * x1;
+  y1 = u * x1 - p * x0;
+}
+template <class R>
+__host__ __device__ __forceinline__ void vsigmabar(const Vec<R>& v, cx<R> x0, cx<R> x1, cx<R>& y0, cx<R>& y1) {
+  const cx<R> d = v.c[0] - v.c[3], u = v.c[0] + v.c[3];
+  const cx<R> m = v.c[1] - times_i(v.c[2]), p = v.c[1] + times_i(v.c[2]);
+  y0 = u * x0 + m * x1;
+  y1 = p * x0 + d * x1;
+}
+// row x times (V.sigma) and (V.sigmabar)
+template <class R>
+__host__ __device__ __forceinline__ void row_vsigma(const Vec<R>& v, cx<R> x0, cx<R> x1, cx<R>& y0, cx<R>& y1) {
+  const cx<R> d = v.c[0] - v.c[3], u = v.c[0] + v.c[3];
+  const cx<R> m = v.c[1] - times_i(v.c[2]), p = v.c[1] + times_i(v.c[2]);
+  y0 = x0 * d - x1 * p;
+  y1 = x1 * u - x0 * m;
+}
+template <class R>
+__host__ __device__ __forceinline__ void row_vsigmabar(const Vec<R>& v, cx<R> x0, cx<R> x1, cx<R>& y0, cx<R>& y1) {
+  const cx<R> d = v.c[0] - v.c[3], u = v.c[0] + v.c[3];
+  const cx<R> m = v.c[1] - times_i(v.c[2]), p = v.c[1] + times_i(v.c[2]);
+  y0 = x0 * u + x1 * p;
+  y1 = x0 * m + x1 * d;
+}
+// Same blocks for a real momentum q.
+template <class R>
+__host__ __device__ __forceinline__ void qsigma(const R* q, cx<R> x0, cx<R> x1, cx<R>& y0, cx<R>& y1) {
+  const R d = q[0] - q[3], u = q[0] + q[3];
+  const cx<R> m = {q[1], -q[2]}, p = {q[1], q[2]};
+  y0 = x0 * d - m * x1;
+  y1 = x1 * u - p * x0;
+}
+template <class R>
+__host__ __device__ __forceinline__ void qsigmabar(const R* q, cx<R> x0, cx<R> x1, cx<R>& y0, cx<R>& y1) {
+  const R d = q[0] - q[3], u = q[0] + q[3];
+  const cx<R> m = {q[1], -q[2]}, p = {q[1], q[2]};
+  y0 = x0 * u + m * x1;
+  y1 = p * x0 + x1 * d;
+}
+template <class R>
+__host__ __device__ __forceinline__ void row_qsigma(const R* q, cx<R> x0, cx<R> x1, cx<R>& y0, cx<R>& y1) {
+  const R d = q[0] - q[3], u = q[0] + q[3];
+  const cx<R> m = {q[1], -q[2]}, p = {q[1], q[2]};
+  y0 = x0 * d - x1 * p;
+  y1 = x1 * u - x0 * m;
+}
+template <class R>
+__host__ __device__ __forceinline__ void row_qsigmabar(const R* q, cx<R> x0, cx<R> x1, cx<R>& y0, cx<R>& y1) {
+  const R d = q[0] - q[3], u = q[0] + q[3];
+  const cx<R> m = {q[1], -q[2]}, p = {q[1], q[2]};
+  y0 = x0 * u + x1 * p;
+  y1 = x0 * m + x1 * d;
+}
+
+// ------------------------------------------------------------------ vertices
+// FFV1_0 role: amplitude fo . Gamma(V) . fi.
+template <class R>
+__host__ __device__ __forceinline__ cx<R> ffv_amp(const Spinor<R>& fo, const Spinor<R>& fi, const Vec<R>& v, cx<R> cl, cx<R> cr) {
+  cx<R> a0, a1, b0, b1;
+  vsigma(v, fi.c[2], fi.c[3], a0, a1);        // (V.sigma) psi_R
+  vsigmabar(v, fi.c[0], fi.c[1], b0, b1);     // (V.sigmabar) psi_L
+  return cr * (fo.c[0] * a0 + fo.c[1] * a1) + cl * (fo.c[2] * b0 + fo.c[3] * b1);
+}
+
+// Off-shell fermion flowing in: i (q-slash + m)/(q^2 - m^2) Gamma(V) fi.
+template <class R>
+__host__ __device__ __forceinline__ Spinor<R> ffv_in(const Spinor<R>& fi, const Vec<R>& v, cx<R> cl, cx<R> cr,
+                                                     const double* qd, double m) {
+  cx<R> u0, u1, d0, d1;
+  vsigma(v, fi.c[2], fi.c[3], u0, u1);
+  vsigmabar(v, fi.c[0], fi.c[1], d0, d1);
+  u0 = cr * u0; u1 = cr * u1; d0 = cl * d0; d1 = cl * d1;
+  const R q[4] = {R(qd[0]), R(qd[1]), R(qd[2]), R(qd[3])};
+  const R den = R(1.0 / (msq(qd) - m * m));
+  const R rm = R(m);
+  Spinor<R> s;
+  cx<R> t0, t1;
+  qsigma(q, d0, d1, t0, t1);                   // upper = m chi_u + (q.sigma) chi_d
+  s.c[0] = t0 + u0 * rm; s.c[1] = t1 + u1 * rm;
+  qsigmabar(q, u0, u1, t0, t1);                // lower = (q.sigmabar) chi_u + m chi_d
+  s.c[2] = t0 + d0 * rm; s.c[3] = t1 + d1 * rm;
+  for (int i = 0; i < 4; ++i) s.c[i] = times_i(s.c[i]) * den;
+  return s;
+}
+
+// Off-shell fermion flowing out (row): fo Gamma(V) i (q-slash + m)/(q^2 - m^2).
+template <class R>
+__host__ __device__ __forceinline__ Spinor<R> ffv_out(const Spinor<R>& fo, const Vec<R>& v, cx<R> cl, cx<R> cr,
+                                                      const double* qd, double m) {
+  cx<R> u0, u1, d0, d1;
+  row_vsigmabar(v, fo.c[2], fo.c[3], u0, u1);  // row (b V.sigmabar) cL
+  row_vsigma(v, fo.c[0], fo.c[1], d0, d1);     // row (a V.sigma) cR
+  u0 = cl * u0; u1 = cl * u1; d0 = cr * d0; d1 = cr * d1;
+  const R q[4] = {R(qd[0]), R(qd[1]), R(qd[2]), R(qd[3])};
+  const R den = R(1.0 / (msq(qd) - m * m));
+  const R rm = R(m);
+  Spinor<R> s;
+  cx<R> t0, t1;
+  row_qsigmabar(q, d0, d1, t0, t1);            // first half = m r_u + r_d (q.sigmabar)
+  s.c[0] = t0 + u0 * rm; s.c[1] = t1 + u1 * rm;
+  row_qsigma(q, u0, u1, t0, t1);               // second half = r_u (q.sigma) + m r_d
+  s.c[2] = t0 + d0 * rm; s.c[3] = t1 + d1 * rm;
+  for (int i = 0; i < 4; ++i) s.c[i] = times_i(s.c[i]) * den;
+  return s;
+}
+
+// Vector current of a fermion pair, j^mu = fo gamma^mu (cL P_L + cR P_R) fi.
+template <class R>
+__host__ __device__ __forceinline__ Vec<R> ff_current(const Spinor<R>& fo, const Spinor<R>& fi, cx<R> cl, cx<R> cr) {
+  // a sigma^mu psi_R and b sigmabar^mu psi_L, a = fo[0..1], b = fo[2..3]
+  const cx<R> a0 = fo.c[0], a1 = fo.c[1], b0 = fo.c[2], b1 = fo.c[3];
+  const cx<R> r0 = fi.c[2], r1 = fi.c[3], l0 = fi.c[0], l1 = fi.c[1];
+  const cx<R> s00 = a0 * r0, s01 = a0 * r1, s10 = a1 * r0, s11 = a1 * r1;
+  const cx<R> t00 = b0 * l0, t01 = b0 * l1, t10 = b1 * l0, t11 = b1 * l1;
+  Vec<R> j;
+  j.c[0] = cr * (s00 + s11) + cl * (t00 + t11);
+  j.c[1] = cr * (s01 + s10) - cl * (t01 + t10);
+  j.c[2] = cr * times_i(s10 - s01) - cl * times_i(t10 - t01);
+  j.c[3] = cr * (s00 - s11) - cl * (t00 - t11);
+  return j;
+}
+
+// Off-shell massless vector from a fermion pair: -i j^mu / q^2.
+template <class R>
+__host__ __device__ __forceinline__ Vec<R> ffv_vec0(const Spinor<R>& fo, const Spinor<R>& fi, cx<R> cl, cx<R> cr, const double* q) {
+  Vec<R> j = ff_current(fo, fi, cl, cr);
+  const R den = R(1.0 / msq(q));
+  for (int i = 0; i < 4; ++i) j.c[i] = times_minus_i(j.c[i]) * den;
+  return j;
+}
+
+// Off-shell massive vector from a fermion pair (unitary gauge, fixed width):
+// -i (j^mu - q^mu (q.j)/M^2) / (q^2 - M^2 + i M W); the denominator is formed
+// and inverted in double.
+template <class R>
+__host__ __device__ __forceinline__ Vec<R> ffv_vecm(const Spinor<R>& fo, const Spinor<R>& fi, cx<R> cl, cx<R> cr,
+                                                    const double* q, double mass, double width) {
+  Vec<R> j = ff_current(fo, fi, cl, cr);
+  const double dre = msq(q) - mass * mass, dim = mass * width;
+  const double inv = 1.0 / (dre * dre + dim * dim);
+  // -i / (dre + i dim) = (-dim - i dre) / |d|^2
+  const cx<R> f = {R(-dim * inv), R(-dre * inv)};
+  const cx<R> qj = mdot(q, j) * R(1.0 / (mass * mass));
+  for (int i = 0; i < 4; ++i) j.c[i] = f * (j.c[i] - qj * R(q[i]));
+  return j;
+}
+
+// VVV1P0_1 role: off-shell gluon from two gluon currents, (-i/K^2) g V3 with
+// V3 = (J1.J2)(k1 - k2) + ((k1 + 2 k2).J1) J2 - ((2 k1 + k2).J2) J1.
+template <class R>
+__host__ __device__ __forceinline__ Vec<R> vvv_vec(const Vec<R>& j1, const double* k1, const Vec<R>& j2, const double* k2, R g) {
+  double kk[4], a[4], b[4], d[4];
+  for (int i = 0; i < 4; ++i) {
+    kk[i] = k1[i] + k2[i];
+    a[i] = k1[i] + 2.0 * k2[i];
+    b[i] = 2.0 * k1[i] + k2[i];
+    d[i] = k1[i] - k2[i];
+  }
+  const cx<R> j12 = mdot(j1, j2), aj1 = mdot(a, j1), bj2 = mdot(b, j2);
+  const R s = R(g / msq(kk));
+  Vec<R> out;
+  for (int i = 0; i < 4; ++i) {
+    const cx<R> v = j12 * R(d[i]) + aj1 * j2.c[i] - bj2 * j1.c[i];
+    out.c[i] = times_minus_i(v) * s;
+  }
+  return out;
+}
+
+// Off-shell gluon from three gluon currents through one of the three colour
+// structures of the four-gluon vertex: (-i/K^2)(-i g^2) L_t,
+//   L_0 = J2 (J1.J3) - J3 (J1.J2),  L_1 = J1 (J2.J3) - J3 (J1.J2),
+//   L_2 = J1 (J2.J3) - J2 (J1.J3).
+template <int TERM, class R>
+__host__ __device__ __forceinline__ Vec<R> vvvv_vec(const Vec<R>& j1, const Vec<R>& j2, const Vec<R>& j3, const double* kk, R g2) {
+  const R s = R(g2 / msq(kk));              // (-i)(-i) = -1 folded below
+  Vec<R> out;
+  if (TERM == 0) {
+    const cx<R> x = mdot(j1, j3), y = mdot(j1, j2);
+    for (int i = 0; i < 4; ++i) out.c[i] = (j3.c[i] * y - j2.c[i] * x) * s;
+  } else if (TERM == 1) {
+    const cx<R> x = mdot(j2, j3), y = mdot(j1, j2);
+    for (int i = 0; i < 4; ++i) out.c[i] = (j3.c[i] * y - j1.c[i] * x) * s;
+  } else {
+    const cx<R> x = mdot(j2, j3), y = mdot(j1, j3);
+    for (int i = 0; i < 4; ++i) out.c[i] = (j2.c[i] * y - j1.c[i] * x) * s;
+  }
+  return out;
+}
+
+}  // namespace rwgt

@@ -1,0 +1,35 @@
+// Internal launch interface between the C-ABI host code and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "card.h"
+
+namespace rwgt {
+
+enum { kProcEeMumu = 0, kProcUuEeg = 1, kProcGgTtgg = 2 };
+enum { kPrecFP64 = 0, kPrecMixedFP16 = 1, kPrecMixedBF16 = 2 };
+constexpr int kMeBlock = 256;
+
+hipError_t launch_ingest(int npart, const double* aos, double* soa, int64_t nevt, hipStream_t s);
+
+// cards[0..ncards): |M|^2 per card -> me_out[k][nevt] (if non-null); when
+// w_out is non-null, card 0 is the original card and
+// w_out[k-1][i] = (w_in[i] * (1/|M|^2_0)) * |M|^2_k for k >= 1.
+hipError_t launch_me(int proc, int precision, const double* soa, int64_t nevt, const CardPair* cards, int ncards,
+                     const double* w_in, double* w_out, double* me_out, hipStream_t s);
+
+void process_constants(int proc, int* npart, int* ngood, int* ncol, int* ndiag);
+
+#define RWGT_DECLARE_PROCESS(NAME)                                                                        \
+  hipError_t launch_me_##NAME(int precision, const double* soa, int64_t nevt, const CardPair* cards,     \
+                              int ncards, const double* w_in, double* w_out, double* me_out, hipStream_t s); \
+  void constants_##NAME(int* npart, int* ngood, int* ncol, int* ndiag);
+RWGT_DECLARE_PROCESS(ee_mumu)
+RWGT_DECLARE_PROCESS(uu_eeg)
+RWGT_DECLARE_PROCESS(gg_ttgg)
+#undef RWGT_DECLARE_PROCESS
+
+}  // namespace rwgt

@@ -1,0 +1,359 @@
+// Host side of the C ABI declared in include/rwgt.h: process and SLHA
+// parsing, per-card couplings, device buffers and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <cctype>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/rwgt.h"
+#include "kernels.h"
+
+using rwgt::Card;
+using rwgt::CardPair;
+using rwgt::cx;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct ProcessDef {
+  const char* text;
+  int id;
+  int npart;
+  std::vector<std::string> layout;   // param_sets columns
+  std::vector<std::string> required; // entries the original card must have
+  std::vector<std::string> fixed;    // entries a new card may not change
+};
+
+const std::vector<ProcessDef>& processes() {
+  static const std::vector<ProcessDef> defs = {
+      {"e+ e- > mu+ mu-", rwgt::kProcEeMumu, 4,
+       {"SMINPUTS 1", "RWGTEW 1", "MASS 23", "DECAY 23"},
+       {"SMINPUTS 1", "RWGTEW 1", "MASS 23", "DECAY 23"}, {}},
+      {"u u~ > e+ e- g", rwgt::kProcUuEeg, 5,
+       {"SMINPUTS 1", "SMINPUTS 3", "RWGTEW 1", "MASS 23", "DECAY 23"},
+       {"SMINPUTS 1", "SMINPUTS 3", "RWGTEW 1", "MASS 23", "DECAY 23"}, {}},
+      {"g g > t t~ g g", rwgt::kProcGgTtgg, 6,
+       {"SMINPUTS 3", "MASS 6"}, {"SMINPUTS 3", "MASS 6"}, {"MASS 6"}},
+  };
+  return defs;
+}
+
+std::string normalise_ws(const char* s) {
+  std::istringstream in(s);
+  std::string tok, out;
+  while (in >> tok) out += (out.empty() ? "" : " ") + tok;
+  return out;
+}
+
+std::string upper(std::string s) {
+  for (auto& c : s) c = char(std::toupper(static_cast<unsigned char>(c)));
+  return s;
+}
+
+// Minimal SLHA reader: "BLOCK NAME" opens a block whose lines are "id value";
+// "DECAY pdg width" sets "DECAY pdg".  '#' starts a comment.
+bool parse_slha(const char* text, std::map<std::string, double>& out, std::string& err) {
+  std::istringstream in(text);
+  std::string line, block;
+  int lineno = 0;
+  while (std::getline(in, line)) {
+    ++lineno;
+    const auto hash = line.find('#');
+    if (hash != std::string::npos) line.resize(hash);
+    std::istringstream ls(line);
+    std::string first;
+    if (!(ls >> first)) continue;
+    const std::string kw = upper(first);
+    if (kw == "BLOCK") {
+      if (!(ls >> block)) { err = "line " + std::to_string(lineno) + ": BLOCK without a name"; return false; }
+      block = upper(block);
+      continue;
+    }
+    if (kw == "DECAY") {
+      std::string pdg;
+      double w;
+      if (!(ls >> pdg >> w)) { err = "line " + std::to_string(lineno) + ": malformed DECAY"; return false; }
+      out["DECAY " + pdg] = w;
+      block.clear();
+      continue;
+    }
+    if (block.empty()) { err = "line " + std::to_string(lineno) + ": entry outside a block"; return false; }
+    double v;
+    if (!(ls >> v)) { err = "line " + std::to_string(lineno) + ": malformed entry in block " + block; return false; }
+    out[block + " " + first] = v;
+  }
+  return true;
+}
+
+// Fermion (charge, weak isospin) in species order e, mu, u, t.
+constexpr double kQ[4] = {-1.0, -1.0, 2.0 / 3.0, 2.0 / 3.0};
+constexpr double kT3[4] = {-0.5, -0.5, 0.5, 0.5};
+
+double get(const std::map<std::string, double>& m, const char* key, double fallback) {
+  auto it = m.find(key);
+  return it == m.end() ? fallback : it->second;
+}
+
+// Couplings of one card (textbook electroweak and QCD vertex factors).
+template <class R>
+Card<R> couplings(const std::map<std::string, double>& m) {
+  const double pi = 3.14159265358979323846;
+  const double inv_alpha = get(m, "SMINPUTS 1", 0.0);
+  const double as = get(m, "SMINPUTS 3", 0.0);
+  const double sw2 = get(m, "RWGTEW 1", 0.0);
+  const double e = inv_alpha > 0.0 ? std::sqrt(4.0 * pi / inv_alpha) : 0.0;
+  const double gs = std::sqrt(4.0 * pi * as);
+  const double sw = std::sqrt(sw2), cw = std::sqrt(1.0 - sw2);
+  const double gz = (sw > 0.0 && cw > 0.0) ? e / (sw * cw) : 0.0;
+  Card<R> c;
+  c.gqq = cx<R>{R(0), R(gs)};
+  c.g3 = R(gs);
+  c.g4 = R(gs * gs);
+  for (int f = 0; f < 4; ++f) {
+    c.aL[f] = cx<R>{R(0), R(-e * kQ[f])};
+    c.aR[f] = c.aL[f];
+    c.zL[f] = cx<R>{R(0), R(-gz * (kT3[f] - kQ[f] * sw2))};
+    c.zR[f] = cx<R>{R(0), R(-gz * (-kQ[f] * sw2))};
+  }
+  c.mz = get(m, "MASS 23", 0.0);
+  c.wz = get(m, "DECAY 23", 0.0);
+  c.mt = get(m, "MASS 6", 0.0);
+  return c;
+}
+
+CardPair card_pair(const std::map<std::string, double>& m) {
+  CardPair p;
+  p.d = couplings<double>(m);
+  p.f = couplings<float>(m);
+  return p;
+}
+
+}  // namespace
+
+struct rwgt_ctx {
+  const ProcessDef* def = nullptr;
+  int precision = 0;
+  int device = 0;
+  std::map<std::string, double> card;
+  hipStream_t stream = nullptr;
+  double* soa = nullptr;
+  int64_t soa_events = 0;
+  CardPair* dcards = nullptr;
+  int dcards_cap = 0;
+  CardPair* hcards = nullptr;   // pinned staging for the card upload
+  int hcards_cap = 0;
+  hipEvent_t upload_done = nullptr;
+  bool upload_pending = false;
+  std::string err;
+
+  int fail(int code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+  int hip_fail(hipError_t e, const char* what) {
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? RWGT_ENOMEM : RWGT_EDEVICE;
+  }
+  ~rwgt_ctx() {
+    if (upload_done) { hipEventSynchronize(upload_done); hipEventDestroy(upload_done); }
+    if (stream) hipStreamSynchronize(stream); else hipDeviceSynchronize();
+    if (soa) hipFree(soa);
+    if (dcards) hipFree(dcards);
+    if (hcards) hipHostFree(hcards);
+  }
+};
+
+namespace {
+
+int ensure_buffers(rwgt_ctx* c, int64_t nevt, int ncards) {
+  if (nevt > c->soa_events) {
+    if (c->soa) {
+      hipStreamSynchronize(c->stream);
+      hipFree(c->soa);
+      c->soa = nullptr;
+      c->soa_events = 0;
+    }
+    const size_t bytes = size_t(nevt) * size_t(c->def->npart) * 4 * sizeof(double);
+    hipError_t e = hipMalloc(&c->soa, bytes);
+    if (e != hipSuccess) return c->hip_fail(e, "hipMalloc(momenta SoA)");
+    c->soa_events = nevt;
+  }
+  if (ncards > c->dcards_cap) {
+    if (c->dcards) { hipStreamSynchronize(c->stream); hipFree(c->dcards); c->dcards = nullptr; }
+    if (c->upload_pending) { hipEventSynchronize(c->upload_done); c->upload_pending = false; }
+    if (c->hcards) { hipHostFree(c->hcards); c->hcards = nullptr; }
+    c->dcards_cap = c->hcards_cap = 0;
+    const int cap = ncards < 16 ? 16 : ncards;
+    hipError_t e = hipMalloc(&c->dcards, size_t(cap) * sizeof(CardPair));
+    if (e != hipSuccess) return c->hip_fail(e, "hipMalloc(cards)");
+    e = hipHostMalloc(&c->hcards, size_t(cap) * sizeof(CardPair), hipHostMallocDefault);
+    if (e != hipSuccess) return c->hip_fail(e, "hipHostMalloc(cards)");
+    c->dcards_cap = c->hcards_cap = cap;
+  }
+  return RWGT_OK;
+}
+
+// Card list [original, param_sets rows...] (with_original) or just the rows.
+int build_cards(rwgt_ctx* c, const double* param_sets, int32_t nsets, bool with_original,
+                std::vector<CardPair>& out) {
+  const auto& layout = c->def->layout;
+  out.clear();
+  if (with_original) out.push_back(card_pair(c->card));
+  for (int32_t k = 0; k < nsets; ++k) {
+    std::map<std::string, double> m = c->card;
+    for (size_t j = 0; j < layout.size(); ++j) {
+      const double v = param_sets[size_t(k) * layout.size() + j];
+      for (const auto& f : c->def->fixed) {
+        if (f == layout[j] && v != c->card[f]) {
+          return c->fail(RWGT_EPARAM, "param set " + std::to_string(k) + " changes " + f +
+                                          ", an external mass fixed by the momenta");
+        }
+      }
+      m[layout[j]] = v;
+    }
+    out.push_back(card_pair(m));
+  }
+  return RWGT_OK;
+}
+
+int run(rwgt_ctx* c, bool reweight, const double* momenta, int64_t nevt, const double* w_in,
+        const double* param_sets, int32_t nsets, double* w_out, double* me_out) {
+  if (nevt < 0) return c->fail(RWGT_EINVAL, "nevt < 0");
+  if (nsets < 1) return c->fail(RWGT_EINVAL, "nsets < 1");
+  if (!param_sets) return c->fail(RWGT_EINVAL, "param_sets is NULL");
+  std::vector<CardPair> cards;
+  int rc = build_cards(c, param_sets, nsets, reweight, cards);
+  if (rc != RWGT_OK) return rc;
+  if (nevt == 0) return RWGT_OK;
+  if (!momenta) return c->fail(RWGT_EINVAL, "momenta is NULL");
+  if (reweight && !w_in) return c->fail(RWGT_EINVAL, "weights_in is NULL");
+  if (reweight && !w_out) return c->fail(RWGT_EINVAL, "weights_out is NULL");
+  if (!reweight && !me_out) return c->fail(RWGT_EINVAL, "me2_out is NULL");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return c->hip_fail(e, "hipSetDevice");
+  rc = ensure_buffers(c, nevt, int(cards.size()));
+  if (rc != RWGT_OK) return rc;
+  if (c->upload_pending) {
+    e = hipEventSynchronize(c->upload_done);
+    if (e != hipSuccess) return c->hip_fail(e, "hipEventSynchronize");
+    c->upload_pending = false;
+  }
+  std::memcpy(c->hcards, cards.data(), cards.size() * sizeof(CardPair));
+  e = hipMemcpyAsync(c->dcards, c->hcards, cards.size() * sizeof(CardPair), hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync(cards)");
+  e = hipEventRecord(c->upload_done, c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "hipEventRecord");
+  c->upload_pending = true;
+  e = rwgt::launch_ingest(c->def->npart, momenta, c->soa, nevt, c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "ingest kernel");
+  e = rwgt::launch_me(c->def->id, c->precision, c->soa, nevt, c->dcards, int(cards.size()), w_in, w_out, me_out,
+                      c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "matrix-element kernel");
+  return RWGT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rwgt_create(const char* process, const char* param_card, int precision, rwgt_ctx** out) {
+  g_create_error.clear();
+  if (!out) { g_create_error = "out is NULL"; return RWGT_EINVAL; }
+  *out = nullptr;
+  if (!process || !param_card) { g_create_error = "process or param_card is NULL"; return RWGT_EINVAL; }
+  if (precision < RWGT_FP64 || precision > RWGT_MIXED_BF16) { g_create_error = "unknown precision"; return RWGT_EINVAL; }
+  const std::string want = normalise_ws(process);
+  const ProcessDef* def = nullptr;
+  for (const auto& d : processes())
+    if (want == d.text) def = &d;
+  if (!def) { g_create_error = "unsupported process '" + want + "'"; return RWGT_EPROCESS; }
+  std::map<std::string, double> card;
+  std::string err;
+  if (!parse_slha(param_card, card, err)) { g_create_error = "param card: " + err; return RWGT_ECARD; }
+  for (const auto& r : def->required) {
+    if (!card.count(r)) { g_create_error = "param card lacks " + r; return RWGT_ECARD; }
+  }
+  rwgt_ctx* c = new (std::nothrow) rwgt_ctx;
+  if (!c) { g_create_error = "out of host memory"; return RWGT_ENOMEM; }
+  c->def = def;
+  c->precision = precision;
+  c->card = card;
+  hipError_t e = hipGetDevice(&c->device);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    g_create_error = std::string("HIP: ") + hipGetErrorString(e);
+    delete c;
+    return RWGT_EDEVICE;
+  }
+  *out = c;
+  return RWGT_OK;
+}
+
+void rwgt_destroy(rwgt_ctx* ctx) { delete ctx; }
+
+int rwgt_param_layout(const rwgt_ctx* ctx, int32_t* npar, const char** names) {
+  if (!ctx || !npar) return RWGT_EINVAL;
+  *npar = int32_t(ctx->def->layout.size());
+  if (names)
+    for (size_t j = 0; j < ctx->def->layout.size(); ++j) names[j] = ctx->def->layout[j].c_str();
+  return RWGT_OK;
+}
+
+int rwgt_original_params(const rwgt_ctx* ctx, double* values) {
+  if (!ctx || !values) return RWGT_EINVAL;
+  for (size_t j = 0; j < ctx->def->layout.size(); ++j) values[j] = ctx->card.at(ctx->def->layout[j]);
+  return RWGT_OK;
+}
+
+int rwgt_set_stream(rwgt_ctx* ctx, void* stream) {
+  if (!ctx) return RWGT_EINVAL;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  return RWGT_OK;
+}
+
+int rwgt_eval(rwgt_ctx* ctx, const double* momenta, int64_t nevt, const double* weights_in,
+              const double* param_sets, int32_t nsets, double* weights_out) {
+  if (!ctx) return RWGT_EINVAL;
+  ctx->err.clear();
+  try {
+    return run(ctx, true, momenta, nevt, weights_in, param_sets, nsets, weights_out, nullptr);
+  } catch (const std::exception& ex) {
+    return ctx->fail(RWGT_ENOMEM, ex.what());
+  }
+}
+
+int rwgt_me2(rwgt_ctx* ctx, const double* momenta, int64_t nevt, const double* param_sets, int32_t nsets,
+             double* me2_out) {
+  if (!ctx) return RWGT_EINVAL;
+  ctx->err.clear();
+  try {
+    return run(ctx, false, momenta, nevt, nullptr, param_sets, nsets, nullptr, me2_out);
+  } catch (const std::exception& ex) {
+    return ctx->fail(RWGT_ENOMEM, ex.what());
+  }
+}
+
+const char* rwgt_last_error(const rwgt_ctx* ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
+
+const char* rwgt_create_error(void) { return g_create_error.c_str(); }
+
+int rwgt_process_info(const rwgt_ctx* ctx, int32_t* npart, int32_t* nhel_kept, int32_t* ncol, int32_t* ndiag) {
+  if (!ctx) return RWGT_EINVAL;
+  int np = 0, ng = 0, nc = 0, nd = 0;
+  rwgt::process_constants(ctx->def->id, &np, &ng, &nc, &nd);
+  if (npart) *npart = np;
+  if (nhel_kept) *nhel_kept = ng;
+  if (ncol) *ncol = nc;
+  if (ndiag) *ndiag = nd;
+  return RWGT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,417 @@
+"""Emit straight-line HIP device code for one process.
+
+For each process the generated header defines, in namespace rwgt::gen_<name>:
+  NPART, NCOL, NHEL, NGOOD, GOOD[] (helicities kept), AVERAGE,
+  CNUM[NCOL][NCOL] (integer colour-matrix numerators), CDEN,
+  jamps<R>(P, hel, card, jamp)  -- colour-flow amplitudes J for one helicity,
+  colour_sum<R>(jamp)           -- J^dagger C J (real), with C = CNUM / CDEN.
+Helicity hel is a bit pattern, bit (NPART-1-i) set meaning helicity +1 for
+particle i.  Helicities that vanish identically by the chirality of a
+massless fermion line (a vector coupling keeps chirality along the line) are
+dropped at generation time.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+from typing import Dict, List
+
+from . import colour as col
+from .diagrams import FERMIONS, Diagrams, Leg
+
+SPECIES = {"e": 0, "mu": 1, "u": 2, "t": 3}
+
+
+def _mass(field):
+    sym = FERMIONS[field][3]
+    return "cd.mt" if sym else "0.0"
+
+
+def _nsf(leg: Leg) -> int:
+    """+1: u (incoming fermion) / ubar (outgoing fermion); -1: v / vbar."""
+    return -1 if leg.anti else 1
+
+
+def good_helicities(d: Diagrams) -> List[int]:
+    legs = d.process.legs
+    n = len(legs)
+    lines = [d.process.line(f) for f in {l.field for l in legs if l.is_fermion}]
+    good = []
+    for hel in range(1 << n):
+        h = [1 if (hel >> (n - 1 - i)) & 1 else -1 for i in range(n)]
+        ok = True
+        for b, f in lines:
+            if FERMIONS[b.field][3] is None:          # massless line
+                if (h[b.idx] * _nsf(b) > 0) != (h[f.idx] * _nsf(f) > 0):
+                    ok = False
+        if ok:
+            good.append(hel)
+    return good
+
+
+class Emitter:
+    def __init__(self, d: Diagrams):
+        self.d = d
+        self.lines: List[str] = []
+        self.cache: Dict[tuple, str] = {}
+        self.kcache: Dict[tuple, str] = {}
+        self.count = {"ixx": 0, "oxx": 0, "vxx": 0, "ffv_in": 0, "ffv_out": 0, "ffv_vec0": 0,
+                      "ffv_vecm": 0, "vvv_vec": 0, "vvvv_vec": 0, "ffv_amp": 0}
+        self.n = 0
+
+    def new(self, prefix):
+        self.n += 1
+        return f"{prefix}{self.n}"
+
+    def emit(self, s):
+        self.lines.append("  " + s)
+
+    # momenta ------------------------------------------------------------
+    def kleg(self, idx):
+        return f"K{idx}"
+
+    def ksum(self, terms):
+        """Name of sum_i sign_i K_legs (terms: tuple of (sign, leg))."""
+        key = tuple(sorted(terms))
+        if len(key) == 1 and key[0][0] == 1:
+            return self.kleg(key[0][1])
+        if key not in self.kcache:
+            name = self.new("q")
+            parts = []
+            for mu in range(4):
+                e = " ".join(("+ " if s > 0 else "- ") + f"K{l}[{mu}]" for s, l in key)
+                parts.append(e.lstrip("+ ").replace("- ", "-", 1) if e.startswith("- ") else e.lstrip("+ "))
+            self.emit(f"const double {name}[4] = {{{', '.join(parts)}}};")
+            self.kcache[key] = name
+        return self.kcache[key]
+
+    # external wavefunctions ---------------------------------------------
+    def ext(self, leg: Leg):
+        key = ("ext", leg.idx)
+        if key in self.cache:
+            return self.cache[key]
+        name = f"w{leg.idx}"
+        if leg.kind == "V":
+            self.emit(f"const Vec<R> {name} = vxx<R>(P[{leg.idx}], h{leg.idx}, {1 if leg.incoming else -1});")
+            self.count["vxx"] += 1
+        elif leg.kind == "F":
+            self.emit(f"const Spinor<R> {name} = ixx<R>(P[{leg.idx}], {_mass(leg.field)}, h{leg.idx}, {_nsf(leg)});")
+            self.count["ixx"] += 1
+        else:
+            self.emit(f"const Spinor<R> {name} = oxx<R>(P[{leg.idx}], {_mass(leg.field)}, h{leg.idx}, {_nsf(leg)});")
+            self.count["oxx"] += 1
+        self.cache[key] = name
+        return name
+
+    # attachments --------------------------------------------------------
+    def block_legs(self, blk):
+        if blk[0] == "glu":
+            from .diagrams import tree_legs
+            return tree_legs(blk[1])
+        sb, sf = self.d.process.line(blk[2])
+        return tuple(sorted((sb.idx, sf.idx)))
+
+    def block_k(self, blk):
+        return self.ksum(tuple((1, l) for l in self.block_legs(blk)))
+
+    def gluon(self, t):
+        """Vec name of a gluon tree current (propagator included)."""
+        if t[0] == "leaf":
+            return self.ext(self.d.process.legs[t[1]])
+        key = ("glu", t)
+        if key in self.cache:
+            return self.cache[key]
+        name = self.new("g")
+        if t[0] == "v3":
+            j1, j2 = self.gluon(t[1]), self.gluon(t[2])
+            k1 = self.block_k(("glu", t[1]))
+            k2 = self.block_k(("glu", t[2]))
+            self.emit(f"const Vec<R> {name} = vvv_vec<R>({j1}, {k1}, {j2}, {k2}, cd.g3);")
+            self.count["vvv_vec"] += 1
+        else:
+            term = t[1]
+            j = [self.gluon(c) for c in t[2:]]
+            kk = self.block_k(("glu", t))
+            self.emit(f"const Vec<R> {name} = vvvv_vec<{term}, R>({j[0]}, {j[1]}, {j[2]}, {kk}, cd.g4);")
+            self.count["vvvv_vec"] += 1
+        self.cache[key] = name
+        return name
+
+    def pair(self, boson, field):
+        key = ("pair", boson, field)
+        if key in self.cache:
+            return self.cache[key]
+        sb, sf = self.d.process.line(field)
+        fo, fi = self.ext(sb), self.ext(sf)
+        q = self.ksum(((1, sb.idx), (1, sf.idx)))
+        s = SPECIES[field]
+        name = self.new("v")
+        if boson == "a":
+            self.emit(f"const Vec<R> {name} = ffv_vec0<R>({fo}, {fi}, cd.aL[{s}], cd.aR[{s}], {q});")
+            self.count["ffv_vec0"] += 1
+        else:
+            self.emit(f"const Vec<R> {name} = ffv_vecm<R>({fo}, {fi}, cd.zL[{s}], cd.zR[{s}], {q}, cd.mz, cd.wz);")
+            self.count["ffv_vecm"] += 1
+        self.cache[key] = name
+        return name
+
+    def attach(self, blk):
+        """(Vec name, cL, cR) of an attachment on the main line."""
+        s = SPECIES[self.d.main]
+        if blk[0] == "glu":
+            return self.gluon(blk[1]), "cd.gqq", "cd.gqq"
+        boson, field = blk[1], blk[2]
+        v = self.pair(boson, field)
+        if boson == "a":
+            return v, f"cd.aL[{s}]", f"cd.aR[{s}]"
+        return v, f"cd.zL[{s}]", f"cd.zR[{s}]"
+
+    # main-line currents ---------------------------------------------------
+    def fcur(self, seq):
+        """Column spinor: Fcur(A_j..A_k) = S(q) Gamma(A_j) Fcur(A_{j+1}..A_k)."""
+        if not seq:
+            return self.ext(self.d.fleg)
+        key = ("F", seq)
+        if key in self.cache:
+            return self.cache[key]
+        inner = self.fcur(seq[1:])
+        v, cl, cr = self.attach(seq[0])
+        legs = [self.d.fleg.idx] + [l for b in seq for l in self.block_legs(b)]
+        q = self.ksum(tuple((1, l) for l in legs))
+        name = self.new("f")
+        self.emit(f"const Spinor<R> {name} = ffv_in<R>({inner}, {v}, {cl}, {cr}, {q}, {_mass(self.d.main)});")
+        self.count["ffv_in"] += 1
+        self.cache[key] = name
+        return name
+
+    def bcur(self, seq):
+        """Row spinor: Bcur(A_1..A_j) = Bcur(A_1..A_{j-1}) Gamma(A_j) S(q)."""
+        if not seq:
+            return self.ext(self.d.bleg)
+        key = ("B", seq)
+        if key in self.cache:
+            return self.cache[key]
+        inner = self.bcur(seq[:-1])
+        v, cl, cr = self.attach(seq[-1])
+        legs = [self.d.bleg.idx] + [l for b in seq for l in self.block_legs(b)]
+        q = self.ksum(tuple((-1, l) for l in legs))
+        name = self.new("b")
+        self.emit(f"const Spinor<R> {name} = ffv_out<R>({inner}, {v}, {cl}, {cr}, {q}, {_mass(self.d.main)});")
+        self.count["ffv_out"] += 1
+        self.cache[key] = name
+        return name
+
+    def missing(self, seq, m):
+        """Number of main-line currents a split at m would newly build."""
+        n = 0
+        for j in range(1, m + 1):
+            n += ("B", seq[:j]) not in self.cache
+        for j in range(m + 1, len(seq)):
+            n += ("F", seq[j:]) not in self.cache
+        return n
+
+    def amplitude(self, seq, colour, best):
+        fo = self.bcur(seq[:best])
+        fi = self.fcur(seq[best + 1:])
+        v, cl, cr = self.attach(seq[best])
+        self.emit(f"amp = ffv_amp<R>({fo}, {fi}, {v}, {cl}, {cr});")
+        self.count["ffv_amp"] += 1
+        for key, c in colour.items():
+            idx = self.d.basis.index(key)
+            c = complex(c)
+            assert c.real == int(c.real) and c.imag == int(c.imag)
+            re, im = int(c.real), int(c.imag)
+            if im == 0:
+                expr = "amp" if re == 1 else ("-amp" if re == -1 else f"amp * R({re})")
+            elif re == 0:
+                expr = "times_i(amp)" if im == 1 else ("times_minus_i(amp)" if im == -1 else f"times_i(amp) * R({im})")
+            else:
+                expr = f"amp * cx<R>{{R({re}), R({im})}}"
+            self.emit(f"jamp[{idx}] = jamp[{idx}] + {expr};")
+
+
+def colour_matrix_ints(d: Diagrams):
+    if not FERMIONS[d.main][2]:
+        return [[1]], 1                       # colourless main line: no colour sum
+    cm = col.colour_matrix(d.basis)
+    den = 1
+    for row in cm:
+        for x in row:
+            den = den * x.denominator // math.gcd(den, x.denominator)
+    num = [[int(x * den) for x in row] for row in cm]
+    for i, row in enumerate(cm):
+        for j, x in enumerate(row):
+            assert Fraction(num[i][j], den) == x
+    return num, den
+
+
+def node_deps(em: "Emitter", key):
+    """Direct dependencies of a plan node."""
+    d = em.d
+    kind = key[0]
+    if kind == "ext":
+        return []
+    if kind == "glu":
+        t = key[1]
+        if t[0] == "leaf":
+            return [("ext", t[1])]
+        kids = t[1:] if t[0] == "v3" else t[2:]
+        return [("ext", c[1]) if c[0] == "leaf" else ("glu", c) for c in kids]
+    if kind == "pair":
+        sb, sf = d.process.line(key[2])
+        return [("ext", sb.idx), ("ext", sf.idx)]
+    seq = key[1]
+    if kind == "F":
+        inner = ("F", seq[1:]) if len(seq) > 1 else ("ext", d.fleg.idx)
+        return [inner, attach_key(seq[0])]
+    inner = ("B", seq[:-1]) if len(seq) > 1 else ("ext", d.bleg.idx)
+    return [inner, attach_key(seq[-1])]
+
+
+def attach_key(blk):
+    if blk[0] == "glu":
+        t = blk[1]
+        return ("ext", t[1]) if t[0] == "leaf" else ("glu", t)
+    return ("pair", blk[1], blk[2])
+
+
+def plan_splits(d: Diagrams):
+    """Split point per amplitude term, chosen greedily to reuse main-line
+    currents (fewest new B/F currents, then nearest the middle)."""
+    have = set()
+    splits = []
+    for seq, _ in d.terms:
+        k = len(seq)
+
+        def missing(m):
+            n = sum(("B", seq[:j]) not in have for j in range(1, m + 1))
+            return n + sum(("F", seq[j:]) not in have for j in range(m + 1, k))
+        m = min(range(k), key=lambda m: (missing(m), abs(m - (k - 1) / 2)))
+        for j in range(1, m + 1):
+            have.add(("B", seq[:j]))
+        for j in range(m + 1, k):
+            have.add(("F", seq[j:]))
+        splits.append(m)
+    return splits
+
+
+def term_roots(d: Diagrams, seq, m):
+    b = ("B", seq[:m]) if m > 0 else ("ext", d.bleg.idx)
+    f = ("F", seq[m + 1:]) if m + 1 < len(seq) else ("ext", d.fleg.idx)
+    return [b, f, attach_key(seq[m])]
+
+
+def schedule(em: "Emitter", splits):
+    """Order amplitude terms to keep few currents live: repeatedly take the
+    term that adds the least live data net of what it lets die."""
+    d = em.d
+    closure = {}
+
+    def clos(key):
+        if key not in closure:
+            s = {key}
+            for c in node_deps(em, key):
+                s |= clos(c)
+            closure[key] = frozenset(s)
+        return closure[key]
+
+    term_nodes = []
+    for (seq, _), m in zip(d.terms, splits):
+        s = set()
+        for r in term_roots(d, seq, m):
+            s |= clos(r)
+        term_nodes.append(frozenset(s))
+    uses = {}
+    for s in term_nodes:
+        for n in s:
+            uses[n] = uses.get(n, 0) + 1
+    size = lambda n: 8
+    computed = set()
+    remaining = set(range(len(d.terms)))
+    order = []
+    while remaining:
+        best, best_cost = None, None
+        for t in remaining:
+            s = term_nodes[t]
+            new = s - computed
+            freed = [n for n in s if uses[n] == 1]
+            cost = (sum(size(n) for n in new if uses[n] > 1) - sum(size(n) for n in freed if n in computed),
+                    len(new), t)
+            if best_cost is None or cost < best_cost:
+                best, best_cost = t, cost
+        order.append(best)
+        remaining.discard(best)
+        computed |= term_nodes[best]
+        for n in term_nodes[best]:
+            uses[n] -= 1
+    return order
+
+
+def generate(d: Diagrams) -> str:
+    name = d.process.name
+    legs = d.process.legs
+    n = len(legs)
+    em = Emitter(d)
+    splits = plan_splits(d)
+    for t in schedule(em, splits):
+        seq, colour = d.terms[t]
+        em.amplitude(seq, colour, splits[t])
+    body = em.lines
+    num, den = colour_matrix_ints(d)
+    good = good_helicities(d)
+    ncol = len(d.basis)
+
+    out = []
+    out.append(f"// Generated by paper_2510_05100_amd.procgen for '{name}'. Do not edit.")
+    out.append(f"// {d.n_diagrams} Feynman diagrams, {len(d.terms)} amplitude terms, {ncol} colour flows.")
+    out.append("// Colour basis (gluon leg ids on the main line, row end first): "
+               + " ".join("(" + ",".join(map(str, b)) + ")" for b in d.basis))
+    out.append("#pragma once")
+    out.append('#include "helas.h"')
+    out.append('#include "card.h"')
+    out.append("namespace rwgt {")
+    out.append(f"namespace gen_{name} {{")
+    out.append(f"constexpr int NPART = {n};")
+    out.append(f"constexpr int NCOL = {ncol};")
+    out.append(f"constexpr int NHEL = {1 << n};")
+    out.append(f"constexpr int NGOOD = {len(good)};")
+    out.append(f"constexpr int NDIAG = {d.n_diagrams};")
+    out.append(f"constexpr int NAMP = {len(d.terms)};")
+    out.append(f"constexpr double AVERAGE = {d.process.average!r};")
+    out.append(f"constexpr int CDEN = {den};")
+    out.append(f"__constant__ int GOOD[NGOOD] = {{{', '.join(map(str, good))}}};")
+    out.append("constexpr int CNUM[NCOL][NCOL] = {")
+    for row in num:
+        out.append("  {" + ", ".join(map(str, row)) + "},")
+    out.append("};")
+    out.append("// Routine counts per helicity: " + ", ".join(f"{k} {v}" for k, v in em.count.items()))
+    for k, v in em.count.items():
+        out.append(f"constexpr int N_{k.upper()} = {v};")
+    out.append("")
+    out.append("template <class R>")
+    out.append(f"__device__ __forceinline__ void jamps(const double (&P)[{n}][4], int hel, const Card<R>& cd, cx<R> (&jamp)[NCOL]) {{")
+    for i, l in enumerate(legs):
+        sign = "" if l.incoming else "-"
+        out.append(f"  const double K{i}[4] = {{{', '.join(f'{sign}P[{i}][{mu}]' for mu in range(4))}}};")
+    for i in range(n):
+        out.append(f"  const int h{i} = ((hel >> {n - 1 - i}) & 1) ? 1 : -1;")
+    out.append("  for (int c = 0; c < NCOL; ++c) jamp[c] = cx<R>{R(0), R(0)};")
+    out.append("  cx<R> amp;")
+    out.extend(body)
+    out.append("}")
+    out.append("")
+    # colour sum: J^dagger C J = sum_i J_i^* (C J)_i, C real symmetric
+    out.append("template <class R>")
+    out.append("__device__ __forceinline__ R colour_sum(const cx<R> (&jamp)[NCOL]) {")
+    out.append("  R me = R(0);")
+    for i in range(ncol):
+        tr = [f"R({num[i][i]}) * jamp[{i}].re"] + [f"R({2 * num[i][j]}) * jamp[{j}].re" for j in range(i + 1, ncol) if num[i][j]]
+        ti = [f"R({num[i][i]}) * jamp[{i}].im"] + [f"R({2 * num[i][j]}) * jamp[{j}].im" for j in range(i + 1, ncol) if num[i][j]]
+        out.append(f"  {{ const R zr = {' + '.join(tr)};")
+        out.append(f"    const R zi = {' + '.join(ti)};")
+        out.append(f"    me += jamp[{i}].re * zr + jamp[{i}].im * zi; }}")
+    out.append(f"  return me * R(1.0 / {den}.0);")
+    out.append("}")
+    out.append(f"}}  // namespace gen_{name}")
+    out.append("}  // namespace rwgt")
+    return "\n".join(out) + "\n"

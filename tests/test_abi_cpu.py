@@ -1,0 +1,96 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/rwgt.h, and rejects bad arguments before touching a
+device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2510_05100_amd", "librwgt.so")
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "rwgt.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rwgt_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.skip("librwgt.so not built (python -m paper_2510_05100_amd.build)")
+    from paper_2510_05100_amd import _abi
+    return _abi.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("rwgt_create", "rwgt_eval", "rwgt_destroy", "rwgt_me2", "rwgt_param_layout", "rwgt_set_stream"):
+        assert must in names
+
+
+def test_every_declared_symbol_exported(lib):
+    from paper_2510_05100_amd import _abi
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in _abi.SIGNATURES, name
+
+
+def test_create_rejects_bad_arguments(lib):
+    from paper_2510_05100_amd import _abi
+    out = ctypes.c_void_p()
+    card = synth.ORIG_QCD.slha().encode()
+    assert lib.rwgt_create(None, card, 0, ctypes.byref(out)) == -1
+    assert lib.rwgt_create(b"g g > t t~ g g", card, 7, ctypes.byref(out)) == -1
+    assert lib.rwgt_create(b"g g > t t~", card, 0, ctypes.byref(out)) == -2
+    assert b"unsupported process" in lib.rwgt_create_error()
+    assert lib.rwgt_create(b"g g > t t~ g g", b"BLOCK MASS\n 6 173\n", 0, ctypes.byref(out)) == -3
+    assert b"SMINPUTS 3" in lib.rwgt_create_error()
+    assert lib.rwgt_create(b"g g > t t~ g g", b"6 173\n", 0, ctypes.byref(out)) == -3
+    assert lib.rwgt_create(b"e+ e- > mu+ mu-", b"BLOCK SMINPUTS\n 1 x\n", 0, ctypes.byref(out)) == -3
+    assert out.value is None
+    with pytest.raises(_abi.RwgtError, match="EPROCESS"):
+        _abi.rwgt_create("u u~ > mu+ mu-", card.decode())
+    lib.rwgt_destroy(None)                      # NULL is a no-op
+    assert lib.rwgt_last_error(None) == b"context is NULL"
+
+
+def test_null_context_calls(lib):
+    assert lib.rwgt_eval(None, None, 0, None, None, 1, None) == -1
+    assert lib.rwgt_me2(None, None, 0, None, 1, None) == -1
+    assert lib.rwgt_set_stream(None, None) == -1
+    n = ctypes.c_int32()
+    assert lib.rwgt_param_layout(None, ctypes.byref(n), None) == -1
+
+
+def test_generated_process_constants():
+    # the process compiler reproduces the diagram, flow and helicity counts
+    from paper_2510_05100_amd.procgen import diagrams, emit
+    for name, text, ndiag, namp, ncol, ngood in [
+        ("ee_mumu", "e+ e- > mu+ mu-", 2, 2, 1, 4),
+        ("uu_eeg", "u u~ > e+ e- g", 4, 4, 1, 8),
+        ("gg_ttgg", "g g > t t~ g g", 123, 159, 24, 64),
+    ]:
+        d = diagrams.build(diagrams.parse(name, text))
+        assert (d.n_diagrams, len(d.terms), len(d.basis)) == (ndiag, namp, ncol)
+        assert len(emit.good_helicities(d)) == ngood
+
+
+def test_procgen_colour_matrix_matches_bruteforce():
+    # symbolic Fierz reduction (device side) against the oracle's brute force
+    import numpy as np
+    from oracle import colour as oc
+    from paper_2510_05100_amd.procgen import diagrams, emit
+    d = diagrams.build(diagrams.parse("gg_ttgg", "g g > t t~ g g"))
+    num, den = emit.colour_matrix_ints(d)
+    assert den == 54
+    sym = np.array(num, dtype=float) / den
+    brute = oc.colour_matrix(4).real          # same basis order: permutations of the 4 gluon slots
+    np.testing.assert_allclose(sym, brute, atol=1e-12)
+    for name, text, want in [("ee_mumu", "e+ e- > mu+ mu-", [[1]]), ("uu_eeg", "u u~ > e+ e- g", [[4]])]:
+        num, den = emit.colour_matrix_ints(diagrams.build(diagrams.parse(name, text)))
+        assert np.allclose(np.array(num) / den, want)
