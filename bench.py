@@ -1,0 +1,155 @@
+"""Benchmark of the reweighting hot path on one MI355X.
+
+One step = one rwgt_eval over the whole g g -> t t~ g g workload: 1e6 RAMBO
+events (sqrt(s) uniform in [500, 2000] GeV, massive tops, gluon cuts), the
+original card (alpha_s = 0.118) as normaliser and one new card
+(alpha_s = 0.130): ingest of the momenta, |M|^2 under both cards for every
+event, and w' = (w / |M|^2) * |M'|^2.  Inputs are resident in HBM before the
+timed region.  The FP64 path gives ``value``; the mixed path (float
+amplitudes) is timed the same way and reported under ``mixed``.  Both carry
+the maximum relative error of w' against the exact ratio (0.130/0.118)^4 over
+all events, which the oracle reproduces to 1e-13.
+
+    python bench.py [--steps K] [--warmup W] [--events N] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "reweighted events/sec (gg→tt̄gg, FP64 vs mixed) at stated max rel. error"
+RATIO = (0.130 / 0.118) ** 4
+PEAK_FP64_VALU = 78.6e12        # MI355X FP64 vector, FLOP/s
+PEAK_FP32_VALU_UNPACKED = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz without packed FP32
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--events", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=200)
+    ap.add_argument("--modes", default="fp64,mixed")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_mode(rw, torch, precision, p_dev, w_dev, rows, nevt, steps, warmup):
+    import synth
+    r = rw.Reweighter("g g > t t~ g g", synth.ORIG_QCD.slha(), precision)
+    out = torch.empty((rows.shape[0], nevt), dtype=torch.float64, device="cuda")
+    rw.rwgt_set_profiling(r.ctx, True)
+    for _ in range(warmup):
+        r.eval(p_dev, w_dev, rows, out)
+    torch.cuda.synchronize()
+    me_ms, ing_ms = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r.eval(p_dev, w_dev, rows, out)
+        a, b = rw.rwgt_kernel_times(r.ctx)
+        ing_ms.append(a)
+        me_ms.append(b)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    w = out.cpu().numpy()
+    flops = rw.rwgt_flops(r.ctx)
+    r.close()
+    err = float(np.max(np.abs(w / RATIO - 1.0)))
+    return dict(ms_per_step=dt * 1e3, me_ms=float(np.mean(me_ms)), ingest_ms=float(np.mean(ing_ms)),
+                max_rel_err=err, flops_per_me2=flops, w=w)
+
+
+def cpu_baseline(p, sample, gpu_w):
+    """The oracle as it stands on a bounded sample of the same events."""
+    import synth
+    from oracle import reweight
+    try:
+        from threadpoolctl import threadpool_limits
+        limits = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        limits = None
+    idx = np.linspace(0, p.shape[0] - 1, sample).astype(np.int64)
+    t0 = time.perf_counter()
+    w, _, _ = reweight.reweight("gg_ttgg", p[idx], np.ones(sample), synth.ORIG_QCD, [synth.NEW_QCD])
+    dt = time.perf_counter() - t0
+    if limits is not None:
+        limits.unregister() if hasattr(limits, "unregister") else None
+    parity = float(np.max(np.abs(gpu_w[0, idx] / w[0] - 1.0)))
+    return {"value": sample / dt, "unit": "reweighted events/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample} of the {p.shape[0]} g g -> t t~ g g events (evenly spaced), original + 1 new "
+                      f"card, FP64 numpy Berends-Giele oracle, single thread, {dt:.1f} s",
+            "gpu_vs_oracle_max_rel_err": parity}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the events are independent "
+              "and a multi-GPU run would shard them without any exchange in the hot path.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2510_05100_amd as rw
+    import synth
+    rw.load()
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    t = time.perf_counter()
+    p = synth.events("gg_ttgg", a.events)
+    log(f"generated {a.events} events in {time.perf_counter() - t:.1f}s")
+    p_dev = torch.as_tensor(p).cuda()
+    w_dev = torch.ones(a.events, dtype=torch.float64, device="cuda")
+    rows = synth.NEW_QCD.row("gg_ttgg")[None, :]
+    res = {}
+    for mode in a.modes.split(","):
+        prec = rw.RWGT_FP64 if mode == "fp64" else rw.RWGT_MIXED_FP16
+        res[mode] = time_mode(rw, torch, prec, p_dev, w_dev, rows, a.events, a.steps, a.warmup)
+        log(f"{mode}: {res[mode]['ms_per_step']:.2f} ms/step, ME kernel {res[mode]['me_ms']:.2f} ms, "
+            f"max rel err {res[mode]['max_rel_err']:.3g}")
+    nsets = rows.shape[0]
+
+    def roofline(r, peak):
+        flops = r["flops_per_me2"] * a.events * (1 + nsets)
+        ach = flops / (r["me_ms"] * 1e-3)
+        return {"bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": ach / peak, "traffic": None,
+                "kernel": "me_kernel<Proc_gg_ttgg>", "flops_per_launch": flops}
+
+    main_mode = "fp64" if "fp64" in res else next(iter(res))
+    m = res[main_mode]
+    value = a.events * nsets / (m["ms_per_step"] * 1e-3)
+    line = {
+        "metric": METRIC, "value": value, "unit": "reweighted events/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if main_mode == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": f"g g -> t t~ g g, {a.events} RAMBO events (sqrt(s) in [500, 2000] GeV, "
+                               "pT(g) > 30 GeV, dR(g,g) > 0.4), alpha_s 0.118 -> 0.130, 1 new card",
+                   "events": a.events, "new_cards": nsets, "precision": main_mode},
+        "max_rel_err": m["max_rel_err"],
+        "roofline": roofline(m, PEAK_FP64_VALU),
+    }
+    if "mixed" in res and main_mode != "mixed":
+        x = res["mixed"]
+        line["mixed"] = {"value": a.events * nsets / (x["ms_per_step"] * 1e-3), "ms_per_step": x["ms_per_step"],
+                         "max_rel_err": x["max_rel_err"], "dtype": "f32 amplitudes, f64 momenta/denominators/ratio",
+                         "roofline": roofline(x, PEAK_FP32_VALU_UNPACKED)}
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(p, a.cpu_sample, m["w"])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

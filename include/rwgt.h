@@ -100,6 +100,21 @@ const char *rwgt_create_error(void);
 /* Process constants: particles, helicity combinations kept, colour flows, diagrams. */
 int rwgt_process_info(const rwgt_ctx *ctx, int32_t *npart, int32_t *nhel_kept, int32_t *ncol, int32_t *ndiag);
 
+/* Floating-point operations of one |M|^2 evaluation (all helicities kept,
+ * colour sums, averaging) as written in the kernels, counted by running the
+ * same generated code on the host with an operation-counting scalar.  One
+ * rwgt_eval over nevt events and nsets cards performs (1 + nsets) * nevt of
+ * them.  Used to express measured throughput as FLOP/s against the peak. */
+int rwgt_flops(const rwgt_ctx *ctx, double *flops_per_me2);
+
+/* Record HIP events around the ingest and matrix-element kernels of each
+ * subsequent rwgt_eval / rwgt_me2 (on the context's stream). */
+int rwgt_set_profiling(rwgt_ctx *ctx, int enable);
+
+/* Durations in milliseconds of the two kernels of the last call made with
+ * profiling on; waits for that call to finish. */
+int rwgt_kernel_times(rwgt_ctx *ctx, float *ingest_ms, float *me_ms);
+
 #ifdef __cplusplus
 }
 #endif

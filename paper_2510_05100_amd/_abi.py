@@ -33,6 +33,10 @@ SIGNATURES = {
     "rwgt_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "rwgt_create_error": (ctypes.c_char_p, []),
     "rwgt_process_info": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int32)] * 4),
+    "rwgt_flops": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "rwgt_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "rwgt_kernel_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
+                                          ctypes.POINTER(ctypes.c_float)]),
 }
 
 _lib = None
@@ -161,3 +165,26 @@ def rwgt_process_info(ctx):
     if rc != 0:
         _raise(rc, ctx)
     return dict(zip(("npart", "nhel_kept", "ncol", "ndiag"), (v.value for v in vals)))
+
+
+def rwgt_flops(ctx):
+    out = ctypes.c_double()
+    rc = load().rwgt_flops(ctx, ctypes.byref(out))
+    if rc != 0:
+        _raise(rc, ctx)
+    return out.value
+
+
+def rwgt_set_profiling(ctx, enable=True):
+    rc = load().rwgt_set_profiling(ctx, int(bool(enable)))
+    if rc != 0:
+        _raise(rc, ctx)
+
+
+def rwgt_kernel_times(ctx):
+    """(ingest_ms, me_ms) of the last call made with profiling on."""
+    a, b = ctypes.c_float(), ctypes.c_float()
+    rc = load().rwgt_kernel_times(ctx, ctypes.byref(a), ctypes.byref(b))
+    if rc != 0:
+        _raise(rc, ctx)
+    return a.value, b.value

@@ -10,14 +10,14 @@
 
 namespace rwgt {
 
-template <class R>
+template <class R, class D = double>
 struct Card {
   cx<R> gqq;             // i g_s   (quark-gluon, both chiralities)
   R g3;                  // g_s     (three-gluon)
   R g4;                  // g_s^2   (four-gluon, the -i is in vvvv_vec)
   cx<R> aL[4], aR[4];    // photon: -i e Q
   cx<R> zL[4], zR[4];    // Z: -i e/(s_W c_W) g_{L,R}
-  double mz, wz, mt;     // always double: resonant and mass terms
+  D mz, wz, mt;          // double on the device: resonant and mass terms
 };
 
 // Both precisions of one card, filled on the host.

@@ -23,7 +23,14 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace rwgt {
+
+// Mass argument of a massless line: the mass terms are dropped at compile
+// time (without fast-math the compiler may not fold x + y * 0).
+struct Massless {};
+template <class M> constexpr bool is_massless = std::is_same<M, Massless>::value;
 
 template <class R> struct cx { R re, im; };
 
@@ -45,23 +52,23 @@ template <class R> struct Vec { cx<R> c[4]; };      // vector field, upper index
 template <class R> __host__ __device__ __forceinline__ cx<R> mdot(const Vec<R>& a, const Vec<R>& b) {
   return a.c[0] * b.c[0] - a.c[1] * b.c[1] - a.c[2] * b.c[2] - a.c[3] * b.c[3];
 }
-template <class R> __host__ __device__ __forceinline__ cx<R> mdot(const double* k, const Vec<R>& a) {
+template <class R, class D> __host__ __device__ __forceinline__ cx<R> mdot(const D* k, const Vec<R>& a) {
   return a.c[0] * R(k[0]) - a.c[1] * R(k[1]) - a.c[2] * R(k[2]) - a.c[3] * R(k[3]);
 }
-__host__ __device__ __forceinline__ double msq(const double* k) {
+template <class D> __host__ __device__ __forceinline__ D msq(const D* k) {
   return k[0] * k[0] - k[1] * k[1] - k[2] * k[2] - k[3] * k[3];
 }
 
 // ------------------------------------------------------------ external states
 // Helicity 2-spinors along p: chi_+ = (cos t/2, e^{if} sin t/2),
 // chi_- = (-e^{-if} sin t/2, cos t/2), written with |p| + pz instead of angles.
-template <class R>
-__host__ __device__ __forceinline__ void helicity_basis(const double* p, double pabs, cx<R>& a0, cx<R>& a1, int lam) {
-  const double pt2 = p[1] * p[1] + p[2] * p[2];
+template <class R, class D>
+__host__ __device__ __forceinline__ void helicity_basis(const D* p, D pabs, cx<R>& a0, cx<R>& a1, int lam) {
+  const D pt2 = p[1] * p[1] + p[2] * p[2];
   // |p| + pz without cancellation when pz < 0
-  const double ppz = p[3] >= 0.0 ? pabs + p[3] : (pt2 > 0.0 ? pt2 / (pabs - p[3]) : 0.0);
+  const D ppz = p[3] >= 0.0 ? pabs + p[3] : (pt2 > 0.0 ? pt2 / (pabs - p[3]) : D(0.0));
   if (ppz > 0.0) {
-    const double nrm = 1.0 / sqrt(2.0 * pabs * ppz);
+    const D nrm = 1.0 / sqrt(2.0 * pabs * ppz);
     if (lam > 0) {
       a0 = {R(ppz * nrm), R(0)};
       a1 = {R(p[1] * nrm), R(p[2] * nrm)};
@@ -79,11 +86,12 @@ __host__ __device__ __forceinline__ void helicity_basis(const double* p, double 
 // incoming fermion; nsf = -1: v(p, h) of an outgoing antifermion.
 //   u = (sqrt(E - h|p|) chi_h, sqrt(E + h|p|) chi_h)
 //   v = (sqrt(E + h|p|) chi_-h, -sqrt(E - h|p|) chi_-h)
-template <class R>
-__host__ __device__ __forceinline__ Spinor<R> ixx(const double* p, double m, int h, int nsf) {
-  const double pabs = sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
-  const double big = sqrt(p[0] + pabs);
-  const double small = m / big;           // sqrt(E - |p|), exactly 0 for m = 0
+template <class R, class D, class M>
+__host__ __device__ __forceinline__ Spinor<R> ixx(const D* p, M m, int h, int nsf) {
+  const D pabs = sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
+  const D big = sqrt(p[0] + pabs);
+  D small;                                // sqrt(E - |p|) = m / sqrt(E + |p|)
+  if constexpr (is_massless<M>) small = D(0.0); else small = m / big;
   Spinor<R> s;
   cx<R> x0, x1;
   if (nsf > 0) {
@@ -101,8 +109,8 @@ __host__ __device__ __forceinline__ Spinor<R> ixx(const double* p, double m, int
 // oxxxxx role: row spinor flowing out of the diagram, psi^dagger gamma^0.
 // nsf = +1: ubar(p, h) of an outgoing fermion; nsf = -1: vbar(p, h) of an
 // incoming antifermion.  gamma^0 swaps the chiral halves.
-template <class R>
-__host__ __device__ __forceinline__ Spinor<R> oxx(const double* p, double m, int h, int nsf) {
+template <class R, class D, class M>
+__host__ __device__ __forceinline__ Spinor<R> oxx(const D* p, M m, int h, int nsf) {
   const Spinor<R> col = ixx<R>(p, m, h, nsf);
   Spinor<R> s;
   s.c[0] = conj(col.c[2]); s.c[1] = conj(col.c[3]);
@@ -113,15 +121,15 @@ __host__ __device__ __forceinline__ Spinor<R> oxx(const double* p, double m, int
 // vxxxxx role: massless vector polarisation eps(k, h) = (-h e1 - i e2)/sqrt 2,
 // e1 = (0, cos t cos f, cos t sin f, -sin t), e2 = (0, -sin f, cos f, 0);
 // nsv = -1 (outgoing) returns eps*.
-template <class R>
-__host__ __device__ __forceinline__ Vec<R> vxx(const double* k, int h, int nsv) {
-  const double pt = sqrt(k[1] * k[1] + k[2] * k[2]);
-  const double pabs = sqrt(pt * pt + k[3] * k[3]);
-  double cf = 1.0, sf = 0.0, ct = k[3] >= 0.0 ? 1.0 : -1.0, st = 0.0;
+template <class R, class D>
+__host__ __device__ __forceinline__ Vec<R> vxx(const D* k, int h, int nsv) {
+  const D pt = sqrt(k[1] * k[1] + k[2] * k[2]);
+  const D pabs = sqrt(pt * pt + k[3] * k[3]);
+  D cf = 1.0, sf = 0.0, ct = k[3] >= 0.0 ? 1.0 : -1.0, st = 0.0;
   if (pt > 0.0) { cf = k[1] / pt; sf = k[2] / pt; ct = k[3] / pabs; st = pt / pabs; }
   const double r = 0.70710678118654752440;
-  const double hr = -h * r;
-  const double im_sign = nsv > 0 ? -r : r;   // -i e2 for eps, +i e2 for eps*
+  const double hr = -h * r;                 // constants: folded at compile time
+  const double im_sign = nsv > 0 ? -r : r;  // -i e2 for eps, +i e2 for eps*
   Vec<R> e;
   e.c[0] = {R(0), R(0)};
   e.c[1] = {R(hr * ct * cf), R(im_sign * -sf)};
@@ -202,43 +210,57 @@ __host__ __device__ __forceinline__ cx<R> ffv_amp(const Spinor<R>& fo, const Spi
 }
 
 // Off-shell fermion flowing in: i (q-slash + m)/(q^2 - m^2) Gamma(V) fi.
-template <class R>
+template <class R, class D, class M>
 __host__ __device__ __forceinline__ Spinor<R> ffv_in(const Spinor<R>& fi, const Vec<R>& v, cx<R> cl, cx<R> cr,
-                                                     const double* qd, double m) {
+                                                     const D* qd, M m) {
   cx<R> u0, u1, d0, d1;
   vsigma(v, fi.c[2], fi.c[3], u0, u1);
   vsigmabar(v, fi.c[0], fi.c[1], d0, d1);
   u0 = cr * u0; u1 = cr * u1; d0 = cl * d0; d1 = cl * d1;
   const R q[4] = {R(qd[0]), R(qd[1]), R(qd[2]), R(qd[3])};
-  const R den = R(1.0 / (msq(qd) - m * m));
-  const R rm = R(m);
   Spinor<R> s;
   cx<R> t0, t1;
   qsigma(q, d0, d1, t0, t1);                   // upper = m chi_u + (q.sigma) chi_d
-  s.c[0] = t0 + u0 * rm; s.c[1] = t1 + u1 * rm;
+  s.c[0] = t0; s.c[1] = t1;
   qsigmabar(q, u0, u1, t0, t1);                // lower = (q.sigmabar) chi_u + m chi_d
-  s.c[2] = t0 + d0 * rm; s.c[3] = t1 + d1 * rm;
+  s.c[2] = t0; s.c[3] = t1;
+  R den;
+  if constexpr (is_massless<M>) {
+    den = R(1.0 / msq(qd));
+  } else {
+    den = R(1.0 / (msq(qd) - m * m));
+    const R rm = R(m);
+    s.c[0] = s.c[0] + u0 * rm; s.c[1] = s.c[1] + u1 * rm;
+    s.c[2] = s.c[2] + d0 * rm; s.c[3] = s.c[3] + d1 * rm;
+  }
   for (int i = 0; i < 4; ++i) s.c[i] = times_i(s.c[i]) * den;
   return s;
 }
 
 // Off-shell fermion flowing out (row): fo Gamma(V) i (q-slash + m)/(q^2 - m^2).
-template <class R>
+template <class R, class D, class M>
 __host__ __device__ __forceinline__ Spinor<R> ffv_out(const Spinor<R>& fo, const Vec<R>& v, cx<R> cl, cx<R> cr,
-                                                      const double* qd, double m) {
+                                                      const D* qd, M m) {
   cx<R> u0, u1, d0, d1;
   row_vsigmabar(v, fo.c[2], fo.c[3], u0, u1);  // row (b V.sigmabar) cL
   row_vsigma(v, fo.c[0], fo.c[1], d0, d1);     // row (a V.sigma) cR
   u0 = cl * u0; u1 = cl * u1; d0 = cr * d0; d1 = cr * d1;
   const R q[4] = {R(qd[0]), R(qd[1]), R(qd[2]), R(qd[3])};
-  const R den = R(1.0 / (msq(qd) - m * m));
-  const R rm = R(m);
   Spinor<R> s;
   cx<R> t0, t1;
   row_qsigmabar(q, d0, d1, t0, t1);            // first half = m r_u + r_d (q.sigmabar)
-  s.c[0] = t0 + u0 * rm; s.c[1] = t1 + u1 * rm;
+  s.c[0] = t0; s.c[1] = t1;
   row_qsigma(q, u0, u1, t0, t1);               // second half = r_u (q.sigma) + m r_d
-  s.c[2] = t0 + d0 * rm; s.c[3] = t1 + d1 * rm;
+  s.c[2] = t0; s.c[3] = t1;
+  R den;
+  if constexpr (is_massless<M>) {
+    den = R(1.0 / msq(qd));
+  } else {
+    den = R(1.0 / (msq(qd) - m * m));
+    const R rm = R(m);
+    s.c[0] = s.c[0] + u0 * rm; s.c[1] = s.c[1] + u1 * rm;
+    s.c[2] = s.c[2] + d0 * rm; s.c[3] = s.c[3] + d1 * rm;
+  }
   for (int i = 0; i < 4; ++i) s.c[i] = times_i(s.c[i]) * den;
   return s;
 }
@@ -260,8 +282,8 @@ __host__ __device__ __forceinline__ Vec<R> ff_current(const Spinor<R>& fo, const
 }
 
 // Off-shell massless vector from a fermion pair: -i j^mu / q^2.
-template <class R>
-__host__ __device__ __forceinline__ Vec<R> ffv_vec0(const Spinor<R>& fo, const Spinor<R>& fi, cx<R> cl, cx<R> cr, const double* q) {
+template <class R, class D>
+__host__ __device__ __forceinline__ Vec<R> ffv_vec0(const Spinor<R>& fo, const Spinor<R>& fi, cx<R> cl, cx<R> cr, const D* q) {
   Vec<R> j = ff_current(fo, fi, cl, cr);
   const R den = R(1.0 / msq(q));
   for (int i = 0; i < 4; ++i) j.c[i] = times_minus_i(j.c[i]) * den;
@@ -271,12 +293,12 @@ __host__ __device__ __forceinline__ Vec<R> ffv_vec0(const Spinor<R>& fo, const S
 // Off-shell massive vector from a fermion pair (unitary gauge, fixed width):
 // -i (j^mu - q^mu (q.j)/M^2) / (q^2 - M^2 + i M W); the denominator is formed
 // and inverted in double.
-template <class R>
+template <class R, class D, class M>
 __host__ __device__ __forceinline__ Vec<R> ffv_vecm(const Spinor<R>& fo, const Spinor<R>& fi, cx<R> cl, cx<R> cr,
-                                                    const double* q, double mass, double width) {
+                                                    const D* q, M mass, M width) {
   Vec<R> j = ff_current(fo, fi, cl, cr);
-  const double dre = msq(q) - mass * mass, dim = mass * width;
-  const double inv = 1.0 / (dre * dre + dim * dim);
+  const D dre = msq(q) - mass * mass, dim = mass * width;
+  const D inv = 1.0 / (dre * dre + dim * dim);
   // -i / (dre + i dim) = (-dim - i dre) / |d|^2
   const cx<R> f = {R(-dim * inv), R(-dre * inv)};
   const cx<R> qj = mdot(q, j) * R(1.0 / (mass * mass));
@@ -286,9 +308,9 @@ __host__ __device__ __forceinline__ Vec<R> ffv_vecm(const Spinor<R>& fo, const S
 
 // VVV1P0_1 role: off-shell gluon from two gluon currents, (-i/K^2) g V3 with
 // V3 = (J1.J2)(k1 - k2) + ((k1 + 2 k2).J1) J2 - ((2 k1 + k2).J2) J1.
-template <class R>
-__host__ __device__ __forceinline__ Vec<R> vvv_vec(const Vec<R>& j1, const double* k1, const Vec<R>& j2, const double* k2, R g) {
-  double kk[4], a[4], b[4], d[4];
+template <class R, class D>
+__host__ __device__ __forceinline__ Vec<R> vvv_vec(const Vec<R>& j1, const D* k1, const Vec<R>& j2, const D* k2, R g) {
+  D kk[4], a[4], b[4], d[4];
   for (int i = 0; i < 4; ++i) {
     kk[i] = k1[i] + k2[i];
     a[i] = k1[i] + 2.0 * k2[i];
@@ -309,8 +331,8 @@ __host__ __device__ __forceinline__ Vec<R> vvv_vec(const Vec<R>& j1, const doubl
 // structures of the four-gluon vertex: (-i/K^2)(-i g^2) L_t,
 //   L_0 = J2 (J1.J3) - J3 (J1.J2),  L_1 = J1 (J2.J3) - J3 (J1.J2),
 //   L_2 = J1 (J2.J3) - J2 (J1.J3).
-template <int TERM, class R>
-__host__ __device__ __forceinline__ Vec<R> vvvv_vec(const Vec<R>& j1, const Vec<R>& j2, const Vec<R>& j3, const double* kk, R g2) {
+template <int TERM, class R, class D>
+__host__ __device__ __forceinline__ Vec<R> vvvv_vec(const Vec<R>& j1, const Vec<R>& j2, const Vec<R>& j3, const D* kk, R g2) {
   const R s = R(g2 / msq(kk));              // (-i)(-i) = -1 folded below
   Vec<R> out;
   if (TERM == 0) {

@@ -22,11 +22,13 @@ hipError_t launch_me(int proc, int precision, const double* soa, int64_t nevt, c
                      const double* w_in, double* w_out, double* me_out, hipStream_t s);
 
 void process_constants(int proc, int* npart, int* ngood, int* ncol, int* ndiag);
+double process_flops(int proc);
 
 #define RWGT_DECLARE_PROCESS(NAME)                                                                        \
   hipError_t launch_me_##NAME(int precision, const double* soa, int64_t nevt, const CardPair* cards,     \
                               int ncards, const double* w_in, double* w_out, double* me_out, hipStream_t s); \
-  void constants_##NAME(int* npart, int* ngood, int* ncol, int* ndiag);
+  void constants_##NAME(int* npart, int* ngood, int* ncol, int* ndiag);                                 \
+  double flops_##NAME();
 RWGT_DECLARE_PROCESS(ee_mumu)
 RWGT_DECLARE_PROCESS(uu_eeg)
 RWGT_DECLARE_PROCESS(gg_ttgg)

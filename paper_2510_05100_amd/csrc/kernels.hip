@@ -60,4 +60,13 @@ void process_constants(int proc, int* npart, int* ngood, int* ncol, int* ndiag) 
   }
 }
 
+double process_flops(int proc) {
+  switch (proc) {
+    case kProcEeMumu: return flops_ee_mumu();
+    case kProcUuEeg: return flops_uu_eeg();
+    case kProcGgTtgg: return flops_gg_ttgg();
+  }
+  return 0.0;
+}
+
 }  // namespace rwgt

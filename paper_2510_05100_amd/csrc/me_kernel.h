@@ -21,7 +21,7 @@ namespace rwgt {
     template <class R>                                                                         \
     static __device__ __forceinline__ void jamps(const double (&P)[NPART][4], int hel,         \
                                                  const Card<R>& cd, cx<R> (&j)[NCOL]) {        \
-      gen_##NAME::jamps<R>(P, hel, cd, j);                                                     \
+      gen_##NAME::jamps<R, double>(P, hel, cd, j);                                                     \
     }                                                                                          \
     template <class R>                                                                         \
     static __device__ __forceinline__ R colour_sum(const cx<R> (&j)[NCOL]) {                   \

@@ -1,6 +1,7 @@
 // Matrix-element kernels for the generated process gg_ttgg (FP64 and mixed).
 #include "generated/gen_gg_ttgg.h"
 #include "me_kernel.h"
+#include "opcount.h"
 
 namespace rwgt {
 
@@ -18,6 +19,37 @@ void constants_gg_ttgg(int* npart, int* ngood, int* ncol, int* ndiag) {
   *ngood = gen_gg_ttgg::NGOOD;
   *ncol = gen_gg_ttgg::NCOL;
   *ndiag = gen_gg_ttgg::NDIAG;
+}
+
+// Floating-point operations of one |M|^2 (all kept helicities, colour sums,
+// average), counted by running the generated code on the host with OpCnt at a
+// representative point (beams along +-z, final state in generic directions).
+double flops_gg_ttgg() {
+  constexpr int N = gen_gg_ttgg::NPART;
+  static const double pts[6][4] = {{500.0, 0.0, 0.0, 500.0}, {500.0, 0.0, 0.0, -500.0},
+                                   {300.0, 110.0, -150.0, 90.0}, {250.0, -60.0, 120.0, -170.0},
+                                   {260.0, -30.0, 20.0, 90.0}, {190.0, -20.0, 10.0, -10.0}};
+  OpCnt P[N][4];
+  for (int a = 0; a < N; ++a)
+    for (int mu = 0; mu < 4; ++mu) P[a][mu] = pts[a][mu];
+  Card<OpCnt, OpCnt> cd;
+  cd.gqq = {0.0, 1.2};
+  cd.g3 = 1.2;
+  cd.g4 = 1.44;
+  for (int f = 0; f < 4; ++f) {
+    cd.aL[f] = cd.aR[f] = {0.0, 0.3};
+    cd.zL[f] = {0.0, 0.2};
+    cd.zR[f] = {0.0, 0.1};
+  }
+  cd.mz = 91.0;
+  cd.wz = 2.5;
+  cd.mt = 173.0;
+  OpCounter::flops = 0;
+  cx<OpCnt> j[gen_gg_ttgg::NCOL];
+  gen_gg_ttgg::jamps<OpCnt, OpCnt>(P, gen_gg_ttgg::GOOD_HOST[0], cd, j);
+  (void)gen_gg_ttgg::colour_sum<OpCnt>(j);
+  const double per_hel = double(OpCounter::flops) + 1.0;   // + accumulate into the sum
+  return per_hel * gen_gg_ttgg::NGOOD + 1.0;                 // + average factor
 }
 
 }  // namespace rwgt

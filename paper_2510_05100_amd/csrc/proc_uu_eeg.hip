@@ -1,6 +1,7 @@
 // Matrix-element kernels for the generated process uu_eeg (FP64 and mixed).
 #include "generated/gen_uu_eeg.h"
 #include "me_kernel.h"
+#include "opcount.h"
 
 namespace rwgt {
 
@@ -18,6 +19,37 @@ void constants_uu_eeg(int* npart, int* ngood, int* ncol, int* ndiag) {
   *ngood = gen_uu_eeg::NGOOD;
   *ncol = gen_uu_eeg::NCOL;
   *ndiag = gen_uu_eeg::NDIAG;
+}
+
+// Floating-point operations of one |M|^2 (all kept helicities, colour sums,
+// average), counted by running the generated code on the host with OpCnt at a
+// representative point (beams along +-z, final state in generic directions).
+double flops_uu_eeg() {
+  constexpr int N = gen_uu_eeg::NPART;
+  static const double pts[6][4] = {{500.0, 0.0, 0.0, 500.0}, {500.0, 0.0, 0.0, -500.0},
+                                   {300.0, 110.0, -150.0, 90.0}, {250.0, -60.0, 120.0, -170.0},
+                                   {260.0, -30.0, 20.0, 90.0}, {190.0, -20.0, 10.0, -10.0}};
+  OpCnt P[N][4];
+  for (int a = 0; a < N; ++a)
+    for (int mu = 0; mu < 4; ++mu) P[a][mu] = pts[a][mu];
+  Card<OpCnt, OpCnt> cd;
+  cd.gqq = {0.0, 1.2};
+  cd.g3 = 1.2;
+  cd.g4 = 1.44;
+  for (int f = 0; f < 4; ++f) {
+    cd.aL[f] = cd.aR[f] = {0.0, 0.3};
+    cd.zL[f] = {0.0, 0.2};
+    cd.zR[f] = {0.0, 0.1};
+  }
+  cd.mz = 91.0;
+  cd.wz = 2.5;
+  cd.mt = 173.0;
+  OpCounter::flops = 0;
+  cx<OpCnt> j[gen_uu_eeg::NCOL];
+  gen_uu_eeg::jamps<OpCnt, OpCnt>(P, gen_uu_eeg::GOOD_HOST[0], cd, j);
+  (void)gen_uu_eeg::colour_sum<OpCnt>(j);
+  const double per_hel = double(OpCounter::flops) + 1.0;   // + accumulate into the sum
+  return per_hel * gen_uu_eeg::NGOOD + 1.0;                 // + average factor
 }
 
 }  // namespace rwgt

@@ -152,6 +152,8 @@ struct rwgt_ctx {
   int hcards_cap = 0;
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
+  bool profiling = false;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // before ingest, after ingest, after ME
   std::string err;
 
   int fail(int code, const std::string& msg) {
@@ -164,6 +166,8 @@ struct rwgt_ctx {
   }
   ~rwgt_ctx() {
     if (upload_done) { hipEventSynchronize(upload_done); hipEventDestroy(upload_done); }
+    for (auto& e : ev)
+      if (e) hipEventDestroy(e);
     if (stream) hipStreamSynchronize(stream); else hipDeviceSynchronize();
     if (soa) hipFree(soa);
     if (dcards) hipFree(dcards);
@@ -252,11 +256,14 @@ int run(rwgt_ctx* c, bool reweight, const double* momenta, int64_t nevt, const d
   e = hipEventRecord(c->upload_done, c->stream);
   if (e != hipSuccess) return c->hip_fail(e, "hipEventRecord");
   c->upload_pending = true;
+  if (c->profiling) hipEventRecord(c->ev[0], c->stream);
   e = rwgt::launch_ingest(c->def->npart, momenta, c->soa, nevt, c->stream);
   if (e != hipSuccess) return c->hip_fail(e, "ingest kernel");
+  if (c->profiling) hipEventRecord(c->ev[1], c->stream);
   e = rwgt::launch_me(c->def->id, c->precision, c->soa, nevt, c->dcards, int(cards.size()), w_in, w_out, me_out,
                       c->stream);
   if (e != hipSuccess) return c->hip_fail(e, "matrix-element kernel");
+  if (c->profiling) hipEventRecord(c->ev[2], c->stream);
   return RWGT_OK;
 }
 
@@ -353,6 +360,34 @@ int rwgt_process_info(const rwgt_ctx* ctx, int32_t* npart, int32_t* nhel_kept, i
   if (nhel_kept) *nhel_kept = ng;
   if (ncol) *ncol = nc;
   if (ndiag) *ndiag = nd;
+  return RWGT_OK;
+}
+
+int rwgt_set_profiling(rwgt_ctx* ctx, int enable) {
+  if (!ctx) return RWGT_EINVAL;
+  if (enable && !ctx->ev[0]) {
+    for (auto& e : ctx->ev) {
+      const hipError_t rc = hipEventCreate(&e);
+      if (rc != hipSuccess) return ctx->hip_fail(rc, "hipEventCreate");
+    }
+  }
+  ctx->profiling = enable != 0;
+  return RWGT_OK;
+}
+
+int rwgt_kernel_times(rwgt_ctx* ctx, float* ingest_ms, float* me_ms) {
+  if (!ctx || !ingest_ms || !me_ms) return RWGT_EINVAL;
+  if (!ctx->profiling) return ctx->fail(RWGT_EINVAL, "profiling is off");
+  hipError_t e = hipEventSynchronize(ctx->ev[2]);
+  if (e == hipSuccess) e = hipEventElapsedTime(ingest_ms, ctx->ev[0], ctx->ev[1]);
+  if (e == hipSuccess) e = hipEventElapsedTime(me_ms, ctx->ev[1], ctx->ev[2]);
+  if (e != hipSuccess) return ctx->hip_fail(e, "kernel timing");
+  return RWGT_OK;
+}
+
+int rwgt_flops(const rwgt_ctx* ctx, double* flops_per_me2) {
+  if (!ctx || !flops_per_me2) return RWGT_EINVAL;
+  *flops_per_me2 = rwgt::process_flops(ctx->def->id);
   return RWGT_OK;
 }
 

@@ -24,7 +24,7 @@ SPECIES = {"e": 0, "mu": 1, "u": 2, "t": 3}
 
 def _mass(field):
     sym = FERMIONS[field][3]
-    return "cd.mt" if sym else "0.0"
+    return "cd.mt" if sym else "Massless{}"
 
 
 def _nsf(leg: Leg) -> int:
@@ -81,7 +81,7 @@ class Emitter:
             for mu in range(4):
                 e = " ".join(("+ " if s > 0 else "- ") + f"K{l}[{mu}]" for s, l in key)
                 parts.append(e.lstrip("+ ").replace("- ", "-", 1) if e.startswith("- ") else e.lstrip("+ "))
-            self.emit(f"const double {name}[4] = {{{', '.join(parts)}}};")
+            self.emit(f"const D {name}[4] = {{{', '.join(parts)}}};")
             self.kcache[key] = name
         return self.kcache[key]
 
@@ -380,6 +380,7 @@ def generate(d: Diagrams) -> str:
     out.append(f"constexpr double AVERAGE = {d.process.average!r};")
     out.append(f"constexpr int CDEN = {den};")
     out.append(f"__constant__ int GOOD[NGOOD] = {{{', '.join(map(str, good))}}};")
+    out.append(f"constexpr int GOOD_HOST[NGOOD] = {{{', '.join(map(str, good))}}};")
     out.append("constexpr int CNUM[NCOL][NCOL] = {")
     for row in num:
         out.append("  {" + ", ".join(map(str, row)) + "},")
@@ -388,11 +389,13 @@ def generate(d: Diagrams) -> str:
     for k, v in em.count.items():
         out.append(f"constexpr int N_{k.upper()} = {v};")
     out.append("")
-    out.append("template <class R>")
-    out.append(f"__device__ __forceinline__ void jamps(const double (&P)[{n}][4], int hel, const Card<R>& cd, cx<R> (&jamp)[NCOL]) {{")
+    out.append("// D is the momentum type: double on the device; an operation-counting")
+    out.append("// type when the host instantiates this to count arithmetic.")
+    out.append("template <class R, class D>")
+    out.append(f"__host__ __device__ __forceinline__ void jamps(const D (&P)[{n}][4], int hel, const Card<R, D>& cd, cx<R> (&jamp)[NCOL]) {{")
     for i, l in enumerate(legs):
         sign = "" if l.incoming else "-"
-        out.append(f"  const double K{i}[4] = {{{', '.join(f'{sign}P[{i}][{mu}]' for mu in range(4))}}};")
+        out.append(f"  const D K{i}[4] = {{{', '.join(f'{sign}P[{i}][{mu}]' for mu in range(4))}}};")
     for i in range(n):
         out.append(f"  const int h{i} = ((hel >> {n - 1 - i}) & 1) ? 1 : -1;")
     out.append("  for (int c = 0; c < NCOL; ++c) jamp[c] = cx<R>{R(0), R(0)};")
@@ -402,7 +405,7 @@ def generate(d: Diagrams) -> str:
     out.append("")
     # colour sum: J^dagger C J = sum_i J_i^* (C J)_i, C real symmetric
     out.append("template <class R>")
-    out.append("__device__ __forceinline__ R colour_sum(const cx<R> (&jamp)[NCOL]) {")
+    out.append("__host__ __device__ __forceinline__ R colour_sum(const cx<R> (&jamp)[NCOL]) {")
     out.append("  R me = R(0);")
     for i in range(ncol):
         tr = [f"R({num[i][i]}) * jamp[{i}].re"] + [f"R({2 * num[i][j]}) * jamp[{j}].re" for j in range(i + 1, ncol) if num[i][j]]
