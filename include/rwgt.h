@@ -115,6 +115,54 @@ int rwgt_set_profiling(rwgt_ctx *ctx, int enable);
  * profiling on; waits for that call to finish. */
 int rwgt_kernel_times(rwgt_ctx *ctx, float *ingest_ms, float *me_ms);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many reweighting jobs of one process family in one launch.
+ *
+ * Each segment is one rwgt_eval-like job with a single new card: its events
+ * (DEVICE momenta [nevt][npart][4], weights in/out [nevt]) are reweighted from
+ * the original card of contexts[ctx] to the card in params (HOST, one
+ * param_sets row of that context's layout).  All segments of one call go to
+ * one persistent kernel (workgroups take event tiles from a shared counter),
+ * captured once into a HIP graph and replayed while the number of segments,
+ * tiles and the schedule stay the same.  The schedule (tile size, workgroup
+ * size, workgroups per CU) comes from rwgt_batch_set_schedule, the tuning
+ * cache written by rwgt_batch_tune, or a default.  The paper runs
+ * subprocesses on a CPU thread pool and notes that sequential subprocesses
+ * leave the GPU latency-bound; this is the single-launch alternative.
+ * Family: e+ e- > mu+ mu- and u u~ > e+ e- g, all contexts of one precision.
+ */
+typedef struct rwgt_batch rwgt_batch;
+
+typedef struct {
+  int32_t ctx;                 /* index into the contexts of rwgt_batch_create */
+  int32_t reserved;
+  int64_t nevt;                /* events of the segment (0: skipped) */
+  const double *momenta;       /* DEVICE [nevt][npart][4] */
+  const double *weights_in;    /* DEVICE [nevt] */
+  const double *params;        /* HOST [npar]: the new card */
+  double *weights_out;         /* DEVICE [nevt] */
+} rwgt_segment;
+
+/* Bind contexts (not owned; they must outlive the batch).  Errors: RWGT_EINVAL,
+ * RWGT_EPROCESS (a context outside the family), RWGT_EDEVICE, RWGT_ENOMEM. */
+int rwgt_batch_create(rwgt_ctx *const *contexts, int32_t ncontexts, rwgt_batch **out);
+void rwgt_batch_destroy(rwgt_batch *batch);
+/* Stream of subsequent launches (NULL: a stream owned by the batch, which
+ * synchronises with the null stream). */
+int rwgt_batch_set_stream(rwgt_batch *batch, void *stream);
+/* Enqueue all segments as one graph launch.  Errors as rwgt_eval. */
+int rwgt_batch_eval(rwgt_batch *batch, const rwgt_segment *segments, int32_t nsegments);
+/* Milliseconds of the last graph launch (waits for it). */
+int rwgt_batch_time(rwgt_batch *batch, float *ms);
+/* Fix the schedule: events per tile, threads per workgroup (64..256, multiple
+ * of 64), persistent workgroups per compute unit. */
+int rwgt_batch_set_schedule(rwgt_batch *batch, int32_t tile_events, int32_t block, int32_t blocks_per_cu);
+int rwgt_batch_get_schedule(const rwgt_batch *batch, int32_t *tile_events, int32_t *block, int32_t *grid);
+/* Autotune the schedule on these segments (each candidate timed reps times
+ * after one capture run); keeps the fastest and records it in the cache. */
+int rwgt_batch_tune(rwgt_batch *batch, const rwgt_segment *segments, int32_t nsegments, int32_t reps);
+const char *rwgt_batch_last_error(const rwgt_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,6 +5,10 @@ The compute path lives in librwgt.so (HIP kernels for gfx950 behind the C ABI
 of include/rwgt.h); this package only marshals arguments to it.
 """
 from ._abi import (  # noqa: F401
+    Segment, make_segments, rwgt_batch_create, rwgt_batch_destroy, rwgt_batch_eval, rwgt_batch_get_schedule,
+    rwgt_batch_set_schedule, rwgt_batch_set_stream, rwgt_batch_time, rwgt_batch_tune,
+)
+from ._abi import (  # noqa: F401
     RWGT_FP64, RWGT_MIXED_BF16, RWGT_MIXED_FP16, RwgtError, load, rwgt_create, rwgt_destroy, rwgt_eval,
     rwgt_flops, rwgt_kernel_times, rwgt_me2, rwgt_original_params, rwgt_param_layout, rwgt_process_info,
     rwgt_set_profiling, rwgt_set_stream,

@@ -39,6 +39,26 @@ SIGNATURES = {
                                           ctypes.POINTER(ctypes.c_float)]),
 }
 
+class Segment(ctypes.Structure):
+    """rwgt_segment of include/rwgt.h."""
+    _fields_ = [("ctx", ctypes.c_int32), ("reserved", ctypes.c_int32), ("nevt", ctypes.c_int64),
+                ("momenta", ctypes.c_void_p), ("weights_in", ctypes.c_void_p),
+                ("params", ctypes.POINTER(ctypes.c_double)), ("weights_out", ctypes.c_void_p)]
+
+
+SIGNATURES.update({
+    "rwgt_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "rwgt_batch_destroy": (None, [ctypes.c_void_p]),
+    "rwgt_batch_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rwgt_batch_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Segment), ctypes.c_int32]),
+    "rwgt_batch_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
+    "rwgt_batch_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "rwgt_batch_get_schedule": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int32)] * 3),
+    "rwgt_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Segment), ctypes.c_int32, ctypes.c_int32]),
+    "rwgt_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+})
+
 _lib = None
 
 
@@ -188,3 +208,92 @@ def rwgt_kernel_times(ctx):
     if rc != 0:
         _raise(rc, ctx)
     return a.value, b.value
+
+
+def _braise(code, batch):
+    raise RwgtError(code, (load().rwgt_batch_last_error(batch) or b"").decode())
+
+
+def rwgt_batch_create(ctxs):
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.value for c in ctxs])
+    out = ctypes.c_void_p()
+    rc = load().rwgt_batch_create(arr, len(ctxs), ctypes.byref(out))
+    if rc != 0:
+        raise RwgtError(rc, "rwgt_batch_create failed")
+    return out
+
+
+def rwgt_batch_destroy(batch):
+    if batch:
+        load().rwgt_batch_destroy(batch)
+
+
+def rwgt_batch_set_stream(batch, stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    rc = load().rwgt_batch_set_stream(batch, ctypes.c_void_p(handle))
+    if rc != 0:
+        _braise(rc, batch)
+
+
+def make_segments(items):
+    """items: iterable of (ctx_index, momenta, weights_in, params row, weights_out);
+    returns (ctypes array, keep-alive list)."""
+    items = list(items)
+    arr = (Segment * len(items))()
+    keep = []
+    for s, (ci, mom, w_in, params, w_out) in zip(arr, items):
+        for t, name in ((mom, "momenta"), (w_in, "weights_in"), (w_out, "weights_out")):
+            _check_device(t, name)
+        prow, pptr = _host_params(params)
+        keep.append(prow)
+        s.ctx, s.nevt = int(ci), int(mom.shape[0])
+        s.momenta, s.weights_in, s.weights_out = mom.data_ptr(), w_in.data_ptr(), w_out.data_ptr()
+        s.params = pptr
+    return arr, keep
+
+
+def _segment_array(segments):
+    if isinstance(segments, ctypes.Array):
+        return segments
+    segments = list(segments)
+    return (Segment * len(segments))(*segments)
+
+
+def rwgt_batch_eval(batch, segments):
+    segments = _segment_array(segments)
+    rc = load().rwgt_batch_eval(batch, segments, len(segments))
+    if rc != 0:
+        _braise(rc, batch)
+
+
+def rwgt_batch_time(batch):
+    ms = ctypes.c_float()
+    rc = load().rwgt_batch_time(batch, ctypes.byref(ms))
+    if rc != 0:
+        _braise(rc, batch)
+    return ms.value
+
+
+def rwgt_batch_set_schedule(batch, tile_events, block, blocks_per_cu):
+    rc = load().rwgt_batch_set_schedule(batch, tile_events, block, blocks_per_cu)
+    if rc != 0:
+        _braise(rc, batch)
+
+
+def rwgt_batch_get_schedule(batch):
+    v = [ctypes.c_int32() for _ in range(3)]
+    rc = load().rwgt_batch_get_schedule(batch, *[ctypes.byref(x) for x in v])
+    if rc != 0:
+        _braise(rc, batch)
+    return dict(zip(("tile_events", "block", "grid"), (x.value for x in v)))
+
+
+def rwgt_batch_tune(batch, segments, reps=2):
+    segments = _segment_array(segments)
+    rc = load().rwgt_batch_tune(batch, segments, len(segments), reps)
+    if rc != 0:
+        _braise(rc, batch)
+    return rwgt_batch_get_schedule(batch)

@@ -1,0 +1,36 @@
+// Internal interface of the batched persistent launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "card.h"
+
+namespace rwgt {
+
+// Process families a batch kernel is compiled for; the process index of a
+// segment is its position in the family.
+enum { kFamilyElectroweak = 0 };   // 0: e+e- -> mu+mu-, 1: u u~ -> e+e- g
+
+struct BatchSeg {
+  int32_t proc;          // index within the family
+  int32_t pad;
+  int64_t nevt;
+  int64_t tile0;         // first global tile of the segment
+  const double* mom;     // [nevt][npart][4]
+  const double* w_in;    // [nevt]
+  double* w_out;         // [nevt]
+};
+
+struct BatchSchedule {
+  int tile_events;       // events per tile
+  int block;             // threads per workgroup
+  int grid;              // persistent workgroups
+};
+
+hipError_t launch_batch(int family, int precision, const BatchSeg* segs, int nseg, int64_t ntiles,
+                        const BatchSchedule& sc, const CardPair* cards, unsigned long long* counter,
+                        hipStream_t s);
+
+}  // namespace rwgt

@@ -1,0 +1,85 @@
+// Batched form: many (process, card, event-range) segments in one persistent
+// launch.  Workgroups claim fixed-size event tiles from a global counter until
+// none are left (every workgroup exits once the counter passes the tile
+// count), find the tile's segment by binary search over the segment table,
+// and evaluate |M|^2 under the segment's original and new cards for each
+// event of the tile: w' = (w * (1/|M|^2_orig)) * |M|^2_new.  Momenta are read
+// in the caller's AoS layout ([nevt][npart][4]); no separate ingest pass.
+#include <hip/hip_runtime.h>
+
+#include "batch.h"
+#include "generated/gen_ee_mumu.h"
+#include "generated/gen_uu_eeg.h"
+#include "me_kernel.h"
+
+namespace rwgt {
+
+RWGT_PROCESS_TRAITS(ee_mumu)
+RWGT_PROCESS_TRAITS(uu_eeg)
+
+template <class R, class PROC>
+__device__ __forceinline__ void batch_event(const BatchSeg& sg, int64_t e, const CardPair& c0, const CardPair& c1) {
+  double P[PROC::NPART][4];
+  const double* src = sg.mom + e * (PROC::NPART * 4);
+#pragma unroll
+  for (int a = 0; a < PROC::NPART; ++a)
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) P[a][mu] = src[a * 4 + mu];
+  const double m0 = me2_event<PROC, R>(P, pick<R>(c0));
+  const double m1 = me2_event<PROC, R>(P, pick<R>(c1));
+  sg.w_out[e] = ((m0 == 0.0 ? 0.0 : 1.0 / m0) * sg.w_in[e]) * m1;
+}
+
+template <class R, class... PROCS>
+__device__ __forceinline__ void batch_dispatch(int proc, const BatchSeg& sg, int64_t e, const CardPair& c0,
+                                               const CardPair& c1) {
+  int idx = 0;
+  ((proc == idx++ ? batch_event<R, PROCS>(sg, e, c0, c1) : void()), ...);
+}
+
+__global__ void batch_reset(unsigned long long* counter) { *counter = 0ull; }
+
+template <class R, class... PROCS>
+__global__ __launch_bounds__(256) void batch_kernel(const BatchSeg* __restrict__ segs, int nseg, int64_t ntiles,
+                                                    int tile_events, const CardPair* __restrict__ cards,
+                                                    unsigned long long* counter) {
+  __shared__ long long s_tile;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    __syncthreads();
+    if (tile >= ntiles) return;
+    int lo = 0, hi = nseg - 1;                 // last segment with tile0 <= tile
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (segs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+    }
+    const BatchSeg sg = segs[lo];
+    const int64_t e0 = (tile - sg.tile0) * tile_events;
+    const int64_t e1 = e0 + tile_events < sg.nevt ? e0 + tile_events : sg.nevt;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
+      batch_dispatch<R, PROCS...>(sg.proc, sg, e, cards[2 * lo], cards[2 * lo + 1]);
+  }
+}
+
+template <class R, class... PROCS>
+static hipError_t launch_batch_t(const BatchSeg* segs, int nseg, int64_t ntiles, const BatchSchedule& sc,
+                                 const CardPair* cards, unsigned long long* counter, hipStream_t s) {
+  hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, counter);
+  hipLaunchKernelGGL((batch_kernel<R, PROCS...>), dim3(sc.grid), dim3(sc.block), 0, s, segs, nseg, ntiles,
+                     sc.tile_events, cards, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(int family, int precision, const BatchSeg* segs, int nseg, int64_t ntiles,
+                        const BatchSchedule& sc, const CardPair* cards, unsigned long long* counter,
+                        hipStream_t s) {
+  const bool f64 = precision == kPrecFP64;
+  if (family == kFamilyElectroweak)
+    return f64 ? launch_batch_t<double, Proc_ee_mumu, Proc_uu_eeg>(segs, nseg, ntiles, sc, cards, counter, s)
+               : launch_batch_t<float, Proc_ee_mumu, Proc_uu_eeg>(segs, nseg, ntiles, sc, cards, counter, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace rwgt

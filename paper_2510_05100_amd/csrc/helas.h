@@ -55,6 +55,23 @@ template <class R> __host__ __device__ __forceinline__ cx<R> mdot(const Vec<R>& 
 template <class R, class D> __host__ __device__ __forceinline__ cx<R> mdot(const D* k, const Vec<R>& a) {
   return a.c[0] * R(k[0]) - a.c[1] * R(k[1]) - a.c[2] * R(k[2]) - a.c[3] * R(k[3]);
 }
+// A momentum component re-read at each use: opaque to value numbering on the
+// device, so the sums below are recomputed where they are needed instead of
+// being computed once and kept live across the whole helicity iteration.
+template <class D> __host__ __device__ __forceinline__ D opq(D x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(x));
+#endif
+  return x;
+}
+// Fence between amplitude terms: the instruction scheduler may not move work
+// across it, so the evaluation order chosen by the process compiler (which
+// keeps few currents live) is the order executed.
+__host__ __device__ __forceinline__ void term_fence() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_sched_barrier(0);
+#endif
+}
 template <class D> __host__ __device__ __forceinline__ D msq(const D* k) {
   return k[0] * k[0] - k[1] * k[1] - k[2] * k[2] - k[3] * k[3];
 }
@@ -200,107 +217,158 @@ __host__ __device__ __forceinline__ void row_qsigmabar(const R* q, cx<R> x0, cx<
 }
 
 // ------------------------------------------------------------------ vertices
-// FFV1_0 role: amplitude fo . Gamma(V) . fi.
-template <class R>
-__host__ __device__ __forceinline__ cx<R> ffv_amp(const Spinor<R>& fo, const Spinor<R>& fi, const Vec<R>& v, cx<R> cl, cx<R> cr) {
-  cx<R> a0, a1, b0, b1;
-  vsigma(v, fi.c[2], fi.c[3], a0, a1);        // (V.sigma) psi_R
-  vsigmabar(v, fi.c[0], fi.c[1], b0, b1);     // (V.sigmabar) psi_L
-  return cr * (fo.c[0] * a0 + fo.c[1] * a1) + cl * (fo.c[2] * b0 + fo.c[3] * b1);
-}
+// Every vertex coupling of these processes is purely imaginary, c = i kappa
+// (quark-gluon i g_s, photon -i e Q, Z -i e/(s_W c_W) g_{L,R}); the routines
+// take the real kappa and fold the i into the propagator factors.  "_v"
+// routines take one kappa (vector coupling), "_c" ones kappa_L and kappa_R.
 
-// Off-shell fermion flowing in: i (q-slash + m)/(q^2 - m^2) Gamma(V) fi.
-template <class R, class D, class M>
-__host__ __device__ __forceinline__ Spinor<R> ffv_in(const Spinor<R>& fi, const Vec<R>& v, cx<R> cl, cx<R> cr,
-                                                     const D* qd, M m) {
-  cx<R> u0, u1, d0, d1;
+// (V.sigma) psi_R and (V.sigmabar) psi_L of Gamma(V) psi.
+template <class R>
+__host__ __device__ __forceinline__ void gamma_v(const Vec<R>& v, const Spinor<R>& fi, cx<R>& u0, cx<R>& u1,
+                                                 cx<R>& d0, cx<R>& d1) {
   vsigma(v, fi.c[2], fi.c[3], u0, u1);
   vsigmabar(v, fi.c[0], fi.c[1], d0, d1);
-  u0 = cr * u0; u1 = cr * u1; d0 = cl * d0; d1 = cl * d1;
-  const R q[4] = {R(qd[0]), R(qd[1]), R(qd[2]), R(qd[3])};
-  Spinor<R> s;
-  cx<R> t0, t1;
-  qsigma(q, d0, d1, t0, t1);                   // upper = m chi_u + (q.sigma) chi_d
-  s.c[0] = t0; s.c[1] = t1;
-  qsigmabar(q, u0, u1, t0, t1);                // lower = (q.sigmabar) chi_u + m chi_d
-  s.c[2] = t0; s.c[3] = t1;
-  R den;
-  if constexpr (is_massless<M>) {
-    den = R(1.0 / msq(qd));
-  } else {
-    den = R(1.0 / (msq(qd) - m * m));
-    const R rm = R(m);
-    s.c[0] = s.c[0] + u0 * rm; s.c[1] = s.c[1] + u1 * rm;
-    s.c[2] = s.c[2] + d0 * rm; s.c[3] = s.c[3] + d1 * rm;
-  }
-  for (int i = 0; i < 4; ++i) s.c[i] = times_i(s.c[i]) * den;
-  return s;
 }
-
-// Off-shell fermion flowing out (row): fo Gamma(V) i (q-slash + m)/(q^2 - m^2).
-template <class R, class D, class M>
-__host__ __device__ __forceinline__ Spinor<R> ffv_out(const Spinor<R>& fo, const Vec<R>& v, cx<R> cl, cx<R> cr,
-                                                      const D* qd, M m) {
-  cx<R> u0, u1, d0, d1;
-  row_vsigmabar(v, fo.c[2], fo.c[3], u0, u1);  // row (b V.sigmabar) cL
-  row_vsigma(v, fo.c[0], fo.c[1], d0, d1);     // row (a V.sigma) cR
-  u0 = cl * u0; u1 = cl * u1; d0 = cr * d0; d1 = cr * d1;
-  const R q[4] = {R(qd[0]), R(qd[1]), R(qd[2]), R(qd[3])};
-  Spinor<R> s;
-  cx<R> t0, t1;
-  row_qsigmabar(q, d0, d1, t0, t1);            // first half = m r_u + r_d (q.sigmabar)
-  s.c[0] = t0; s.c[1] = t1;
-  row_qsigma(q, u0, u1, t0, t1);               // second half = r_u (q.sigma) + m r_d
-  s.c[2] = t0; s.c[3] = t1;
-  R den;
-  if constexpr (is_massless<M>) {
-    den = R(1.0 / msq(qd));
-  } else {
-    den = R(1.0 / (msq(qd) - m * m));
-    const R rm = R(m);
-    s.c[0] = s.c[0] + u0 * rm; s.c[1] = s.c[1] + u1 * rm;
-    s.c[2] = s.c[2] + d0 * rm; s.c[3] = s.c[3] + d1 * rm;
-  }
-  for (int i = 0; i < 4; ++i) s.c[i] = times_i(s.c[i]) * den;
-  return s;
-}
-
-// Vector current of a fermion pair, j^mu = fo gamma^mu (cL P_L + cR P_R) fi.
+// Row versions: (b V.sigmabar, a V.sigma) of fo Gamma(V), fo = (a, b).
 template <class R>
-__host__ __device__ __forceinline__ Vec<R> ff_current(const Spinor<R>& fo, const Spinor<R>& fi, cx<R> cl, cx<R> cr) {
-  // a sigma^mu psi_R and b sigmabar^mu psi_L, a = fo[0..1], b = fo[2..3]
+__host__ __device__ __forceinline__ void row_gamma_v(const Vec<R>& v, const Spinor<R>& fo, cx<R>& u0, cx<R>& u1,
+                                                     cx<R>& d0, cx<R>& d1) {
+  row_vsigmabar(v, fo.c[2], fo.c[3], u0, u1);
+  row_vsigma(v, fo.c[0], fo.c[1], d0, d1);
+}
+
+// Fermion-pair vectors X^mu = a sigma^mu psi_R, Y^mu = b sigmabar^mu psi_L
+// (fo = (a, b), fi = (psi_L, psi_R)); fo gamma^mu (cL P_L + cR P_R) fi =
+// i (kR X + kL Y).  pair_w returns W = X + Y (vector coupling).
+template <class R>
+__host__ __device__ __forceinline__ void pair_xy(const Spinor<R>& fo, const Spinor<R>& fi, Vec<R>& x, Vec<R>& y) {
   const cx<R> a0 = fo.c[0], a1 = fo.c[1], b0 = fo.c[2], b1 = fo.c[3];
   const cx<R> r0 = fi.c[2], r1 = fi.c[3], l0 = fi.c[0], l1 = fi.c[1];
   const cx<R> s00 = a0 * r0, s01 = a0 * r1, s10 = a1 * r0, s11 = a1 * r1;
   const cx<R> t00 = b0 * l0, t01 = b0 * l1, t10 = b1 * l0, t11 = b1 * l1;
-  Vec<R> j;
-  j.c[0] = cr * (s00 + s11) + cl * (t00 + t11);
-  j.c[1] = cr * (s01 + s10) - cl * (t01 + t10);
-  j.c[2] = cr * times_i(s10 - s01) - cl * times_i(t10 - t01);
-  j.c[3] = cr * (s00 - s11) - cl * (t00 - t11);
-  return j;
+  x.c[0] = s00 + s11; x.c[1] = s01 + s10; x.c[2] = times_i(s10 - s01); x.c[3] = s00 - s11;
+  y.c[0] = t00 + t11; y.c[1] = -(t01 + t10); y.c[2] = times_i(t01 - t10); y.c[3] = t11 - t00;
+}
+template <class R>
+__host__ __device__ __forceinline__ Vec<R> pair_w(const Spinor<R>& fo, const Spinor<R>& fi) {
+  const cx<R> a0 = fo.c[0], a1 = fo.c[1], b0 = fo.c[2], b1 = fo.c[3];
+  const cx<R> r0 = fi.c[2], r1 = fi.c[3], l0 = fi.c[0], l1 = fi.c[1];
+  const cx<R> s00 = a0 * r0, s01 = a0 * r1, s10 = a1 * r0, s11 = a1 * r1;
+  const cx<R> t00 = b0 * l0, t01 = b0 * l1, t10 = b1 * l0, t11 = b1 * l1;
+  Vec<R> w;
+  w.c[0] = (s00 + s11) + (t00 + t11);
+  w.c[1] = (s01 + s10) - (t01 + t10);
+  w.c[2] = times_i((s10 - s01) - (t10 - t01));
+  w.c[3] = (s00 - s11) - (t00 - t11);
+  return w;
 }
 
-// Off-shell massless vector from a fermion pair: -i j^mu / q^2.
-template <class R, class D>
-__host__ __device__ __forceinline__ Vec<R> ffv_vec0(const Spinor<R>& fo, const Spinor<R>& fi, cx<R> cl, cx<R> cr, const D* q) {
-  Vec<R> j = ff_current(fo, fi, cl, cr);
-  const R den = R(1.0 / msq(q));
-  for (int i = 0; i < 4; ++i) j.c[i] = times_minus_i(j.c[i]) * den;
-  return j;
+// FFV1_0 role, vector coupling: fo Gamma(V) fi = i k V.W(fo, fi).
+template <class R>
+__host__ __device__ __forceinline__ cx<R> ffv_amp_v(const Spinor<R>& fo, const Spinor<R>& fi, const Vec<R>& v, R k) {
+  return times_i(mdot(v, pair_w(fo, fi))) * k;
+}
+// Same with a precomputed W of the (fo, fi) pair.
+template <class R>
+__host__ __device__ __forceinline__ cx<R> pair_amp_v(const Vec<R>& w, const Vec<R>& v, R k) {
+  return times_i(mdot(v, w)) * k;
+}
+// FFV1_0 role, chiral coupling: i (kR V.X + kL V.Y).
+template <class R>
+__host__ __device__ __forceinline__ cx<R> ffv_amp_c(const Spinor<R>& fo, const Spinor<R>& fi, const Vec<R>& v, R kl, R kr) {
+  Vec<R> x, y;
+  pair_xy(fo, fi, x, y);
+  return times_i(mdot(v, x) * kr + mdot(v, y) * kl);
 }
 
-// Off-shell massive vector from a fermion pair (unitary gauge, fixed width):
-// -i (j^mu - q^mu (q.j)/M^2) / (q^2 - M^2 + i M W); the denominator is formed
-// and inverted in double.
+// (q-slash + m) applied to a column (u, d) / a row (u, d), then scaled by s.
 template <class R, class D, class M>
-__host__ __device__ __forceinline__ Vec<R> ffv_vecm(const Spinor<R>& fo, const Spinor<R>& fi, cx<R> cl, cx<R> cr,
-                                                    const D* q, M mass, M width) {
-  Vec<R> j = ff_current(fo, fi, cl, cr);
+__host__ __device__ __forceinline__ Spinor<R> qslash_col(cx<R> u0, cx<R> u1, cx<R> d0, cx<R> d1, const D* qd, M m, R s) {
+  const R q[4] = {R(qd[0]), R(qd[1]), R(qd[2]), R(qd[3])};
+  Spinor<R> o;
+  qsigma(q, d0, d1, o.c[0], o.c[1]);          // upper = (q.sigma) d + m u
+  qsigmabar(q, u0, u1, o.c[2], o.c[3]);       // lower = (q.sigmabar) u + m d
+  if constexpr (!is_massless<M>) {
+    const R rm = R(m);
+    o.c[0] = o.c[0] + u0 * rm; o.c[1] = o.c[1] + u1 * rm;
+    o.c[2] = o.c[2] + d0 * rm; o.c[3] = o.c[3] + d1 * rm;
+  }
+  for (int i = 0; i < 4; ++i) o.c[i] = o.c[i] * s;
+  return o;
+}
+template <class R, class D, class M>
+__host__ __device__ __forceinline__ Spinor<R> qslash_row(cx<R> u0, cx<R> u1, cx<R> d0, cx<R> d1, const D* qd, M m, R s) {
+  const R q[4] = {R(qd[0]), R(qd[1]), R(qd[2]), R(qd[3])};
+  Spinor<R> o;
+  row_qsigmabar(q, d0, d1, o.c[0], o.c[1]);   // first half = m u + d (q.sigmabar)
+  row_qsigma(q, u0, u1, o.c[2], o.c[3]);      // second half = u (q.sigma) + m d
+  if constexpr (!is_massless<M>) {
+    const R rm = R(m);
+    o.c[0] = o.c[0] + u0 * rm; o.c[1] = o.c[1] + u1 * rm;
+    o.c[2] = o.c[2] + d0 * rm; o.c[3] = o.c[3] + d1 * rm;
+  }
+  for (int i = 0; i < 4; ++i) o.c[i] = o.c[i] * s;
+  return o;
+}
+// 1/(q^2 - m^2) in double (the momentum type), then rounded
+template <class D, class M>
+__host__ __device__ __forceinline__ D inv_den(const D* q, M m) {
+  if constexpr (is_massless<M>) return 1.0 / msq(q);
+  else return 1.0 / (msq(q) - m * m);
+}
+
+// Off-shell fermion flowing in, i (q-slash + m)/(q^2 - m^2) Gamma(V) fi, with
+// Gamma = i kappa V-slash: -kappa (q-slash + m)/(q^2 - m^2) V-slash fi.
+template <class R, class D, class M>
+__host__ __device__ __forceinline__ Spinor<R> ffv_in_v(const Spinor<R>& fi, const Vec<R>& v, R k, const D* q, M m) {
+  cx<R> u0, u1, d0, d1;
+  gamma_v(v, fi, u0, u1, d0, d1);
+  return qslash_col(u0, u1, d0, d1, q, m, R(-k * inv_den(q, m)));
+}
+template <class R, class D, class M>
+__host__ __device__ __forceinline__ Spinor<R> ffv_in_c(const Spinor<R>& fi, const Vec<R>& v, R kl, R kr, const D* q, M m) {
+  cx<R> u0, u1, d0, d1;
+  gamma_v(v, fi, u0, u1, d0, d1);
+  u0 = u0 * kr; u1 = u1 * kr; d0 = d0 * kl; d1 = d1 * kl;
+  return qslash_col(u0, u1, d0, d1, q, m, R(-inv_den(q, m)));
+}
+// Off-shell fermion flowing out (row): fo Gamma(V) i (q-slash + m)/(q^2 - m^2).
+template <class R, class D, class M>
+__host__ __device__ __forceinline__ Spinor<R> ffv_out_v(const Spinor<R>& fo, const Vec<R>& v, R k, const D* q, M m) {
+  cx<R> u0, u1, d0, d1;
+  row_gamma_v(v, fo, u0, u1, d0, d1);
+  return qslash_row(u0, u1, d0, d1, q, m, R(-k * inv_den(q, m)));
+}
+template <class R, class D, class M>
+__host__ __device__ __forceinline__ Spinor<R> ffv_out_c(const Spinor<R>& fo, const Vec<R>& v, R kl, R kr, const D* q, M m) {
+  cx<R> u0, u1, d0, d1;
+  row_gamma_v(v, fo, u0, u1, d0, d1);
+  u0 = u0 * kl; u1 = u1 * kl; d0 = d0 * kr; d1 = d1 * kr;
+  return qslash_row(u0, u1, d0, d1, q, m, R(-inv_den(q, m)));
+}
+
+// Off-shell massless vector from a fermion pair, vector coupling:
+// (-i/q^2) (i k W) = k W / q^2.
+template <class R, class D>
+__host__ __device__ __forceinline__ Vec<R> ffv_vec0_v(const Spinor<R>& fo, const Spinor<R>& fi, R k, const D* q) {
+  Vec<R> w = pair_w(fo, fi);
+  const R s = R(k / msq(q));
+  for (int i = 0; i < 4; ++i) w.c[i] = w.c[i] * s;
+  return w;
+}
+
+// Off-shell massive vector from a fermion pair, chiral coupling, unitary
+// gauge and fixed width: (-i)(i j')... = (j' - q (q.j')/M^2) / (q^2 - M^2 + i M W)
+// with j' = kR X + kL Y; the denominator is formed and inverted in double.
+template <class R, class D, class M>
+__host__ __device__ __forceinline__ Vec<R> ffv_vecm_c(const Spinor<R>& fo, const Spinor<R>& fi, R kl, R kr,
+                                                      const D* q, M mass, M width) {
+  Vec<R> x, y, j;
+  pair_xy(fo, fi, x, y);
+  for (int i = 0; i < 4; ++i) j.c[i] = x.c[i] * kr + y.c[i] * kl;
   const D dre = msq(q) - mass * mass, dim = mass * width;
   const D inv = 1.0 / (dre * dre + dim * dim);
-  // -i / (dre + i dim) = (-dim - i dre) / |d|^2
-  const cx<R> f = {R(-dim * inv), R(-dre * inv)};
+  const cx<R> f = {R(dre * inv), R(-dim * inv)};      // 1 / (dre + i dim)
   const cx<R> qj = mdot(q, j) * R(1.0 / (mass * mass));
   for (int i = 0; i < 4; ++i) j.c[i] = f * (j.c[i] - qj * R(q[i]));
   return j;

@@ -6,7 +6,10 @@
 
 #include <cstdint>
 
+#include <type_traits>
+
 #include "card.h"
+#include "colour_mfma.h"
 #include "kernels.h"
 
 namespace rwgt {
@@ -17,14 +20,16 @@ namespace rwgt {
     static constexpr int NCOL = gen_##NAME::NCOL;                                              \
     static constexpr int NGOOD = gen_##NAME::NGOOD;                                            \
     static constexpr double AVERAGE = gen_##NAME::AVERAGE;                                     \
+    static constexpr int CDEN = gen_##NAME::CDEN;                                              \
+    static __device__ __forceinline__ const int (&cnum())[NCOL][NCOL] { return gen_##NAME::CNUM; } \
     static __device__ __forceinline__ int good(int i) { return gen_##NAME::GOOD[i]; }         \
-    template <class R>                                                                         \
+    template <class R, class J>                                                                \
     static __device__ __forceinline__ void jamps(const double (&P)[NPART][4], int hel,         \
-                                                 const Card<R>& cd, cx<R> (&j)[NCOL]) {        \
-      gen_##NAME::jamps<R, double>(P, hel, cd, j);                                                     \
+                                                 const Card<R>& cd, J& j) {                    \
+      gen_##NAME::jamps<R, double>(P, hel, cd, j);                                             \
     }                                                                                          \
-    template <class R>                                                                         \
-    static __device__ __forceinline__ R colour_sum(const cx<R> (&j)[NCOL]) {                   \
+    template <class R, class J>                                                                \
+    static __device__ __forceinline__ R colour_sum(const J& j) {                               \
       return gen_##NAME::colour_sum<R>(j);                                                     \
     }                                                                                          \
   };
@@ -33,41 +38,87 @@ template <class R> __device__ __forceinline__ const Card<R>& pick(const CardPair
 template <> __device__ __forceinline__ const Card<double>& pick<double>(const CardPair& c) { return c.d; }
 template <> __device__ __forceinline__ const Card<float>& pick<float>(const CardPair& c) { return c.f; }
 
+// Colour-flow amplitudes of one lane kept in LDS, [NCOL][kMeBlock] so that
+// the lanes of a wave touch consecutive addresses.
+template <class R, int NCOL>
+struct LdsJamp {
+  cx<R>* base;
+  __device__ __forceinline__ cx<R>& operator[](int c) { return base[c * kMeBlock]; }
+  __device__ __forceinline__ const cx<R>& operator[](int c) const { return base[c * kMeBlock]; }
+};
+
+// Where a lane keeps its colour-flow amplitudes: registers, unless the
+// process has many flows and the amplitudes are double (then LDS, which frees
+// 4 * NCOL registers for the currents).
 template <class PROC, class R>
+constexpr bool jamp_in_lds() { return PROC::NCOL >= 8 && sizeof(R) == 8; }
+
+// |M|^2 of one event under one card with the colour flows in registers and
+// the colour sum on the VALU (the form of few-flow processes).
+template <class PROC, class R>
+__device__ __forceinline__ double me2_event(const double (&P)[PROC::NPART][4], const Card<R>& cd) {
+  double me = 0.0;
+  for (int ih = 0; ih < PROC::NGOOD; ++ih) {
+    cx<R> jamp[PROC::NCOL];
+    PROC::template jamps<R>(P, PROC::good(ih), cd, jamp);
+    me += double(PROC::template colour_sum<R>(jamp));
+  }
+  return me * PROC::AVERAGE;
+}
+
+// LDS of the matrix-core colour sum (one region per wave), or nothing.
+template <class CT> struct ColourLdsOf { typedef ColourLds<CT> type; };
+template <> struct ColourLdsOf<void> { typedef char type; };
+
+// One lane per event.  R: amplitude precision.  CT: 16-bit type of the
+// matrix-core colour sum (_Float16 or __bf16), or void for the VALU form.
+template <class PROC, class R, class CT>
 __global__ __launch_bounds__(kMeBlock) void me_kernel(const double* __restrict__ soa, int64_t nevt,
                                                       const CardPair* __restrict__ cards, int ncards,
                                                       const double* __restrict__ w_in, double* __restrict__ w_out,
                                                       double* __restrict__ me_out) {
+  constexpr bool kMfma = !std::is_void<CT>::value;
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= nevt) return;
+  // whole waves past the end leave together; inside the last wave the lanes
+  // past the end recompute the last event (the matrix-core colour sum needs
+  // every lane) and write nothing
+  if (int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63) >= nevt) return;
+  const bool valid = i < nevt;
+  const int64_t ie = valid ? i : nevt - 1;
   double P[PROC::NPART][4];
 #pragma unroll
   for (int a = 0; a < PROC::NPART; ++a)
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) P[a][mu] = soa[int64_t(a * 4 + mu) * nevt + i];
+    for (int mu = 0; mu < 4; ++mu) P[a][mu] = soa[int64_t(a * 4 + mu) * nevt + ie];
+
+  [[maybe_unused]] __shared__ cx<R> lds_jamp[jamp_in_lds<PROC, R>() ? PROC::NCOL * kMeBlock : 1];
+  [[maybe_unused]] __shared__ typename ColourLdsOf<CT>::type lds_colour[kMfma ? kMeBlock / 64 : 1];
+  [[maybe_unused]] std::conditional_t<kMfma, ColourMfma<PROC::NCOL, std::conditional_t<kMfma, CT, _Float16>>, char> cm;
+  if constexpr (kMfma) cm.init(PROC::cnum(), lds_colour[threadIdx.x >> 6]);
 
   double norm = 0.0;
   for (int k = 0; k < ncards; ++k) {
     const Card<R>& cd = pick<R>(cards[k]);
     double me = 0.0;
     for (int ih = 0; ih < PROC::NGOOD; ++ih) {
-      // Momentum sums and propagator denominators do not depend on the
-      // helicity; left to itself the compiler hoists all of them out of this
-      // loop and keeps them live across it, which spills.  Re-defining the
-      // momenta opaquely here keeps that algebra inside the iteration.
-      double Ph[PROC::NPART][4];
-#pragma unroll
-      for (int a = 0; a < PROC::NPART; ++a)
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
-          Ph[a][mu] = P[a][mu];
-          asm volatile("" : "+v"(Ph[a][mu]));
+      // The generated code reads the momenta through opq() at every use, so
+      // none of the helicity-independent algebra is hoisted out of this loop.
+      if constexpr (jamp_in_lds<PROC, R>()) {
+        LdsJamp<R, PROC::NCOL> jamp{lds_jamp + threadIdx.x};
+        PROC::template jamps<R>(P, PROC::good(ih), cd, jamp);
+        me += double(PROC::template colour_sum<R>(jamp));
+      } else {
+        cx<R> jamp[PROC::NCOL];
+        PROC::template jamps<R>(P, PROC::good(ih), cd, jamp);
+        if constexpr (kMfma) {
+          me += cm.sum(jamp, lds_colour[threadIdx.x >> 6]) * (1.0 / PROC::CDEN);
+        } else {
+          me += double(PROC::template colour_sum<R>(jamp));
         }
-      cx<R> jamp[PROC::NCOL];
-      PROC::template jamps<R>(Ph, PROC::good(ih), cd, jamp);
-      me += double(PROC::template colour_sum<R>(jamp));
+      }
     }
     me *= PROC::AVERAGE;
+    if (!valid) continue;
     if (me_out) me_out[int64_t(k) * nevt + i] = me;
     if (w_out) {
       if (k == 0) {
@@ -79,13 +130,29 @@ __global__ __launch_bounds__(kMeBlock) void me_kernel(const double* __restrict__
   }
 }
 
-template <class PROC, class R>
+template <class PROC, class R, class CT>
 inline hipError_t launch_me_t(const double* soa, int64_t nevt, const CardPair* cards, int ncards,
                               const double* w_in, double* w_out, double* me_out, hipStream_t s) {
   const int64_t blocks = (nevt + kMeBlock - 1) / kMeBlock;
-  hipLaunchKernelGGL((me_kernel<PROC, R>), dim3(unsigned(blocks)), dim3(kMeBlock), 0, s, soa, nevt, cards, ncards,
-                     w_in, w_out, me_out);
+  hipLaunchKernelGGL((me_kernel<PROC, R, CT>), dim3(unsigned(blocks)), dim3(kMeBlock), 0, s, soa, nevt, cards,
+                     ncards, w_in, w_out, me_out);
   return hipGetLastError();
+}
+
+// Precision dispatch: FP64; or float amplitudes with the colour sum on the
+// matrix cores (FP16 or BF16 split) for many-flow processes, on the VALU
+// otherwise.
+template <class PROC>
+inline hipError_t launch_me_prec(int precision, const double* soa, int64_t nevt, const CardPair* cards, int ncards,
+                                 const double* w_in, double* w_out, double* me_out, hipStream_t s) {
+  constexpr bool many = PROC::NCOL >= 8;
+  if (precision == kPrecFP64)
+    return launch_me_t<PROC, double, void>(soa, nevt, cards, ncards, w_in, w_out, me_out, s);
+  if (precision == kPrecMixedBF16)
+    return launch_me_t<PROC, float, std::conditional_t<many, __bf16, void>>(soa, nevt, cards, ncards, w_in, w_out,
+                                                                             me_out, s);
+  return launch_me_t<PROC, float, std::conditional_t<many, _Float16, void>>(soa, nevt, cards, ncards, w_in, w_out,
+                                                                             me_out, s);
 }
 
 

@@ -9,9 +9,7 @@ RWGT_PROCESS_TRAITS(gg_ttgg)
 
 hipError_t launch_me_gg_ttgg(int precision, const double* soa, int64_t nevt, const CardPair* cards, int ncards,
                             const double* w_in, double* w_out, double* me_out, hipStream_t s) {
-  if (precision == kPrecFP64)
-    return launch_me_t<Proc_gg_ttgg, double>(soa, nevt, cards, ncards, w_in, w_out, me_out, s);
-  return launch_me_t<Proc_gg_ttgg, float>(soa, nevt, cards, ncards, w_in, w_out, me_out, s);
+  return launch_me_prec<Proc_gg_ttgg>(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, s);
 }
 
 void constants_gg_ttgg(int* npart, int* ngood, int* ncol, int* ndiag) {
@@ -33,13 +31,13 @@ double flops_gg_ttgg() {
   for (int a = 0; a < N; ++a)
     for (int mu = 0; mu < 4; ++mu) P[a][mu] = pts[a][mu];
   Card<OpCnt, OpCnt> cd;
-  cd.gqq = {0.0, 1.2};
+  cd.gqq = 1.2;
   cd.g3 = 1.2;
   cd.g4 = 1.44;
   for (int f = 0; f < 4; ++f) {
-    cd.aL[f] = cd.aR[f] = {0.0, 0.3};
-    cd.zL[f] = {0.0, 0.2};
-    cd.zR[f] = {0.0, 0.1};
+    cd.a[f] = 0.3;
+    cd.zL[f] = 0.2;
+    cd.zR[f] = 0.1;
   }
   cd.mz = 91.0;
   cd.wz = 2.5;

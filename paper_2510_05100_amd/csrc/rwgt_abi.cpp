@@ -12,12 +12,16 @@
 #include <string>
 #include <vector>
 
+#include <chrono>
+#include <cstdlib>
+#include <fstream>
+
 #include "../../include/rwgt.h"
+#include "batch.h"
 #include "kernels.h"
 
 using rwgt::Card;
 using rwgt::CardPair;
-using rwgt::cx;
 
 namespace {
 
@@ -114,14 +118,13 @@ Card<R> couplings(const std::map<std::string, double>& m) {
   const double sw = std::sqrt(sw2), cw = std::sqrt(1.0 - sw2);
   const double gz = (sw > 0.0 && cw > 0.0) ? e / (sw * cw) : 0.0;
   Card<R> c;
-  c.gqq = cx<R>{R(0), R(gs)};
+  c.gqq = R(gs);                    // i g_s gamma^mu t^a
   c.g3 = R(gs);
   c.g4 = R(gs * gs);
   for (int f = 0; f < 4; ++f) {
-    c.aL[f] = cx<R>{R(0), R(-e * kQ[f])};
-    c.aR[f] = c.aL[f];
-    c.zL[f] = cx<R>{R(0), R(-gz * (kT3[f] - kQ[f] * sw2))};
-    c.zR[f] = cx<R>{R(0), R(-gz * (-kQ[f] * sw2))};
+    c.a[f] = R(-e * kQ[f]);                      // -i e Q gamma^mu
+    c.zL[f] = R(-gz * (kT3[f] - kQ[f] * sw2));   // -i gZ gL gamma^mu P_L
+    c.zR[f] = R(-gz * (-kQ[f] * sw2));           // -i gZ gR gamma^mu P_R
   }
   c.mz = get(m, "MASS 23", 0.0);
   c.wz = get(m, "DECAY 23", 0.0);
@@ -390,5 +393,322 @@ int rwgt_flops(const rwgt_ctx* ctx, double* flops_per_me2) {
   *flops_per_me2 = rwgt::process_flops(ctx->def->id);
   return RWGT_OK;
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------ batched form
+struct rwgt_batch {
+  std::vector<rwgt_ctx*> ctxs;
+  int precision = 0;
+  int family = rwgt::kFamilyElectroweak;
+  int device = 0;
+  int ncu = 256;
+  hipStream_t user_stream = nullptr;
+  hipStream_t own_stream = nullptr;    // capture needs a non-null stream
+  rwgt::BatchSeg* dsegs = nullptr;
+  CardPair* dcards = nullptr;
+  rwgt::BatchSeg* hsegs = nullptr;     // pinned staging
+  CardPair* hcards = nullptr;
+  int cap = 0;
+  unsigned long long* counter = nullptr;
+  hipEvent_t staged = nullptr, t0 = nullptr, t1 = nullptr;
+  bool staged_pending = false;
+  rwgt::BatchSchedule sched{256, 256, 0};
+  bool tuned = false;
+  // captured graph and the launch shape it was captured for
+  hipGraphExec_t exec = nullptr;
+  int g_nseg = -1, g_tile = 0, g_block = 0, g_grid = 0;
+  int64_t g_ntiles = -1;
+  std::string err;
+
+  int fail(int code, const std::string& m) { err = m; return code; }
+  int hip_fail(hipError_t e, const char* what) {
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? RWGT_ENOMEM : RWGT_EDEVICE;
+  }
+  hipStream_t stream() const { return user_stream ? user_stream : own_stream; }
+  ~rwgt_batch() {
+    if (own_stream) hipStreamSynchronize(own_stream);
+    if (user_stream) hipStreamSynchronize(user_stream);
+    if (exec) hipGraphExecDestroy(exec);
+    if (dsegs) hipFree(dsegs);
+    if (dcards) hipFree(dcards);
+    if (counter) hipFree(counter);
+    if (hsegs) hipHostFree(hsegs);
+    if (hcards) hipHostFree(hcards);
+    for (hipEvent_t e : {staged, t0, t1})
+      if (e) hipEventDestroy(e);
+    if (own_stream) hipStreamDestroy(own_stream);
+  }
+};
+
+namespace {
+
+int family_index(int proc) {
+  if (proc == rwgt::kProcEeMumu) return 0;
+  if (proc == rwgt::kProcUuEeg) return 1;
+  return -1;
+}
+
+std::string tune_cache_path() {
+  if (const char* p = std::getenv("RWGT_TUNE_CACHE")) return p;
+  const char* home = std::getenv("HOME");
+  return std::string(home ? home : "/tmp") + "/.rwgt_autotune";
+}
+
+std::string tune_key(const rwgt_batch* b, int nseg, int64_t events) {
+  int lg = 0;
+  while ((int64_t(1) << (lg + 1)) <= events) ++lg;
+  return "gfx950 family=" + std::to_string(b->family) + " prec=" + std::to_string(b->precision) +
+         " nseg=" + std::to_string(nseg) + " log2events=" + std::to_string(lg);
+}
+
+bool tune_lookup(const std::string& key, rwgt::BatchSchedule& out) {
+  std::ifstream in(tune_cache_path());
+  std::string line;
+  while (std::getline(in, line)) {
+    const auto bar = line.find('|');
+    if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+    std::istringstream v(line.substr(bar + 1));
+    rwgt::BatchSchedule s{};
+    if (v >> s.tile_events >> s.block >> s.grid) { out = s; return true; }
+  }
+  return false;
+}
+
+void tune_store(const std::string& key, const rwgt::BatchSchedule& s) {
+  std::ofstream outf(tune_cache_path(), std::ios::app);
+  if (outf) outf << key << "|" << s.tile_events << " " << s.block << " " << s.grid << "\n";
+}
+
+int batch_stage(rwgt_batch* b, const rwgt_segment* segs, int32_t nseg, int& nlive, int64_t& ntiles,
+                int64_t& events) {
+  // host tables: segments with events, two cards each
+  std::vector<rwgt::BatchSeg> hs;
+  std::vector<CardPair> hc;
+  ntiles = 0;
+  events = 0;
+  for (int32_t k = 0; k < nseg; ++k) {
+    const rwgt_segment& s = segs[k];
+    if (s.ctx < 0 || s.ctx >= int32_t(b->ctxs.size())) return b->fail(RWGT_EINVAL, "segment ctx out of range");
+    if (s.nevt < 0) return b->fail(RWGT_EINVAL, "segment nevt < 0");
+    if (!s.params) return b->fail(RWGT_EINVAL, "segment params is NULL");
+    rwgt_ctx* c = b->ctxs[s.ctx];
+    std::vector<CardPair> cards;
+    int rc = build_cards(c, s.params, 1, true, cards);
+    if (rc != RWGT_OK) return b->fail(rc, c->err);
+    if (s.nevt == 0) continue;
+    if (!s.momenta || !s.weights_in || !s.weights_out) return b->fail(RWGT_EINVAL, "segment pointer is NULL");
+    rwgt::BatchSeg d{};
+    d.proc = family_index(c->def->id);
+    d.nevt = s.nevt;
+    d.tile0 = ntiles;
+    d.mom = s.momenta;
+    d.w_in = s.weights_in;
+    d.w_out = s.weights_out;
+    hs.push_back(d);
+    hc.push_back(cards[0]);
+    hc.push_back(cards[1]);
+    ntiles += (s.nevt + b->sched.tile_events - 1) / b->sched.tile_events;
+    events += s.nevt;
+  }
+  nlive = int(hs.size());
+  if (nlive == 0) return RWGT_OK;
+  hipError_t e;
+  if (nlive > b->cap) {
+    if (b->staged_pending) { hipEventSynchronize(b->staged); b->staged_pending = false; }
+    hipStreamSynchronize(b->stream());
+    if (b->dsegs) hipFree(b->dsegs);
+    if (b->dcards) hipFree(b->dcards);
+    if (b->hsegs) hipHostFree(b->hsegs);
+    if (b->hcards) hipHostFree(b->hcards);
+    b->dsegs = nullptr; b->dcards = nullptr; b->hsegs = nullptr; b->hcards = nullptr; b->cap = 0;
+    const int cap = nlive < 64 ? 64 : nlive;
+    if ((e = hipMalloc(&b->dsegs, cap * sizeof(rwgt::BatchSeg))) != hipSuccess) return b->hip_fail(e, "hipMalloc");
+    if ((e = hipMalloc(&b->dcards, 2 * cap * sizeof(CardPair))) != hipSuccess) return b->hip_fail(e, "hipMalloc");
+    if ((e = hipHostMalloc(&b->hsegs, cap * sizeof(rwgt::BatchSeg), hipHostMallocDefault)) != hipSuccess)
+      return b->hip_fail(e, "hipHostMalloc");
+    if ((e = hipHostMalloc(&b->hcards, 2 * cap * sizeof(CardPair), hipHostMallocDefault)) != hipSuccess)
+      return b->hip_fail(e, "hipHostMalloc");
+    b->cap = cap;
+    if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; b->g_nseg = -1; }
+  }
+  if (b->staged_pending) {
+    if ((e = hipEventSynchronize(b->staged)) != hipSuccess) return b->hip_fail(e, "hipEventSynchronize");
+    b->staged_pending = false;
+  }
+  std::memcpy(b->hsegs, hs.data(), hs.size() * sizeof(rwgt::BatchSeg));
+  std::memcpy(b->hcards, hc.data(), hc.size() * sizeof(CardPair));
+  hipStream_t st = b->stream();
+  if ((e = hipMemcpyAsync(b->dsegs, b->hsegs, hs.size() * sizeof(rwgt::BatchSeg), hipMemcpyHostToDevice, st)) !=
+      hipSuccess)
+    return b->hip_fail(e, "hipMemcpyAsync(segments)");
+  if ((e = hipMemcpyAsync(b->dcards, b->hcards, hc.size() * sizeof(CardPair), hipMemcpyHostToDevice, st)) !=
+      hipSuccess)
+    return b->hip_fail(e, "hipMemcpyAsync(cards)");
+  if ((e = hipEventRecord(b->staged, st)) != hipSuccess) return b->hip_fail(e, "hipEventRecord");
+  b->staged_pending = true;
+  return RWGT_OK;
+}
+
+// One launch of the staged tables: replay the captured graph when the launch
+// shape is unchanged, otherwise capture it again.
+int batch_launch(rwgt_batch* b, int nlive, int64_t ntiles) {
+  hipStream_t st = b->stream();
+  hipError_t e;
+  rwgt::BatchSchedule sc = b->sched;
+  if (sc.grid <= 0) sc.grid = 2 * b->ncu;
+  const bool same = b->exec && b->g_nseg == nlive && b->g_ntiles == ntiles && b->g_tile == sc.tile_events &&
+                    b->g_block == sc.block && b->g_grid == sc.grid;
+  if (!same) {
+    if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    hipGraph_t g = nullptr;
+    if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed)) != hipSuccess)
+      return b->hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le = rwgt::launch_batch(b->family, b->precision, b->dsegs, nlive, ntiles, sc, b->dcards, b->counter,
+                                       st);
+    e = hipStreamEndCapture(st, &g);
+    if (le != hipSuccess) { if (g) hipGraphDestroy(g); return b->hip_fail(le, "batch kernel"); }
+    if (e != hipSuccess) return b->hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) { b->exec = nullptr; return b->hip_fail(e, "hipGraphInstantiate"); }
+    b->g_nseg = nlive; b->g_ntiles = ntiles; b->g_tile = sc.tile_events; b->g_block = sc.block; b->g_grid = sc.grid;
+  }
+  hipEventRecord(b->t0, st);
+  if ((e = hipGraphLaunch(b->exec, st)) != hipSuccess) return b->hip_fail(e, "hipGraphLaunch");
+  hipEventRecord(b->t1, st);
+  return RWGT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rwgt_batch_create(rwgt_ctx* const* ctxs, int32_t nctx, rwgt_batch** out) {
+  if (!out) return RWGT_EINVAL;
+  *out = nullptr;
+  if (!ctxs || nctx < 1) return RWGT_EINVAL;
+  for (int32_t i = 0; i < nctx; ++i) {
+    if (!ctxs[i]) return RWGT_EINVAL;
+    if (family_index(ctxs[i]->def->id) < 0) {
+      ctxs[i]->err = "the batched form covers the electroweak family (e+ e- > mu+ mu-, u u~ > e+ e- g)";
+      return RWGT_EPROCESS;
+    }
+    if (ctxs[i]->precision != ctxs[0]->precision) return RWGT_EINVAL;
+  }
+  rwgt_batch* b = new (std::nothrow) rwgt_batch;
+  if (!b) return RWGT_ENOMEM;
+  b->ctxs.assign(ctxs, ctxs + nctx);
+  b->precision = ctxs[0]->precision == RWGT_FP64 ? rwgt::kPrecFP64 : rwgt::kPrecMixedFP16;
+  b->device = ctxs[0]->device;
+  hipError_t e = hipSetDevice(b->device);
+  hipDeviceProp_t prop;
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, b->device);
+  if (e == hipSuccess) b->ncu = prop.multiProcessorCount;
+  if (e == hipSuccess) e = hipStreamCreate(&b->own_stream);
+  if (e == hipSuccess) e = hipMalloc(&b->counter, sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreate(&b->t0);
+  if (e == hipSuccess) e = hipEventCreate(&b->t1);
+  if (e != hipSuccess) { delete b; return e == hipErrorOutOfMemory ? RWGT_ENOMEM : RWGT_EDEVICE; }
+  *out = b;
+  return RWGT_OK;
+}
+
+void rwgt_batch_destroy(rwgt_batch* b) { delete b; }
+
+int rwgt_batch_set_stream(rwgt_batch* b, void* stream) {
+  if (!b) return RWGT_EINVAL;
+  b->user_stream = static_cast<hipStream_t>(stream);
+  if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; b->g_nseg = -1; }
+  return RWGT_OK;
+}
+
+int rwgt_batch_set_schedule(rwgt_batch* b, int32_t tile_events, int32_t block, int32_t blocks_per_cu) {
+  if (!b || tile_events < 1 || block < 64 || block > 256 || block % 64 || blocks_per_cu < 1) return RWGT_EINVAL;
+  b->sched = rwgt::BatchSchedule{tile_events, block, blocks_per_cu * b->ncu};
+  b->tuned = true;
+  return RWGT_OK;
+}
+
+int rwgt_batch_get_schedule(const rwgt_batch* b, int32_t* tile_events, int32_t* block, int32_t* grid) {
+  if (!b || !tile_events || !block || !grid) return RWGT_EINVAL;
+  *tile_events = b->sched.tile_events;
+  *block = b->sched.block;
+  *grid = b->sched.grid > 0 ? b->sched.grid : 2 * b->ncu;
+  return RWGT_OK;
+}
+
+int rwgt_batch_eval(rwgt_batch* b, const rwgt_segment* segs, int32_t nseg) {
+  if (!b) return RWGT_EINVAL;
+  b->err.clear();
+  if (nseg < 0 || (nseg > 0 && !segs)) return b->fail(RWGT_EINVAL, "bad segment list");
+  if (nseg == 0) return RWGT_OK;
+  try {
+    hipError_t e = hipSetDevice(b->device);
+    if (e != hipSuccess) return b->hip_fail(e, "hipSetDevice");
+    if (!b->tuned) {
+      int64_t total = 0;
+      for (int32_t k = 0; k < nseg; ++k) total += segs[k].nevt > 0 ? segs[k].nevt : 0;
+      rwgt::BatchSchedule s{};
+      if (tune_lookup(tune_key(b, nseg, total), s)) b->sched = s;
+      b->tuned = true;
+    }
+    int nlive = 0;
+    int64_t ntiles = 0, events = 0;
+    int rc = batch_stage(b, segs, nseg, nlive, ntiles, events);
+    if (rc != RWGT_OK || nlive == 0) return rc;
+    return batch_launch(b, nlive, ntiles);
+  } catch (const std::exception& ex) {
+    return b->fail(RWGT_ENOMEM, ex.what());
+  }
+}
+
+int rwgt_batch_time(rwgt_batch* b, float* ms) {
+  if (!b || !ms) return RWGT_EINVAL;
+  hipError_t e = hipEventSynchronize(b->t1);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, b->t0, b->t1);
+  if (e != hipSuccess) return b->hip_fail(e, "batch timing");
+  return RWGT_OK;
+}
+
+// Grid search over (tile events, workgroup size, workgroups per CU) on the
+// given segments, timing each candidate with HIP events; the fastest is kept
+// and appended to the tuning cache (RWGT_TUNE_CACHE, default ~/.rwgt_autotune).
+int rwgt_batch_tune(rwgt_batch* b, const rwgt_segment* segs, int32_t nseg, int32_t reps) {
+  if (!b || !segs || nseg < 1) return RWGT_EINVAL;
+  if (reps < 1) reps = 2;
+  static const int tiles[] = {64, 128, 256, 512, 1024, 2048};
+  static const int blocks[] = {64, 128, 256};
+  static const int per_cu[] = {1, 2, 4, 8};
+  float best = 1e30f;
+  rwgt::BatchSchedule best_s = b->sched;
+  int64_t total = 0;
+  for (int32_t k = 0; k < nseg; ++k) total += segs[k].nevt > 0 ? segs[k].nevt : 0;
+  for (int t : tiles)
+    for (int bl : blocks)
+      for (int pc : per_cu) {
+        if (bl > t) continue;
+        b->sched = rwgt::BatchSchedule{t, bl, pc * b->ncu};
+        b->tuned = true;
+        float acc = 0.0f;
+        for (int r = 0; r <= reps; ++r) {
+          int rc = rwgt_batch_eval(b, segs, nseg);
+          if (rc != RWGT_OK) return rc;
+          float ms = 0.0f;
+          rc = rwgt_batch_time(b, &ms);
+          if (rc != RWGT_OK) return rc;
+          if (r > 0) acc += ms;   // the first run captures the graph
+        }
+        if (acc / reps < best) { best = acc / reps; best_s = b->sched; }
+      }
+  b->sched = best_s;
+  b->tuned = true;
+  tune_store(tune_key(b, nseg, total), best_s);
+  return RWGT_OK;
+}
+
+const char* rwgt_batch_last_error(const rwgt_batch* b) { return b ? b->err.c_str() : "batch is NULL"; }
 
 }  // extern "C"

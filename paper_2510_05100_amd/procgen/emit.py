@@ -56,7 +56,7 @@ class Emitter:
         self.cache: Dict[tuple, str] = {}
         self.kcache: Dict[tuple, str] = {}
         self.count = {"ixx": 0, "oxx": 0, "vxx": 0, "ffv_in": 0, "ffv_out": 0, "ffv_vec0": 0,
-                      "ffv_vecm": 0, "vvv_vec": 0, "vvvv_vec": 0, "ffv_amp": 0}
+                      "ffv_vecm": 0, "vvv_vec": 0, "vvvv_vec": 0, "ffv_amp": 0, "pair_w": 0}
         self.n = 0
 
     def new(self, prefix):
@@ -71,19 +71,20 @@ class Emitter:
         return f"K{idx}"
 
     def ksum(self, terms):
-        """Name of sum_i sign_i K_legs (terms: tuple of (sign, leg))."""
+        """Name of sum_i sign_i K_legs (terms: tuple of (sign, leg)), rebuilt
+        from opaque reads of the momenta at every use (see opq)."""
         key = tuple(sorted(terms))
-        if len(key) == 1 and key[0][0] == 1:
-            return self.kleg(key[0][1])
-        if key not in self.kcache:
-            name = self.new("q")
-            parts = []
-            for mu in range(4):
-                e = " ".join(("+ " if s > 0 else "- ") + f"K{l}[{mu}]" for s, l in key)
-                parts.append(e.lstrip("+ ").replace("- ", "-", 1) if e.startswith("- ") else e.lstrip("+ "))
-            self.emit(f"const D {name}[4] = {{{', '.join(parts)}}};")
-            self.kcache[key] = name
-        return self.kcache[key]
+        name = self.new("q")
+        parts = []
+        for mu in range(4):
+            e = ""
+            for s, l in key:
+                sign = s * (1 if self.d.process.legs[l].incoming else -1)
+                e += (" + " if sign > 0 else " - ") + f"opq(P[{l}][{mu}])"
+            e = e[3:] if e.startswith(" + ") else "-" + e[3:]
+            parts.append(e)
+        self.emit(f"const D {name}[4] = {{{', '.join(parts)}}};")
+        return name
 
     # external wavefunctions ---------------------------------------------
     def ext(self, leg: Leg):
@@ -91,14 +92,18 @@ class Emitter:
         if key in self.cache:
             return self.cache[key]
         name = f"w{leg.idx}"
+        # momentum through opaque reads: nothing helicity-independent of the
+        # external state is hoisted out of the helicity loop and kept live
+        p = f"pw{leg.idx}"
+        self.emit(f"const D {p}[4] = {{{', '.join(f'opq(P[{leg.idx}][{mu}])' for mu in range(4))}}};")
         if leg.kind == "V":
-            self.emit(f"const Vec<R> {name} = vxx<R>(P[{leg.idx}], h{leg.idx}, {1 if leg.incoming else -1});")
+            self.emit(f"const Vec<R> {name} = vxx<R>({p}, h{leg.idx}, {1 if leg.incoming else -1});")
             self.count["vxx"] += 1
         elif leg.kind == "F":
-            self.emit(f"const Spinor<R> {name} = ixx<R>(P[{leg.idx}], {_mass(leg.field)}, h{leg.idx}, {_nsf(leg)});")
+            self.emit(f"const Spinor<R> {name} = ixx<R>({p}, {_mass(leg.field)}, h{leg.idx}, {_nsf(leg)});")
             self.count["ixx"] += 1
         else:
-            self.emit(f"const Spinor<R> {name} = oxx<R>(P[{leg.idx}], {_mass(leg.field)}, h{leg.idx}, {_nsf(leg)});")
+            self.emit(f"const Spinor<R> {name} = oxx<R>({p}, {_mass(leg.field)}, h{leg.idx}, {_nsf(leg)});")
             self.count["oxx"] += 1
         self.cache[key] = name
         return name
@@ -147,24 +152,26 @@ class Emitter:
         s = SPECIES[field]
         name = self.new("v")
         if boson == "a":
-            self.emit(f"const Vec<R> {name} = ffv_vec0<R>({fo}, {fi}, cd.aL[{s}], cd.aR[{s}], {q});")
+            self.emit(f"const Vec<R> {name} = ffv_vec0_v<R>({fo}, {fi}, cd.a[{s}], {q});")
             self.count["ffv_vec0"] += 1
         else:
-            self.emit(f"const Vec<R> {name} = ffv_vecm<R>({fo}, {fi}, cd.zL[{s}], cd.zR[{s}], {q}, cd.mz, cd.wz);")
+            self.emit(f"const Vec<R> {name} = ffv_vecm_c<R>({fo}, {fi}, cd.zL[{s}], cd.zR[{s}], {q}, cd.mz, cd.wz);")
             self.count["ffv_vecm"] += 1
         self.cache[key] = name
         return name
 
     def attach(self, blk):
-        """(Vec name, cL, cR) of an attachment on the main line."""
+        """(Vec name, coupling suffix, coupling args) of an attachment on the
+        main line: suffix "v" with one kappa (vector) or "c" with kappa_L,
+        kappa_R (chiral)."""
         s = SPECIES[self.d.main]
         if blk[0] == "glu":
-            return self.gluon(blk[1]), "cd.gqq", "cd.gqq"
+            return self.gluon(blk[1]), "v", "cd.gqq"
         boson, field = blk[1], blk[2]
         v = self.pair(boson, field)
         if boson == "a":
-            return v, f"cd.aL[{s}]", f"cd.aR[{s}]"
-        return v, f"cd.zL[{s}]", f"cd.zR[{s}]"
+            return v, "v", f"cd.a[{s}]"
+        return v, "c", f"cd.zL[{s}], cd.zR[{s}]"
 
     # main-line currents ---------------------------------------------------
     def fcur(self, seq):
@@ -175,11 +182,11 @@ class Emitter:
         if key in self.cache:
             return self.cache[key]
         inner = self.fcur(seq[1:])
-        v, cl, cr = self.attach(seq[0])
+        v, kind, k = self.attach(seq[0])
         legs = [self.d.fleg.idx] + [l for b in seq for l in self.block_legs(b)]
         q = self.ksum(tuple((1, l) for l in legs))
         name = self.new("f")
-        self.emit(f"const Spinor<R> {name} = ffv_in<R>({inner}, {v}, {cl}, {cr}, {q}, {_mass(self.d.main)});")
+        self.emit(f"const Spinor<R> {name} = ffv_in_{kind}<R>({inner}, {v}, {k}, {q}, {_mass(self.d.main)});")
         self.count["ffv_in"] += 1
         self.cache[key] = name
         return name
@@ -192,11 +199,11 @@ class Emitter:
         if key in self.cache:
             return self.cache[key]
         inner = self.bcur(seq[:-1])
-        v, cl, cr = self.attach(seq[-1])
+        v, kind, k = self.attach(seq[-1])
         legs = [self.d.bleg.idx] + [l for b in seq for l in self.block_legs(b)]
         q = self.ksum(tuple((-1, l) for l in legs))
         name = self.new("b")
-        self.emit(f"const Spinor<R> {name} = ffv_out<R>({inner}, {v}, {cl}, {cr}, {q}, {_mass(self.d.main)});")
+        self.emit(f"const Spinor<R> {name} = ffv_out_{kind}<R>({inner}, {v}, {k}, {q}, {_mass(self.d.main)});")
         self.count["ffv_out"] += 1
         self.cache[key] = name
         return name
@@ -210,11 +217,27 @@ class Emitter:
             n += ("F", seq[j:]) not in self.cache
         return n
 
-    def amplitude(self, seq, colour, best):
-        fo = self.bcur(seq[:best])
-        fi = self.fcur(seq[best + 1:])
-        v, cl, cr = self.attach(seq[best])
-        self.emit(f"amp = ffv_amp<R>({fo}, {fi}, {v}, {cl}, {cr});")
+    def wpair(self, bseq, fseq):
+        """W = X + Y of a (row, column) pair shared by several amplitudes."""
+        key = ("W", bseq, fseq)
+        if key in self.cache:
+            return self.cache[key]
+        fo, fi = self.bcur(bseq), self.fcur(fseq)
+        name = self.new("p")
+        self.emit(f"const Vec<R> {name} = pair_w<R>({fo}, {fi});")
+        self.count["pair_w"] += 1
+        self.cache[key] = name
+        return name
+
+    def amplitude(self, seq, colour, best, shared):
+        v, kind, k = self.attach(seq[best])
+        if shared:
+            w = self.wpair(seq[:best], seq[best + 1:])
+            self.emit(f"amp = pair_amp_v<R>({w}, {v}, {k});")
+        else:
+            fo = self.bcur(seq[:best])
+            fi = self.fcur(seq[best + 1:])
+            self.emit(f"amp = ffv_amp_{kind}<R>({fo}, {fi}, {v}, {k});")
         self.count["ffv_amp"] += 1
         for key, c in colour.items():
             idx = self.d.basis.index(key)
@@ -228,6 +251,7 @@ class Emitter:
             else:
                 expr = f"amp * cx<R>{{R({re}), R({im})}}"
             self.emit(f"jamp[{idx}] = jamp[{idx}] + {expr};")
+        self.emit("term_fence();")
 
 
 def colour_matrix_ints(d: Diagrams):
@@ -260,6 +284,10 @@ def node_deps(em: "Emitter", key):
     if kind == "pair":
         sb, sf = d.process.line(key[2])
         return [("ext", sb.idx), ("ext", sf.idx)]
+    if kind == "W":
+        b = ("B", key[1]) if key[1] else ("ext", d.bleg.idx)
+        f = ("F", key[2]) if key[2] else ("ext", d.fleg.idx)
+        return [b, f]
     seq = key[1]
     if kind == "F":
         inner = ("F", seq[1:]) if len(seq) > 1 else ("ext", d.fleg.idx)
@@ -275,33 +303,69 @@ def attach_key(blk):
     return ("pair", blk[1], blk[2])
 
 
+def _vector_middle(blk):
+    return blk[0] == "glu" or blk[1] == "a"
+
+
 def plan_splits(d: Diagrams):
-    """Split point per amplitude term, chosen greedily to reuse main-line
-    currents (fewest new B/F currents, then nearest the middle)."""
-    have = set()
-    splits = []
+    """Split point per amplitude term and whether its (row, column) pair is
+    shared.  First, pairs (Bcur(A_1..A_{m-1}), Fcur(A_{m+1}..)) that several
+    terms with a vector-coupled middle attachment can use are taken, most
+    popular first: each such term then costs one four-component dot product.
+    The other terms pick the split that builds the fewest new main-line
+    currents, then the one nearest the middle."""
+    from collections import Counter
+    options = []
+    counts = Counter()
     for seq, _ in d.terms:
+        opts = {}
+        for m in range(len(seq)):
+            if _vector_middle(seq[m]):
+                opts[(seq[:m], seq[m + 1:])] = m
+        options.append(opts)
+        counts.update(opts.keys())
+    splits = [None] * len(d.terms)
+    shared = [False] * len(d.terms)
+    for key, c in counts.most_common():
+        if c < 2:
+            break
+        users = [t for t in range(len(d.terms)) if splits[t] is None and key in options[t]]
+        if len(users) < 2:
+            continue
+        for t in users:
+            splits[t] = options[t][key]
+            shared[t] = True
+    have = set()
+    for t, (seq, _) in enumerate(d.terms):
+        if splits[t] is None:
+            continue
+        m = splits[t]
+        have.update(("B", seq[:j]) for j in range(1, m + 1))
+        have.update(("F", seq[j:]) for j in range(m + 1, len(seq)))
+    for t, (seq, _) in enumerate(d.terms):
+        if splits[t] is not None:
+            continue
         k = len(seq)
 
         def missing(m):
             n = sum(("B", seq[:j]) not in have for j in range(1, m + 1))
             return n + sum(("F", seq[j:]) not in have for j in range(m + 1, k))
         m = min(range(k), key=lambda m: (missing(m), abs(m - (k - 1) / 2)))
-        for j in range(1, m + 1):
-            have.add(("B", seq[:j]))
-        for j in range(m + 1, k):
-            have.add(("F", seq[j:]))
-        splits.append(m)
-    return splits
+        have.update(("B", seq[:j]) for j in range(1, m + 1))
+        have.update(("F", seq[j:]) for j in range(m + 1, k))
+        splits[t] = m
+    return splits, shared
 
 
-def term_roots(d: Diagrams, seq, m):
+def term_roots(d: Diagrams, seq, m, shared=False):
+    if shared:
+        return [("W", seq[:m], seq[m + 1:]), attach_key(seq[m])]
     b = ("B", seq[:m]) if m > 0 else ("ext", d.bleg.idx)
     f = ("F", seq[m + 1:]) if m + 1 < len(seq) else ("ext", d.fleg.idx)
     return [b, f, attach_key(seq[m])]
 
 
-def schedule(em: "Emitter", splits):
+def schedule(em: "Emitter", splits, shared):
     """Order amplitude terms to keep few currents live: repeatedly take the
     term that adds the least live data net of what it lets die."""
     d = em.d
@@ -316,9 +380,9 @@ def schedule(em: "Emitter", splits):
         return closure[key]
 
     term_nodes = []
-    for (seq, _), m in zip(d.terms, splits):
+    for (seq, _), m, sh in zip(d.terms, splits, shared):
         s = set()
-        for r in term_roots(d, seq, m):
+        for r in term_roots(d, seq, m, sh):
             s |= clos(r)
         term_nodes.append(frozenset(s))
     uses = {}
@@ -344,7 +408,61 @@ def schedule(em: "Emitter", splits):
         computed |= term_nodes[best]
         for n in term_nodes[best]:
             uses[n] -= 1
-    return order
+    return refine_order(order, term_nodes)
+
+
+def _live_profile(order, tn):
+    """(peak, sum) of the number of currents live after each term, a current
+    being live from the first to the last term that needs it."""
+    first, last = {}, {}
+    for pos, t in enumerate(order):
+        for n in tn[t]:
+            if n not in first:
+                first[n] = pos
+            last[n] = pos
+    delta = [0] * (len(order) + 1)
+    for n, f in first.items():
+        delta[f] += 1
+        delta[last[n] + 1] -= 1
+    cur = peak = total = 0
+    for pos in range(len(order)):
+        cur += delta[pos]
+        peak = max(peak, cur)
+        total += cur
+    return peak, total
+
+
+def refine_order(order, term_nodes, iters=30000, seed=20251005):
+    """Seeded simulated annealing on the term order (moves: take one term out
+    and insert it elsewhere), minimising the peak number of live currents and
+    then their average."""
+    import math
+    import random
+    if len(order) < 8:
+        return order
+    ids = {}
+    tn = [[ids.setdefault(n, len(ids)) for n in s] for s in term_nodes]
+    rng = random.Random(seed)
+
+    def cost(o):
+        p, s = _live_profile(o, tn)
+        return p * 10000 + s / len(o)
+    cur = list(order)
+    c_cur = cost(cur)
+    best, c_best = list(cur), c_cur
+    for it in range(iters):
+        temp = 2000.0 * (1.0 - it / iters) + 1e-3
+        i, j = rng.randrange(len(cur)), rng.randrange(len(cur))
+        if i == j:
+            continue
+        cand = list(cur)
+        cand.insert(j, cand.pop(i))
+        c = cost(cand)
+        if c <= c_cur or rng.random() < math.exp((c_cur - c) / temp):
+            cur, c_cur = cand, c
+            if c < c_best:
+                best, c_best = list(cand), c
+    return best
 
 
 def generate(d: Diagrams) -> str:
@@ -352,10 +470,10 @@ def generate(d: Diagrams) -> str:
     legs = d.process.legs
     n = len(legs)
     em = Emitter(d)
-    splits = plan_splits(d)
-    for t in schedule(em, splits):
+    splits, shared = plan_splits(d)
+    for t in schedule(em, splits, shared):
         seq, colour = d.terms[t]
-        em.amplitude(seq, colour, splits[t])
+        em.amplitude(seq, colour, splits[t], shared[t])
     body = em.lines
     num, den = colour_matrix_ints(d)
     good = good_helicities(d)
@@ -379,7 +497,7 @@ def generate(d: Diagrams) -> str:
     out.append(f"constexpr int NAMP = {len(d.terms)};")
     out.append(f"constexpr double AVERAGE = {d.process.average!r};")
     out.append(f"constexpr int CDEN = {den};")
-    out.append(f"__constant__ int GOOD[NGOOD] = {{{', '.join(map(str, good))}}};")
+    out.append(f"static __constant__ int GOOD[NGOOD] = {{{', '.join(map(str, good))}}};")
     out.append(f"constexpr int GOOD_HOST[NGOOD] = {{{', '.join(map(str, good))}}};")
     out.append("constexpr int CNUM[NCOL][NCOL] = {")
     for row in num:
@@ -391,11 +509,9 @@ def generate(d: Diagrams) -> str:
     out.append("")
     out.append("// D is the momentum type: double on the device; an operation-counting")
     out.append("// type when the host instantiates this to count arithmetic.")
-    out.append("template <class R, class D>")
-    out.append(f"__host__ __device__ __forceinline__ void jamps(const D (&P)[{n}][4], int hel, const Card<R, D>& cd, cx<R> (&jamp)[NCOL]) {{")
-    for i, l in enumerate(legs):
-        sign = "" if l.incoming else "-"
-        out.append(f"  const D K{i}[4] = {{{', '.join(f'{sign}P[{i}][{mu}]' for mu in range(4))}}};")
+    out.append("// J indexes like cx<R>[NCOL]: a register array, or an accessor into LDS.")
+    out.append("template <class R, class D, class J>")
+    out.append(f"__host__ __device__ __forceinline__ void jamps(const D (&P)[{n}][4], int hel, const Card<R, D>& cd, J& jamp) {{")
     for i in range(n):
         out.append(f"  const int h{i} = ((hel >> {n - 1 - i}) & 1) ? 1 : -1;")
     out.append("  for (int c = 0; c < NCOL; ++c) jamp[c] = cx<R>{R(0), R(0)};")
@@ -404,8 +520,8 @@ def generate(d: Diagrams) -> str:
     out.append("}")
     out.append("")
     # colour sum: J^dagger C J = sum_i J_i^* (C J)_i, C real symmetric
-    out.append("template <class R>")
-    out.append("__host__ __device__ __forceinline__ R colour_sum(const cx<R> (&jamp)[NCOL]) {")
+    out.append("template <class R, class J>")
+    out.append("__host__ __device__ __forceinline__ R colour_sum(const J& jamp) {")
     out.append("  R me = R(0);")
     for i in range(ncol):
         tr = [f"R({num[i][i]}) * jamp[{i}].re"] + [f"R({2 * num[i][j]}) * jamp[{j}].re" for j in range(i + 1, ncol) if num[i][j]]
