@@ -38,8 +38,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--events", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=200)
+    ap.add_argument("--cpu-sample", type=int, default=2000)
     ap.add_argument("--modes", default="fp64,mixed")
+    ap.add_argument("--no-batched", action="store_true")
     return ap.parse_args()
 
 
@@ -94,6 +95,66 @@ def cpu_baseline(p, sample, gpu_w):
             "gpu_vs_oracle_max_rel_err": parity}
 
 
+def batched_leg(rw, torch, precision, steps, warmup):
+    """Config-3 style mix: 64 cards on the (M_Z, Gamma_Z, sin^2 theta_W) grid,
+    each reweighting the first n events of a 2e5-event pool of e+e- -> mu+mu-
+    and of u u~ -> e+e- g (n log-uniform in [1e3, 2e5], seeded): one tuned,
+    graph-captured persistent launch against 128 separate rwgt_eval calls."""
+    import synth
+    grid = synth.batch_grid()
+    counts = synth.batch_counts()
+    procs = ("ee_mumu", "uu_eeg")
+    texts = {"ee_mumu": "e+ e- > mu+ mu-", "uu_eeg": "u u~ > e+ e- g"}
+    pools = {p: torch.as_tensor(synth.events(p, 200_000)).cuda() for p in procs}
+    ones = torch.ones(200_000, dtype=torch.float64, device="cuda")
+    ctxs = [rw.rwgt_create(texts[p], synth.ORIG_EW.slha(), precision) for p in procs]
+    items, plain_out = [], []
+    for c, card in enumerate(grid):
+        for j, p in enumerate(procs):
+            n = int(counts[c, j])
+            items.append((j, pools[p][:n], ones[:n], card.row(p), torch.empty(n, dtype=torch.float64, device="cuda")))
+            plain_out.append(torch.empty((1, n), dtype=torch.float64, device="cuda"))
+    total = int(counts.sum())
+    b = rw.rwgt_batch_create(ctxs)
+    segs, keep = rw.make_segments(items)
+    t = time.perf_counter()
+    sched = rw.rwgt_batch_tune(b, segs, reps=2)
+    tune_s = time.perf_counter() - t
+    for _ in range(warmup):
+        rw.rwgt_batch_eval(b, segs)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    kernel_ms = []
+    for _ in range(steps):
+        rw.rwgt_batch_eval(b, segs)
+        kernel_ms.append(rw.rwgt_batch_time(b))
+    torch.cuda.synchronize()
+    batched_ms = (time.perf_counter() - t) / steps * 1e3
+    for ctx in ctxs:
+        rw.rwgt_set_stream(ctx, None)
+
+    def plain():
+        for (j, mom, w, row, _), out in zip(items, plain_out):
+            rw.rwgt_eval(ctxs[j], mom, w, row, out)
+    for _ in range(warmup):
+        plain()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        plain()
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t) / steps * 1e3
+    diff = max(float(torch.max(torch.abs(it[4] - po[0]) / torch.abs(po[0])).item()) for it, po in zip(items, plain_out))
+    rw.rwgt_batch_destroy(b)
+    for ctx in ctxs:
+        rw.rwgt_destroy(ctx)
+    return {"events": total, "segments": len(items), "batched_ms": batched_ms,
+            "batched_kernel_ms": float(np.mean(kernel_ms)), "plain_ms": plain_ms,
+            "batched_value": total / (batched_ms * 1e-3), "plain_value": total / (plain_ms * 1e-3),
+            "speedup": plain_ms / batched_ms, "schedule": sched, "tune_seconds": tune_s,
+            "max_rel_diff_vs_plain": diff, "unit": "reweighted events/s"}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -146,6 +207,12 @@ def main():
         line["mixed"] = {"value": a.events * nsets / (x["ms_per_step"] * 1e-3), "ms_per_step": x["ms_per_step"],
                          "max_rel_err": x["max_rel_err"], "dtype": "f32 amplitudes, f64 momenta/denominators/ratio",
                          "roofline": roofline(x, PEAK_FP32_VALU_UNPACKED)}
+    if not a.no_batched:
+        line["batched"] = {}
+        for mode, prec in (("fp64", rw.RWGT_FP64), ("mixed", rw.RWGT_MIXED_FP16)):
+            line["batched"][mode] = batched_leg(rw, torch, prec, steps=5, warmup=2)
+            log(f"batched {mode}: {line['batched'][mode]['batched_ms']:.2f} ms vs plain "
+                f"{line['batched'][mode]['plain_ms']:.2f} ms")
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, a.cpu_sample, m["w"])
     print(json.dumps(line), flush=True)
