@@ -163,6 +163,69 @@ int rwgt_batch_get_schedule(const rwgt_batch *batch, int32_t *tile_events, int32
 int rwgt_batch_tune(rwgt_batch *batch, const rwgt_segment *segments, int32_t nsegments, int32_t reps);
 const char *rwgt_batch_last_error(const rwgt_batch *batch);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate: a multilayer perceptron for log(w'/w) with a second
+ * head for the log of its own error, trained and run by the library's own
+ * kernels (BF16 operands on the matrix cores with FP32 accumulation, or FP32
+ * operands on the VALU for gradient checks; FP32 master weights and Adam).
+ * The input row of one (event, card) pair is [momenta (npart*4), card
+ * parameters (nparam)], standardised with the mean and standard deviation set
+ * by rwgt_mlp_set_normalisation.  Hidden layers use SiLU.  The loss per row is
+ *   1/2 (y - mu)^2 + lambda (1/2 r^2 exp(-2 s) + s),  r = y - mu held fixed,
+ * mu = head 0, s = head 1 (clamped at -15).  Device pointers unless noted;
+ * calls enqueue on the network's stream (rwgt_mlp_set_stream).
+ */
+typedef struct rwgt_mlp rwgt_mlp;
+
+enum { RWGT_MLP_BF16 = 0, RWGT_MLP_FP32 = 1 };
+
+/* n_in inputs, depth hidden layers of width (multiple of 32), n_out heads
+ * (2..32); He-uniform initial weights from seed (last layer scaled by 0.1),
+ * zero biases.  Errors: RWGT_EINVAL, RWGT_EDEVICE, RWGT_ENOMEM. */
+int rwgt_mlp_create(int32_t n_in, int32_t width, int32_t depth, int32_t n_out, int32_t precision, uint64_t seed,
+                    rwgt_mlp **out);
+void rwgt_mlp_destroy(rwgt_mlp *mlp);
+int rwgt_mlp_set_stream(rwgt_mlp *mlp, void *stream);
+/* Number of parameters; get/set pack them (HOST float array) layer by layer as
+ * W[out][in] row-major then b[out]; get_grads packs the last gradients. */
+int rwgt_mlp_num_params(const rwgt_mlp *mlp, int64_t *n);
+int rwgt_mlp_get_params(rwgt_mlp *mlp, float *host);
+int rwgt_mlp_set_params(rwgt_mlp *mlp, const float *host);
+int rwgt_mlp_get_grads(rwgt_mlp *mlp, float *host);
+/* HOST arrays of n_in floats. */
+int rwgt_mlp_set_normalisation(rwgt_mlp *mlp, const float *mean, const float *stdv);
+/* Loss weight lambda of the error head and the Adam constants. */
+int rwgt_mlp_set_training(rwgt_mlp *mlp, float lambda, float beta1, float beta2, float eps);
+/* Quantile factor k: the error bound of a prediction is k exp(s). */
+int rwgt_mlp_set_calibration(rwgt_mlp *mlp, float k);
+/* Bytes of the input buffer for n rows (rows are padded to a multiple of 64). */
+int rwgt_mlp_input_bytes(const rwgt_mlp *mlp, int64_t n, int64_t *bytes);
+/* Input rows: row r = [momenta[event_index[r]] (npart*4 doubles; event_index
+ * NULL: r), card_params[card_index[r]] (nparam floats)], standardised. */
+int rwgt_mlp_features(rwgt_mlp *mlp, const double *momenta, int32_t npart, const int32_t *event_index,
+                      const int32_t *card_index, const float *card_params, int32_t nparam, int64_t n, void *x_out);
+/* Heads of n rows into heads_out [n][32] (FP32; head 0 = mu, 1 = s). */
+int rwgt_mlp_forward(rwgt_mlp *mlp, const void *x, int64_t n, float *heads_out);
+/* Forward, loss, backward and (lr > 0) one Adam step on n rows with targets y
+ * [n] (FP32); the summed loss goes to loss_out (device float) if non-NULL. */
+int rwgt_mlp_train_step(rwgt_mlp *mlp, const void *x, const float *y, int64_t n, float lr, float *loss_out);
+/* Training targets y[i] = log(w_new[i] / w_old[i]) (w_old NULL: 1; w_old = 0: y = 0). */
+int rwgt_mlp_targets(rwgt_mlp *mlp, const double *w_new, const double *w_old, int64_t n, float *y);
+const char *rwgt_mlp_last_error(const rwgt_mlp *mlp);
+
+/* Reweighting through the surrogate with exact fallback (same result
+ * definition as rwgt_eval): event i gets card card_index[i] (DEVICE int32) of
+ * param_table (HOST [ncards][npar], the context's layout); where the predicted
+ * error k exp(s) of log(w'/w) is at most err_threshold,
+ * w'_i = w_i exp(mu_i); elsewhere w'_i is computed exactly by the
+ * matrix-element path.  The network's inputs are the momenta and the card's
+ * (M_Z, Gamma_Z, sin^2 theta_W).  *n_fallback (HOST, optional; waits for the
+ * call) receives the number of exact evaluations.  Processes of the
+ * electroweak family. */
+int rwgt_sur_eval(rwgt_ctx *ctx, rwgt_mlp *mlp, const double *momenta, int64_t nevt, const double *weights_in,
+                  const double *param_table, int32_t ncards, const int32_t *card_index, double err_threshold,
+                  double *weights_out, int64_t *n_fallback);
+
 #ifdef __cplusplus
 }
 #endif

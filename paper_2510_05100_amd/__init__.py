@@ -5,6 +5,12 @@ The compute path lives in librwgt.so (HIP kernels for gfx950 behind the C ABI
 of include/rwgt.h); this package only marshals arguments to it.
 """
 from ._abi import (  # noqa: F401
+    RWGT_MLP_BF16, RWGT_MLP_FP32, rwgt_mlp_create, rwgt_mlp_destroy, rwgt_mlp_features, rwgt_mlp_forward,
+    rwgt_mlp_get_grads, rwgt_mlp_get_params, rwgt_mlp_input_bytes, rwgt_mlp_num_params, rwgt_mlp_set_calibration,
+    rwgt_mlp_set_normalisation, rwgt_mlp_set_params, rwgt_mlp_set_stream, rwgt_mlp_set_training, rwgt_mlp_targets,
+    rwgt_mlp_train_step, rwgt_sur_eval,
+)
+from ._abi import (  # noqa: F401
     Segment, make_segments, rwgt_batch_create, rwgt_batch_destroy, rwgt_batch_eval, rwgt_batch_get_schedule,
     rwgt_batch_set_schedule, rwgt_batch_set_stream, rwgt_batch_time, rwgt_batch_tune,
 )

@@ -59,6 +59,34 @@ SIGNATURES.update({
     "rwgt_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
 })
 
+SIGNATURES.update({
+    "rwgt_mlp_create": (ctypes.c_int, [ctypes.c_int32] * 5 + [ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p)]),
+    "rwgt_mlp_destroy": (None, [ctypes.c_void_p]),
+    "rwgt_mlp_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rwgt_mlp_num_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "rwgt_mlp_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
+    "rwgt_mlp_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
+    "rwgt_mlp_get_grads": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
+    "rwgt_mlp_set_normalisation": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
+                                                  ctypes.POINTER(ctypes.c_float)]),
+    "rwgt_mlp_set_training": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_float] * 4),
+    "rwgt_mlp_set_calibration": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_float]),
+    "rwgt_mlp_input_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    "rwgt_mlp_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                          ctypes.c_void_p]),
+    "rwgt_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "rwgt_mlp_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                            ctypes.c_float, ctypes.c_void_p]),
+    "rwgt_mlp_targets": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.c_void_p]),
+    "rwgt_mlp_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "rwgt_sur_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_int64)]),
+})
+
 _lib = None
 
 
@@ -297,3 +325,142 @@ def rwgt_batch_tune(batch, segments, reps=2):
     if rc != 0:
         _braise(rc, batch)
     return rwgt_batch_get_schedule(batch)
+
+
+# ------------------------------------------------------------------ surrogate
+RWGT_MLP_BF16, RWGT_MLP_FP32 = 0, 1
+
+
+def _mraise(code, mlp):
+    raise RwgtError(code, (load().rwgt_mlp_last_error(mlp) or b"").decode())
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def rwgt_mlp_create(n_in, width, depth, n_out=2, precision=RWGT_MLP_BF16, seed=0):
+    out = ctypes.c_void_p()
+    rc = load().rwgt_mlp_create(n_in, width, depth, n_out, precision, seed, ctypes.byref(out))
+    if rc != 0:
+        raise RwgtError(rc, "rwgt_mlp_create failed")
+    return out
+
+
+def rwgt_mlp_destroy(mlp):
+    if mlp:
+        load().rwgt_mlp_destroy(mlp)
+
+
+def rwgt_mlp_set_stream(mlp, stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    rc = load().rwgt_mlp_set_stream(mlp, ctypes.c_void_p(handle))
+    if rc != 0:
+        _mraise(rc, mlp)
+
+
+def rwgt_mlp_num_params(mlp):
+    n = ctypes.c_int64()
+    rc = load().rwgt_mlp_num_params(mlp, ctypes.byref(n))
+    if rc != 0:
+        _mraise(rc, mlp)
+    return n.value
+
+
+def rwgt_mlp_get_params(mlp):
+    out = np.zeros(rwgt_mlp_num_params(mlp), dtype=np.float32)
+    rc = load().rwgt_mlp_get_params(mlp, _fptr(out))
+    if rc != 0:
+        _mraise(rc, mlp)
+    return out
+
+
+def rwgt_mlp_set_params(mlp, flat):
+    a = np.ascontiguousarray(flat, dtype=np.float32)
+    rc = load().rwgt_mlp_set_params(mlp, _fptr(a))
+    if rc != 0:
+        _mraise(rc, mlp)
+
+
+def rwgt_mlp_get_grads(mlp):
+    out = np.zeros(rwgt_mlp_num_params(mlp), dtype=np.float32)
+    rc = load().rwgt_mlp_get_grads(mlp, _fptr(out))
+    if rc != 0:
+        _mraise(rc, mlp)
+    return out
+
+
+def rwgt_mlp_set_normalisation(mlp, mean, std):
+    m = np.ascontiguousarray(mean, dtype=np.float32)
+    s = np.ascontiguousarray(std, dtype=np.float32)
+    rc = load().rwgt_mlp_set_normalisation(mlp, _fptr(m), _fptr(s))
+    if rc != 0:
+        _mraise(rc, mlp)
+
+
+def rwgt_mlp_set_training(mlp, lam=0.1, beta1=0.9, beta2=0.999, eps=1e-8):
+    rc = load().rwgt_mlp_set_training(mlp, lam, beta1, beta2, eps)
+    if rc != 0:
+        _mraise(rc, mlp)
+
+
+def rwgt_mlp_set_calibration(mlp, k):
+    rc = load().rwgt_mlp_set_calibration(mlp, float(k))
+    if rc != 0:
+        _mraise(rc, mlp)
+
+
+def rwgt_mlp_input_bytes(mlp, n):
+    b = ctypes.c_int64()
+    rc = load().rwgt_mlp_input_bytes(mlp, int(n), ctypes.byref(b))
+    if rc != 0:
+        _mraise(rc, mlp)
+    return b.value
+
+
+def _dp(t):
+    return ctypes.c_void_p(0) if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def rwgt_mlp_features(mlp, momenta, event_index, card_index, card_params, n, x_out):
+    """momenta: [nev, npart, 4] f64; event_index/card_index: int32 [n] (event_index may be None);
+    card_params: f32 [ncards, nparam]; x_out: device buffer (uint8 tensor of rwgt_mlp_input_bytes)."""
+    rc = load().rwgt_mlp_features(mlp, _dp(momenta), momenta.shape[1], _dp(event_index), _dp(card_index),
+                                  _dp(card_params), card_params.shape[1], int(n), _dp(x_out))
+    if rc != 0:
+        _mraise(rc, mlp)
+
+
+def rwgt_mlp_forward(mlp, x, n, heads_out=None):
+    rc = load().rwgt_mlp_forward(mlp, _dp(x), int(n), _dp(heads_out))
+    if rc != 0:
+        _mraise(rc, mlp)
+
+
+def rwgt_mlp_train_step(mlp, x, y, n, lr, loss_out=None):
+    rc = load().rwgt_mlp_train_step(mlp, _dp(x), _dp(y), int(n), float(lr), _dp(loss_out))
+    if rc != 0:
+        _mraise(rc, mlp)
+
+
+def rwgt_mlp_targets(mlp, w_new, w_old, y):
+    rc = load().rwgt_mlp_targets(mlp, _dp(w_new), _dp(w_old), int(w_new.numel()), _dp(y))
+    if rc != 0:
+        _mraise(rc, mlp)
+
+
+def rwgt_sur_eval(ctx, mlp, momenta, weights_in, param_table, card_index, err_threshold, weights_out):
+    """Returns the number of events that took the exact path."""
+    _check_device(momenta, "momenta")
+    _check_device(weights_in, "weights_in")
+    _check_device(weights_out, "weights_out")
+    table, tptr = _host_params(param_table)
+    nfb = ctypes.c_int64()
+    rc = load().rwgt_sur_eval(ctx, mlp, _dp(momenta), momenta.shape[0], _dp(weights_in), tptr, table.shape[0],
+                              _dp(card_index), float(err_threshold), _dp(weights_out), ctypes.byref(nfb))
+    if rc != 0:
+        _raise(rc, ctx)
+    return nfb.value

@@ -29,6 +29,11 @@ namespace rwgt {
       gen_##NAME::jamps<R, double>(P, hel, cd, j);                                             \
     }                                                                                          \
     template <class R, class J>                                                                \
+    static __device__ __forceinline__ void jamps_grouped(const double (&P)[NPART][4], int hel, \
+                                                         const Card<R>& cd, J& j) {            \
+      gen_##NAME::jamps_grouped<R, double>(P, hel, cd, j);                                     \
+    }                                                                                          \
+    template <class R, class J>                                                                \
     static __device__ __forceinline__ R colour_sum(const J& j) {                               \
       return gen_##NAME::colour_sum<R>(j);                                                     \
     }                                                                                          \
@@ -105,7 +110,7 @@ __global__ __launch_bounds__(kMeBlock) void me_kernel(const double* __restrict__
       // none of the helicity-independent algebra is hoisted out of this loop.
       if constexpr (jamp_in_lds<PROC, R>()) {
         LdsJamp<R, PROC::NCOL> jamp{lds_jamp + threadIdx.x};
-        PROC::template jamps<R>(P, PROC::good(ih), cd, jamp);
+        PROC::template jamps_grouped<R>(P, PROC::good(ih), cd, jamp);
         me += double(PROC::template colour_sum<R>(jamp));
       } else {
         cx<R> jamp[PROC::NCOL];

@@ -19,6 +19,8 @@
 #include "../../include/rwgt.h"
 #include "batch.h"
 #include "kernels.h"
+#include "mlp.h"
+#include "mlp_internal.h"
 
 using rwgt::Card;
 using rwgt::CardPair;
@@ -157,6 +159,15 @@ struct rwgt_ctx {
   bool upload_pending = false;
   bool profiling = false;
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // before ingest, after ingest, after ME
+  // surrogate path workspace
+  void* sur_x = nullptr;
+  int32_t* sur_list = nullptr;
+  unsigned int* sur_count = nullptr;
+  float* sur_heads = nullptr;
+  CardPair* sur_cards = nullptr;
+  float* sur_cpar = nullptr;
+  int64_t sur_cap = 0;
+  int sur_card_cap = 0;
   std::string err;
 
   int fail(int code, const std::string& msg) {
@@ -175,6 +186,9 @@ struct rwgt_ctx {
     if (soa) hipFree(soa);
     if (dcards) hipFree(dcards);
     if (hcards) hipHostFree(hcards);
+    for (void* p : {sur_x, static_cast<void*>(sur_list), static_cast<void*>(sur_count), static_cast<void*>(sur_heads),
+                    static_cast<void*>(sur_cards), static_cast<void*>(sur_cpar)})
+      if (p) hipFree(p);
   }
 };
 
@@ -710,5 +724,92 @@ int rwgt_batch_tune(rwgt_batch* b, const rwgt_segment* segs, int32_t nseg, int32
 }
 
 const char* rwgt_batch_last_error(const rwgt_batch* b) { return b ? b->err.c_str() : "batch is NULL"; }
+
+int rwgt_sur_eval(rwgt_ctx* c, rwgt_mlp* m, const double* momenta, int64_t nevt, const double* w_in,
+                  const double* param_table, int32_t ncards, const int32_t* card_index, double threshold,
+                  double* w_out, int64_t* n_fallback) {
+  if (!c || !m) return RWGT_EINVAL;
+  c->err.clear();
+  if (n_fallback) *n_fallback = 0;
+  if (nevt < 0 || ncards < 1 || !param_table) return c->fail(RWGT_EINVAL, "bad sizes or NULL param_table");
+  const int proc = family_index(c->def->id);
+  if (proc < 0) return c->fail(RWGT_EPROCESS, "the surrogate path covers the electroweak family");
+  constexpr int kNparam = 3;                                 // M_Z, Gamma_Z, sin^2 theta_W
+  if (m->n_in != c->def->npart * 4 + kNparam) return c->fail(RWGT_EINVAL, "network input width mismatch");
+  if (nevt == 0) return RWGT_OK;
+  if (!momenta || !w_in || !w_out || !card_index) return c->fail(RWGT_EINVAL, "NULL device pointer");
+  try {
+    // cards: original, then the table; network inputs per card
+    std::vector<CardPair> cards;
+    int rc = build_cards(c, param_table, ncards, true, cards);
+    if (rc != RWGT_OK) return rc;
+    const auto& layout = c->def->layout;
+    auto col = [&](const char* name) {
+      for (size_t j = 0; j < layout.size(); ++j)
+        if (layout[j] == name) return int(j);
+      return -1;
+    };
+    const int jm = col("MASS 23"), jw = col("DECAY 23"), js = col("RWGTEW 1");
+    std::vector<float> cpar(size_t(ncards) * kNparam);
+    for (int k = 0; k < ncards; ++k) {
+      const double* row = param_table + size_t(k) * layout.size();
+      cpar[k * kNparam + 0] = float(row[jm]);
+      cpar[k * kNparam + 1] = float(row[jw]);
+      cpar[k * kNparam + 2] = float(row[js]);
+    }
+    hipError_t e = hipSetDevice(c->device);
+    hipStream_t st = c->stream;
+    const int64_t rows = (nevt + 63) / 64 * 64;
+    if (e == hipSuccess && (rows > c->sur_cap || ncards + 1 > c->sur_card_cap)) {
+      hipStreamSynchronize(st);
+      for (void* p : {c->sur_x, static_cast<void*>(c->sur_list), static_cast<void*>(c->sur_count),
+                      static_cast<void*>(c->sur_heads), static_cast<void*>(c->sur_cards), static_cast<void*>(c->sur_cpar)})
+        if (p) hipFree(p);
+      c->sur_x = nullptr; c->sur_list = nullptr; c->sur_count = nullptr; c->sur_heads = nullptr;
+      c->sur_cards = nullptr; c->sur_cpar = nullptr; c->sur_cap = 0; c->sur_card_cap = 0;
+      int64_t xbytes = 0;
+      rwgt_mlp_input_bytes(m, rows, &xbytes);
+      const int cc = ncards + 1 < 64 ? 64 : ncards + 1;
+      e = hipMalloc(&c->sur_x, size_t(xbytes));
+      if (e == hipSuccess) e = hipMalloc(&c->sur_list, size_t(rows) * 4);
+      if (e == hipSuccess) e = hipMalloc(&c->sur_count, 4);
+      if (e == hipSuccess) e = hipMalloc(&c->sur_heads, size_t(rows) * 32 * 4);
+      if (e == hipSuccess) e = hipMalloc(&c->sur_cards, size_t(cc) * sizeof(CardPair));
+      if (e == hipSuccess) e = hipMalloc(&c->sur_cpar, size_t(cc) * kNparam * 4);
+      if (e == hipSuccess) { c->sur_cap = rows; c->sur_card_cap = cc; }
+    }
+    if (e != hipSuccess) return c->hip_fail(e, "surrogate workspace");
+    // small tables: synchronous copies (pageable host memory)
+    e = hipMemcpyAsync(c->sur_cards, cards.data(), cards.size() * sizeof(CardPair), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->sur_cpar, cpar.data(), cpar.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return c->hip_fail(e, "surrogate tables");
+    rwgt_mlp_set_stream(m, st);
+    rc = rwgt_mlp_features(m, momenta, c->def->npart, nullptr, card_index, c->sur_cpar, kNparam, nevt, c->sur_x);
+    if (rc == RWGT_OK) rc = rwgt_mlp_forward(m, c->sur_x, nevt, nullptr);
+    if (rc != RWGT_OK) return c->fail(rc, m->err);
+    e = rwgt::mlp_gate(m->z.back(), 32, nevt, m->k_cal, float(threshold), w_in, w_out, c->sur_list, c->sur_count, st);
+    if (e == hipSuccess) {
+      int ncu = 256;
+      hipDeviceProp_t prop;
+      if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) ncu = prop.multiProcessorCount;
+      e = rwgt::launch_exact_list(rwgt::kFamilyElectroweak, c->precision == RWGT_FP64 ? rwgt::kPrecFP64 : rwgt::kPrecMixedFP16,
+                                  proc, momenta, c->sur_list, c->sur_count, card_index, c->sur_cards, w_in, w_out,
+                                  4 * ncu, st);
+    }
+    if (e != hipSuccess) return c->hip_fail(e, "surrogate gate / exact fallback");
+    if (n_fallback) {
+      unsigned int cnt = 0;
+      e = hipMemcpyAsync(&cnt, c->sur_count, 4, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return c->hip_fail(e, "fallback count");
+      *n_fallback = cnt;
+    }
+    return RWGT_OK;
+  } catch (const std::exception& ex) {
+    return c->fail(RWGT_ENOMEM, ex.what());
+  }
+}
 
 }  // extern "C"

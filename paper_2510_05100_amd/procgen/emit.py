@@ -465,16 +465,39 @@ def refine_order(order, term_nodes, iters=30000, seed=20251005):
     return best
 
 
-def generate(d: Diagrams) -> str:
+# Groups of amplitude terms per helicity.  Between groups every current is
+# forgotten and rebuilt on demand (from opaque momentum reads, so nothing is
+# carried across): fewer currents live at once for some recomputation.
+GROUPS = {"gg_ttgg": 3}
+
+
+def emit_body(d: Diagrams, groups: int):
+    """Statements of the amplitude code with the terms split into groups."""
+    em = Emitter(d)
+    splits, shared = plan_splits(d)
+    order = schedule(em, splits, shared)
+    cuts = {round(g * len(order) / groups) for g in range(1, groups)}
+    em.emit("{  // group 1")
+    for pos, t in enumerate(order):
+        if pos in cuts:
+            em.cache.clear()
+            em.emit("}")
+            em.emit("term_fence();")
+            em.emit("{  // next group: currents are rebuilt from here on")
+        seq, colour = d.terms[t]
+        em.amplitude(seq, colour, splits[t], shared[t])
+    em.emit("}")
+    return em
+
+
+def generate(d: Diagrams, groups: int | None = None) -> str:
     name = d.process.name
     legs = d.process.legs
     n = len(legs)
-    em = Emitter(d)
-    splits, shared = plan_splits(d)
-    for t in schedule(em, splits, shared):
-        seq, colour = d.terms[t]
-        em.amplitude(seq, colour, splits[t], shared[t])
+    em = emit_body(d, 1)
     body = em.lines
+    groups = groups or GROUPS.get(d.process.name, 1)
+    em_g = emit_body(d, groups) if groups > 1 else em
     num, den = colour_matrix_ints(d)
     good = good_helicities(d)
     ncol = len(d.basis)
@@ -517,6 +540,18 @@ def generate(d: Diagrams) -> str:
     out.append("  for (int c = 0; c < NCOL; ++c) jamp[c] = cx<R>{R(0), R(0)};")
     out.append("  cx<R> amp;")
     out.extend(body)
+    out.append("}")
+    out.append("")
+    out.append(f"// Same amplitudes with the terms in {groups} group(s), currents rebuilt in each")
+    out.append("// group: fewer live registers (used for the double-precision kernel).")
+    out.append("// Routine counts per helicity: " + ", ".join(f"{k} {v}" for k, v in em_g.count.items()))
+    out.append("template <class R, class D, class J>")
+    out.append(f"__host__ __device__ __forceinline__ void jamps_grouped(const D (&P)[{n}][4], int hel, const Card<R, D>& cd, J& jamp) {{")
+    for i in range(n):
+        out.append(f"  const int h{i} = ((hel >> {n - 1 - i}) & 1) ? 1 : -1;")
+    out.append("  for (int c = 0; c < NCOL; ++c) jamp[c] = cx<R>{R(0), R(0)};")
+    out.append("  cx<R> amp;")
+    out.extend(em_g.lines)
     out.append("}")
     out.append("")
     # colour sum: J^dagger C J = sum_i J_i^* (C J)_i, C real symmetric
