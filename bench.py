@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=2000)
     ap.add_argument("--modes", default="fp64,mixed")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 512 MiB device copy (scale reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -213,6 +216,17 @@ def main():
             line["batched"][mode] = batched_leg(rw, torch, prec, steps=5, warmup=2)
             log(f"batched {mode}: {line['batched'][mode]['batched_ms']:.2f} ms vs plain "
                 f"{line['batched'][mode]['plain_ms']:.2f} ms")
+    if not a.no_surrogate:
+        from paper_2510_05100_amd import surrogate
+        summary, sur, _ = surrogate.run(torch, surrogate.Config(), log=log)
+        sur.close()
+        line["surrogate"] = summary
+    if a.copy_probe:
+        src = torch.empty(64 << 20, dtype=torch.float64, device="cuda")
+        dst = src.clone()
+        torch.cuda.synchronize()
+        line["copy_probe_bytes"] = 2 * src.numel() * 8
+        del src, dst
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, a.cpu_sample, m["w"])
     print(json.dumps(line), flush=True)

@@ -107,6 +107,18 @@ int rwgt_process_info(const rwgt_ctx *ctx, int32_t *npart, int32_t *nhel_kept, i
  * them.  Used to express measured throughput as FLOP/s against the peak. */
 int rwgt_flops(const rwgt_ctx *ctx, double *flops_per_me2);
 
+/* Reweighted cross sections and their errors for nsets cards (teaRex section):
+ *   sigma'_k  = norm * sum_i w'_ki,
+ *   dsigma'_k = dsigma * (1/N) sum_i w'_ki / w_i + sigma * std_i(w'_ki),
+ * std the population standard deviation, terms with w_i = 0 counted as 0.
+ * If dsigma'_k is infinite, NaN or not positive, a warning goes to stderr,
+ * fallback[k] = 1 and dsigma'_k = dsigma * max(sigma'_k/sigma, sigma/sigma'_k).
+ * weights_in [nevt], weights_out [nsets][nevt]: DEVICE; xsec, xerr [nsets] and
+ * fallback [nsets] (optional): HOST.  The sums are reduced on the device in a
+ * fixed order (reproducible); the call waits for the result. */
+int rwgt_xsec(rwgt_ctx *ctx, const double *weights_in, const double *weights_out, int64_t nevt, int32_t nsets,
+              double sigma, double dsigma, double norm, double *xsec, double *xerr, int32_t *fallback);
+
 /* Record HIP events around the ingest and matrix-element kernels of each
  * subsequent rwgt_eval / rwgt_me2 (on the context's stream). */
 int rwgt_set_profiling(rwgt_ctx *ctx, int enable);

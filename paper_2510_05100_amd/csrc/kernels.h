@@ -21,6 +21,11 @@ hipError_t launch_ingest(int npart, const double* aos, double* soa, int64_t nevt
 hipError_t launch_me(int proc, int precision, const double* soa, int64_t nevt, const CardPair* cards, int ncards,
                      const double* w_in, double* w_out, double* me_out, hipStream_t s);
 
+// Reweighted cross sections and errors per card: out[k] = {sigma', dsigma', fallback flag};
+// part must hold nsets * nblocks * 3 doubles.
+hipError_t launch_xsec(const double* w_in, const double* w_out, int64_t nevt, int nsets, double sigma, double dsigma,
+                       double norm, double* part, int nblocks, double* out, hipStream_t s);
+
 void process_constants(int proc, int* npart, int* ngood, int* ncol, int* ndiag);
 double process_flops(int proc);
 

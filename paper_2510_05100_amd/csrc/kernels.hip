@@ -30,6 +30,68 @@ __global__ __launch_bounds__(256) void ingest_kernel(const double* __restrict__ 
   }
 }
 
+// Reweighted cross sections (teaRex section): per card the sums
+// S1 = sum w', S2 = sum w'^2 and R = sum w'/w (terms with w = 0 count 0),
+// reduced in two deterministic passes, then
+//   sigma' = C S1,  dsigma' = dsigma R/N + sigma std(w'),  std = sqrt(S2/N - (S1/N)^2),
+// and, when dsigma' is infinite, NaN or not positive, dsigma' = dsigma max(sigma'/sigma, sigma/sigma').
+constexpr int kXsecBlock = 256;
+
+__global__ __launch_bounds__(kXsecBlock) void xsec_partial(const double* __restrict__ w_in,
+                                                           const double* __restrict__ w_out, int64_t nevt,
+                                                           double* __restrict__ part) {
+  __shared__ double sh[3][kXsecBlock];
+  const int k = blockIdx.y;
+  const double* wo = w_out + int64_t(k) * nevt;
+  double s1 = 0.0, s2 = 0.0, r = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nevt; i += int64_t(gridDim.x) * blockDim.x) {
+    const double x = wo[i];
+    s1 += x;
+    s2 += x * x;
+    r += w_in[i] != 0.0 ? x / w_in[i] : 0.0;
+  }
+  sh[0][threadIdx.x] = s1;
+  sh[1][threadIdx.x] = s2;
+  sh[2][threadIdx.x] = r;
+  __syncthreads();
+  for (int w = kXsecBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) part[(int64_t(k) * gridDim.x + blockIdx.x) * 3 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(64) void xsec_final(const double* __restrict__ part, int nblocks, int64_t nevt,
+                                                 double sigma, double dsigma, double norm, double* __restrict__ out) {
+  const int k = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int b = 0; b < nblocks; ++b)
+    for (int q = 0; q < 3; ++q) s[q] += part[(int64_t(k) * nblocks + b) * 3 + q];
+  const double n = double(nevt);
+  const double xs = norm * s[0];
+  const double mean = s[0] / n;
+  const double var = s[1] / n - mean * mean;
+  double err = dsigma * (s[2] / n) + sigma * sqrt(var > 0.0 ? var : 0.0);
+  double fallback = 0.0;
+  if (!(err > 0.0) || isinf(err)) {
+    const double a = xs / sigma, b = sigma / xs;
+    err = dsigma * (a > b ? a : b);
+    fallback = 1.0;
+  }
+  out[k * 3 + 0] = xs;
+  out[k * 3 + 1] = err;
+  out[k * 3 + 2] = fallback;
+}
+
+hipError_t launch_xsec(const double* w_in, const double* w_out, int64_t nevt, int nsets, double sigma, double dsigma,
+                       double norm, double* part, int nblocks, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(xsec_partial, dim3(nblocks, nsets), dim3(kXsecBlock), 0, s, w_in, w_out, nevt, part);
+  hipLaunchKernelGGL(xsec_final, dim3(nsets), dim3(64), 0, s, part, nblocks, nevt, sigma, dsigma, norm, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_ingest(int npart, const double* aos, double* soa, int64_t nevt, hipStream_t s) {
   const int64_t blocks = (nevt + kIngestEvents - 1) / kIngestEvents;
   switch (npart) {

@@ -402,6 +402,36 @@ int rwgt_kernel_times(rwgt_ctx* ctx, float* ingest_ms, float* me_ms) {
   return RWGT_OK;
 }
 
+int rwgt_xsec(rwgt_ctx* ctx, const double* weights_in, const double* weights_out, int64_t nevt, int32_t nsets,
+              double sigma, double dsigma, double norm, double* xsec, double* xerr, int32_t* fallback) {
+  if (!ctx) return RWGT_EINVAL;
+  ctx->err.clear();
+  if (nevt < 1 || nsets < 1 || !weights_in || !weights_out || !xsec || !xerr)
+    return ctx->fail(RWGT_EINVAL, "bad arguments");
+  constexpr int kBlocks = 512;
+  double *part = nullptr, *out = nullptr;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipMalloc(&part, size_t(nsets) * kBlocks * 3 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&out, size_t(nsets) * 3 * sizeof(double));
+  if (e == hipSuccess)
+    e = rwgt::launch_xsec(weights_in, weights_out, nevt, nsets, sigma, dsigma, norm, part, kBlocks, out, ctx->stream);
+  std::vector<double> host(size_t(nsets) * 3);
+  if (e == hipSuccess) e = hipMemcpyAsync(host.data(), out, host.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (part) hipFree(part);
+  if (out) hipFree(out);
+  if (e != hipSuccess) return ctx->hip_fail(e, "cross-section reduction");
+  for (int32_t k = 0; k < nsets; ++k) {
+    xsec[k] = host[k * 3];
+    xerr[k] = host[k * 3 + 1];
+    if (fallback) fallback[k] = host[k * 3 + 2] != 0.0;
+    if (host[k * 3 + 2] != 0.0)
+      std::fprintf(stderr, "rwgt: error propagation for card %d gave no positive finite value; "
+                           "using dsigma * max(sigma'/sigma, sigma/sigma')\n", int(k));
+  }
+  return RWGT_OK;
+}
+
 int rwgt_flops(const rwgt_ctx* ctx, double* flops_per_me2) {
   if (!ctx || !flops_per_me2) return RWGT_EINVAL;
   *flops_per_me2 = rwgt::process_flops(ctx->def->id);

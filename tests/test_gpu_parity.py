@@ -127,3 +127,24 @@ def test_side_stream():
         s.synchronize()
         ref, _, _ = reweight.reweight("ee_mumu", p, np.ones(3000), synth.ORIG_EW, [synth.NEW_EE])
         assert rel_err(out.cpu().numpy(), ref).max() < 1e-12
+
+
+def test_xsec_against_oracle():
+    _print_case("xsec")
+    torch = torch_cuda()
+    import paper_2510_05100_amd as rw
+    from oracle import xsec as oxsec
+    n = 5000
+    p = synth.events("uu_eeg", n)
+    w = np.random.default_rng(4).uniform(0.2, 2.0, n)
+    cards = [synth.NEW_UU, synth.NEW_EE, synth.ORIG_EW]
+    with rw.Reweighter("u u~ > e+ e- g", synth.ORIG_EW.slha()) as r:
+        out = torch.empty((3, n), dtype=torch.float64, device="cuda")
+        wd = dev(w)
+        r.eval(dev(p), wd, np.stack([c.row("uu_eeg") for c in cards]), out)
+        xs, xe, fb = rw.rwgt_xsec(r.ctx, wd, out, 12.5, 0.3, 12.5 / w.sum())
+        ref_w, _, _ = reweight.reweight("uu_eeg", p, w, synth.ORIG_EW, cards)
+    rx, re_, rb = oxsec.xsec(w, ref_w, 12.5, 0.3, 12.5 / w.sum())
+    assert rel_err(xs, rx).max() < 1e-11 and rel_err(xe, re_).max() < 1e-9
+    assert not fb.any() and not rb.any()
+    assert abs(xs[2] - 12.5) < 1e-10          # the original card gives back sigma
