@@ -15,6 +15,7 @@ all events, which the oracle reproduces to 1e-13.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,6 +30,33 @@ METRIC = "reweighted events/sec (gg→tt̄gg, FP64 vs mixed) at stated max rel. 
 RATIO = (0.130 / 0.118) ** 4
 PEAK_FP64_VALU = 78.6e12        # MI355X FP64 vector, FLOP/s
 PEAK_FP32_VALU_UNPACKED = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz without packed FP32
+# HBM bytes per launch of the matrix-element kernel, from the FETCH_SIZE and
+# WRITE_SIZE counter passes (scaled by a copy kernel of known size); valid only
+# for the kernel sources they were taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "me_kernel_gg_ttgg_1e6_traffic.json")
+KERNEL_SOURCES = ["me_kernel.h", "helas.h", "card.h", "colour_mfma.h", "proc_gg_ttgg.hip", "generated/gen_gg_ttgg.h"]
+
+
+def kernel_sources_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2510_05100_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(mode, events):
+    """Counter-measured HBM bytes per launch, or None when the counters were
+    taken on other kernel sources, another mode or another event count."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    rec = d.get("modes", {}).get(mode)
+    if not rec or d.get("sources_sha256") != kernel_sources_hash() or d.get("events") != events:
+        return None
+    return rec["bytes_per_launch"]
 
 
 def parse():
@@ -185,11 +213,11 @@ def main():
             f"max rel err {res[mode]['max_rel_err']:.3g}")
     nsets = rows.shape[0]
 
-    def roofline(r, peak):
+    def roofline(r, peak, mode):
         flops = r["flops_per_me2"] * a.events * (1 + nsets)
         ach = flops / (r["me_ms"] * 1e-3)
         return {"bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": None,
+                "frac": ach / peak, "traffic": measured_traffic(mode, a.events),
                 "kernel": "me_kernel<Proc_gg_ttgg>", "flops_per_launch": flops}
 
     main_mode = "fp64" if "fp64" in res else next(iter(res))
@@ -203,13 +231,13 @@ def main():
                                "pT(g) > 30 GeV, dR(g,g) > 0.4), alpha_s 0.118 -> 0.130, 1 new card",
                    "events": a.events, "new_cards": nsets, "precision": main_mode},
         "max_rel_err": m["max_rel_err"],
-        "roofline": roofline(m, PEAK_FP64_VALU),
+        "roofline": roofline(m, PEAK_FP64_VALU, main_mode),
     }
     if "mixed" in res and main_mode != "mixed":
         x = res["mixed"]
         line["mixed"] = {"value": a.events * nsets / (x["ms_per_step"] * 1e-3), "ms_per_step": x["ms_per_step"],
                          "max_rel_err": x["max_rel_err"], "dtype": "f32 amplitudes, f64 momenta/denominators/ratio",
-                         "roofline": roofline(x, PEAK_FP32_VALU_UNPACKED)}
+                         "roofline": roofline(x, PEAK_FP32_VALU_UNPACKED, "mixed")}
     if not a.no_batched:
         line["batched"] = {}
         for mode, prec in (("fp64", rw.RWGT_FP64), ("mixed", rw.RWGT_MIXED_FP16)):
