@@ -7,10 +7,23 @@ of the error of mu).  Loss over n rows with targets y:
   L = 1/n sum_r [ 1/2 (y_r - mu_r)^2 + lambda (1/2 r_r^2 exp(-2 s_r) + s_r) ]
 
 with r_r = y_r - mu_r held fixed in the second term (its gradient reaches s
-only) and s clamped below at -15 (zero gradient there).  Parameters are a list
-of (W [out][in], b [out]).
+only) and s clamped below at -15 (zero gradient there).  Targets may be
+standardised first, y -> (y - y_mean) / y_std (``scale``); the heads are then
+in standardised units.  Parameters are a list of (W [out][in], b [out]).
 
-Pinned by central finite differences of L (tests/test_oracle_mlp.py).
+Input features of one (event, card) pair (``phys_features``): with the
+momenta p_0..p_{n-1} (two incoming first, all massless), s_hat = 2 p_0.p_1
+and s_ij = 2 p_i.p_j,
+  [log s_hat, log(s_ij / s_hat) for i < j (row-major), M_Z, Gamma_Z,
+   sin^2 theta_W, asinh Re chi, asinh Im chi, asinh Re chi_0, asinh Im chi_0]
+where chi = s / (s - M_Z^2 + i M_Z Gamma_Z) is the Z propagator relative to
+the photon's at the invariant mass s = s_ab of the resonant pair (a, b),
+under the card (chi) and under the original card (chi_0).  ``raw_features``
+is the plain [momenta (n*4), M_Z, Gamma_Z, sin^2 theta_W] row.
+
+Pinned by central finite differences of L, and the features by momentum
+conservation, a direct (p_i + p_j)^2 and the propagator's pole and
+high-energy limits (tests/test_oracle_mlp.py).
 """
 from __future__ import annotations
 
@@ -39,7 +52,42 @@ def forward(params, x):
     return h, cache
 
 
-def loss(params, x, y, lam):
+def raw_features(p, cards):
+    """[n][npart*4 + 3] rows from momenta p [n][npart][4] and cards [n][3]."""
+    p = np.asarray(p, dtype=np.float64)
+    return np.concatenate([p.reshape(p.shape[0], -1), np.asarray(cards, dtype=np.float64)], axis=1)
+
+
+def _mdot(a, b):
+    return a[..., 0] * b[..., 0] - a[..., 1] * b[..., 1] - a[..., 2] * b[..., 2] - a[..., 3] * b[..., 3]
+
+
+def phys_features(p, cards, res, orig):
+    """Physics features (module docstring) of momenta p [n][npart][4] with
+    cards [n][3] = (M_Z, Gamma_Z, sin^2 theta_W); res = (a, b) the resonant
+    pair; orig = (M_Z, Gamma_Z) of the original card."""
+    p = np.asarray(p, dtype=np.float64)
+    cards = np.asarray(cards, dtype=np.float64)
+    npart = p.shape[1]
+    s_hat = 2.0 * _mdot(p[:, 0], p[:, 1])
+    cols = [np.log(s_hat)]
+    for i in range(npart):
+        for j in range(i + 1, npart):
+            cols.append(np.log(np.maximum(np.abs(2.0 * _mdot(p[:, i], p[:, j])) / s_hat, 1e-300)))
+    cols += [cards[:, 0], cards[:, 1], cards[:, 2]]
+    s = 2.0 * _mdot(p[:, res[0]], p[:, res[1]])
+    for mz, wz in ((cards[:, 0], cards[:, 1]), (orig[0], orig[1])):
+        chi = s / (s - mz * mz + 1j * mz * wz)
+        cols += [np.arcsinh(chi.real), np.arcsinh(chi.imag)]
+    return np.stack(cols, axis=1)
+
+
+def n_phys_features(npart):
+    return 1 + npart * (npart - 1) // 2 + 3 + 4
+
+
+def loss(params, x, y, lam, scale=(0.0, 1.0)):
+    y = (np.asarray(y, dtype=np.float64) - scale[0]) / scale[1]
     heads, _ = forward(params, x)
     mu, s_raw = heads[:, 0], heads[:, 1]
     s = np.maximum(s_raw, S_MIN)
@@ -47,8 +95,9 @@ def loss(params, x, y, lam):
     return float(np.mean(0.5 * r * r + lam * (0.5 * r * r * np.exp(-2 * s) + s)))
 
 
-def gradients(params, x, y, lam):
+def gradients(params, x, y, lam, scale=(0.0, 1.0)):
     """d loss / d (W, b) for every layer (the r held fixed in the error term)."""
+    y = (np.asarray(y, dtype=np.float64) - scale[0]) / scale[1]
     heads, cache = forward(params, x)
     n = heads.shape[0]
     mu, s_raw = heads[:, 0], heads[:, 1]
