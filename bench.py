@@ -246,7 +246,7 @@ def main():
                 f"{line['batched'][mode]['plain_ms']:.2f} ms")
     if not a.no_surrogate:
         from paper_2510_05100_amd import surrogate
-        summary, sur, _ = surrogate.run(torch, surrogate.Config(), log=log)
+        summary, sur = surrogate.run(torch, surrogate.Config(), log=log)
         sur.close()
         line["surrogate"] = summary
     if a.copy_probe:

@@ -178,22 +178,38 @@ const char *rwgt_batch_last_error(const rwgt_batch *batch);
 /* ------------------------------------------------------------------------
  * Learned surrogate: a multilayer perceptron for log(w'/w) with a second
  * head for the log of its own error, trained and run by the library's own
- * kernels (BF16 operands on the matrix cores with FP32 accumulation, or FP32
- * operands on the VALU for gradient checks; FP32 master weights and Adam).
- * The input row of one (event, card) pair is [momenta (npart*4), card
- * parameters (nparam)], standardised with the mean and standard deviation set
- * by rwgt_mlp_set_normalisation.  Hidden layers use SiLU.  The loss per row is
- *   1/2 (y - mu)^2 + lambda (1/2 r^2 exp(-2 s) + s),  r = y - mu held fixed,
+ * kernels with FP32 master weights, Adam and FP32 accumulation.  Operand
+ * types: in a BF16 network the first layer and the head are FP32 (VALU) and
+ * the width x width hidden layers BF16 (matrix cores); in an FP32 network
+ * (gradient checks) every layer is FP32.  Hidden layers use SiLU.
+ *
+ * Input row of one (event, card) pair, standardised with the mean and
+ * standard deviation of rwgt_mlp_set_normalisation, from one of two maps
+ * (rwgt_mlp_set_features; n_in must equal the map's width):
+ *   RWGT_FEAT_RAW   [momenta (npart*4), M_Z, Gamma_Z, sin^2 theta_W]
+ *   RWGT_FEAT_PHYS  with s_hat = 2 p0.p1, s_ij = 2 pi.pj (massless momenta):
+ *                   [log s_hat, log(|s_ij| / s_hat) for i < j (row-major),
+ *                    M_Z, Gamma_Z, sin^2 theta_W, asinh Re chi, asinh Im chi,
+ *                    asinh Re chi0, asinh Im chi0],
+ *                   chi = s / (s - M_Z^2 + i M_Z Gamma_Z) at s = s_ab of the
+ *                   resonant pair (a, b) under the card, chi0 under the
+ *                   original card: 1 + npart(npart-1)/2 + 7 inputs.
+ * Targets y are standardised, y' = (y - y_mean) / y_std
+ * (rwgt_mlp_set_target_scale); mu and s below are in y' units, and every
+ * output (heads, gate) is converted back: mu_y = mu y_std + y_mean,
+ * s_y = s + log y_std.  Loss per row:
+ *   1/2 (y' - mu)^2 + lambda (1/2 r^2 exp(-2 s) + s),  r = y' - mu held fixed,
  * mu = head 0, s = head 1 (clamped at -15).  Device pointers unless noted;
  * calls enqueue on the network's stream (rwgt_mlp_set_stream).
  */
 typedef struct rwgt_mlp rwgt_mlp;
 
 enum { RWGT_MLP_BF16 = 0, RWGT_MLP_FP32 = 1 };
+enum { RWGT_FEAT_RAW = 0, RWGT_FEAT_PHYS = 1 };
 
-/* n_in inputs, depth hidden layers of width (multiple of 32), n_out heads
- * (2..32); He-uniform initial weights from seed (last layer scaled by 0.1),
- * zero biases.  Errors: RWGT_EINVAL, RWGT_EDEVICE, RWGT_ENOMEM. */
+/* n_in (1..32) inputs, depth hidden layers of width (multiple of 32), n_out
+ * heads (2..32); He-uniform initial weights from seed (last layer scaled by
+ * 0.1), zero biases.  Errors: RWGT_EINVAL, RWGT_EDEVICE, RWGT_ENOMEM. */
 int rwgt_mlp_create(int32_t n_in, int32_t width, int32_t depth, int32_t n_out, int32_t precision, uint64_t seed,
                     rwgt_mlp **out);
 void rwgt_mlp_destroy(rwgt_mlp *mlp);
@@ -204,34 +220,76 @@ int rwgt_mlp_num_params(const rwgt_mlp *mlp, int64_t *n);
 int rwgt_mlp_get_params(rwgt_mlp *mlp, float *host);
 int rwgt_mlp_set_params(rwgt_mlp *mlp, const float *host);
 int rwgt_mlp_get_grads(rwgt_mlp *mlp, float *host);
-/* HOST arrays of n_in floats. */
+/* HOST arrays of n_in floats (standard deviations positive). */
 int rwgt_mlp_set_normalisation(rwgt_mlp *mlp, const float *mean, const float *stdv);
+/* Feature map (see above) for npart (4 or 5) external particles; res_a,
+ * res_b: the resonant pair; mz0, wz0: the original card's Z mass and width.
+ * Without this call a network uses the raw map of the npart passed to
+ * rwgt_mlp_features.  Errors: RWGT_EINVAL (unknown map, width mismatch). */
+int rwgt_mlp_set_features(rwgt_mlp *mlp, int32_t kind, int32_t npart, int32_t res_a, int32_t res_b, double mz0,
+                          double wz0);
+/* HOST outputs: mean and stdv (n_in floats each) of the input normalisation
+ * and y_scale = (y_mean, y_std). */
+int rwgt_mlp_get_normalisation(rwgt_mlp *mlp, float *mean, float *stdv, float *y_scale);
+/* Target standardisation (y_std > 0). */
+int rwgt_mlp_set_target_scale(rwgt_mlp *mlp, float y_mean, float y_std);
+/* Sets the input normalisation to the mean and (population) standard
+ * deviation of each feature over n rows given as in rwgt_mlp_features
+ * (constant features: standard deviation 1); FP64 sums on the device, waits
+ * for the stream. */
+int rwgt_mlp_fit_normalisation(rwgt_mlp *mlp, const double *momenta, int32_t npart, const int32_t *event_index,
+                               const int32_t *card_index, const float *card_params, int64_t n);
+/* Sets the target scale to the mean and standard deviation of y [n] (device
+ * FP32); waits for the stream. */
+int rwgt_mlp_fit_target_scale(rwgt_mlp *mlp, const float *y, int64_t n);
 /* Loss weight lambda of the error head and the Adam constants. */
 int rwgt_mlp_set_training(rwgt_mlp *mlp, float lambda, float beta1, float beta2, float eps);
-/* Quantile factor k: the error bound of a prediction is k exp(s). */
+/* Quantile factor k: the error bound of a prediction is k exp(s_y). */
 int rwgt_mlp_set_calibration(rwgt_mlp *mlp, float k);
-/* Bytes of the input buffer for n rows (rows are padded to a multiple of 64). */
+/* Bytes of the FP32 input buffer for n rows (rows padded to a multiple of 64,
+ * 32 columns). */
 int rwgt_mlp_input_bytes(const rwgt_mlp *mlp, int64_t n, int64_t *bytes);
-/* Input rows: row r = [momenta[event_index[r]] (npart*4 doubles; event_index
- * NULL: r), card_params[card_index[r]] (nparam floats)], standardised. */
+/* Input rows of the training path: row r = features of (momenta[event_index[r]]
+ * (npart*4 doubles each; event_index NULL: r), card_params[card_index[r]]
+ * (nparam = 3 floats: M_Z, Gamma_Z, sin^2 theta_W)), standardised. */
 int rwgt_mlp_features(rwgt_mlp *mlp, const double *momenta, int32_t npart, const int32_t *event_index,
                       const int32_t *card_index, const float *card_params, int32_t nparam, int64_t n, void *x_out);
-/* Heads of n rows into heads_out [n][32] (FP32; head 0 = mu, 1 = s). */
+/* Layered forward pass: heads of n rows into heads_out [n][32] (FP32; column 0
+ * = mu_y, 1 = s_y, the others the padding heads). */
 int rwgt_mlp_forward(rwgt_mlp *mlp, const void *x, int64_t n, float *heads_out);
+/* Fused forward pass from the momenta (rows as in rwgt_mlp_features):
+ * heads_out [n][2] = (mu_y, s_y).  The first layer runs as three BF16
+ * products of the high and low parts of its FP32 operands, the hidden layers
+ * in BF16 as in training, the head in FP32.  BF16 networks of width 128 or
+ * 256 and depth 2..9 only (else RWGT_EINVAL). */
+int rwgt_mlp_predict(rwgt_mlp *mlp, const double *momenta, int32_t npart, const int32_t *event_index,
+                     const int32_t *card_index, const float *card_params, int64_t n, float *heads_out);
 /* Forward, loss, backward and (lr > 0) one Adam step on n rows with targets y
- * [n] (FP32); the summed loss goes to loss_out (device float) if non-NULL. */
+ * [n] (FP32, unstandardised); the summed loss goes to loss_out (device float)
+ * if non-NULL. */
 int rwgt_mlp_train_step(rwgt_mlp *mlp, const void *x, const float *y, int64_t n, float lr, float *loss_out);
 /* Training targets y[i] = log(w_new[i] / w_old[i]) (w_old NULL: 1; w_old = 0: y = 0). */
 int rwgt_mlp_targets(rwgt_mlp *mlp, const double *w_new, const double *w_old, int64_t n, float *y);
 const char *rwgt_mlp_last_error(const rwgt_mlp *mlp);
+
+/* Exact reweighting with a card per event (the path rwgt_sur_eval falls back
+ * to, on every event): event i gets card card_index[i] (DEVICE int32, in
+ * [0, ncards)) of param_table (HOST [ncards][npar], the context's layout),
+ * w'_i = (w_i / |M|^2(p_i; original)) |M|^2(p_i; card).  Processes of the
+ * electroweak family.  Errors as rwgt_eval, RWGT_EPROCESS for other
+ * processes. */
+int rwgt_eval_cards(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const double *weights_in,
+                    const double *param_table, int32_t ncards, const int32_t *card_index, double *weights_out);
 
 /* Reweighting through the surrogate with exact fallback (same result
  * definition as rwgt_eval): event i gets card card_index[i] (DEVICE int32) of
  * param_table (HOST [ncards][npar], the context's layout); where the predicted
  * error k exp(s) of log(w'/w) is at most err_threshold,
  * w'_i = w_i exp(mu_i); elsewhere w'_i is computed exactly by the
- * matrix-element path.  The network's inputs are the momenta and the card's
- * (M_Z, Gamma_Z, sin^2 theta_W).  *n_fallback (HOST, optional; waits for the
+ * matrix-element path.  The network's inputs are its feature map of the
+ * momenta and the card's (M_Z, Gamma_Z, sin^2 theta_W).  Networks eligible
+ * for rwgt_mlp_predict run as one fused kernel (features, layers, heads and
+ * gate), others layer by layer.  *n_fallback (HOST, optional; waits for the
  * call) receives the number of exact evaluations.  Processes of the
  * electroweak family. */
 int rwgt_sur_eval(rwgt_ctx *ctx, rwgt_mlp *mlp, const double *momenta, int64_t nevt, const double *weights_in,

@@ -8,7 +8,9 @@ from ._abi import (  # noqa: F401
     RWGT_MLP_BF16, RWGT_MLP_FP32, rwgt_mlp_create, rwgt_mlp_destroy, rwgt_mlp_features, rwgt_mlp_forward,
     rwgt_mlp_get_grads, rwgt_mlp_get_params, rwgt_mlp_input_bytes, rwgt_mlp_num_params, rwgt_mlp_set_calibration,
     rwgt_mlp_set_normalisation, rwgt_mlp_set_params, rwgt_mlp_set_stream, rwgt_mlp_set_training, rwgt_mlp_targets,
-    rwgt_mlp_train_step, rwgt_sur_eval,
+    rwgt_mlp_train_step, rwgt_sur_eval, RWGT_FEAT_RAW, RWGT_FEAT_PHYS, n_features, rwgt_mlp_set_features,
+    rwgt_mlp_set_target_scale, rwgt_mlp_predict, rwgt_mlp_fit_normalisation,
+    rwgt_mlp_fit_target_scale, rwgt_mlp_get_normalisation, rwgt_eval_cards,
 )
 from ._abi import (  # noqa: F401
     Segment, make_segments, rwgt_batch_create, rwgt_batch_destroy, rwgt_batch_eval, rwgt_batch_get_schedule,

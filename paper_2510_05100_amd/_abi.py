@@ -76,11 +76,22 @@ SIGNATURES.update({
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                                           ctypes.c_void_p]),
     "rwgt_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "rwgt_mlp_set_features": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_int32] * 4 + [ctypes.c_double] * 2),
+    "rwgt_mlp_set_target_scale": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_float, ctypes.c_float]),
+    "rwgt_mlp_fit_normalisation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "rwgt_mlp_fit_target_scale": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "rwgt_mlp_get_normalisation": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_float)] * 3),
+    "rwgt_mlp_predict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "rwgt_mlp_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                             ctypes.c_float, ctypes.c_void_p]),
     "rwgt_mlp_targets": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                          ctypes.c_void_p]),
     "rwgt_mlp_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "rwgt_eval_cards": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
     "rwgt_sur_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                       ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
@@ -334,6 +345,12 @@ def rwgt_batch_tune(batch, segments, reps=2):
 
 # ------------------------------------------------------------------ surrogate
 RWGT_MLP_BF16, RWGT_MLP_FP32 = 0, 1
+RWGT_FEAT_RAW, RWGT_FEAT_PHYS = 0, 1
+
+
+def n_features(kind, npart):
+    """Width of a feature map (rwgt_mlp_set_features)."""
+    return npart * 4 + 3 if kind == RWGT_FEAT_RAW else 1 + npart * (npart - 1) // 2 + 3 + 4
 
 
 def _mraise(code, mlp):
@@ -406,6 +423,43 @@ def rwgt_mlp_set_normalisation(mlp, mean, std):
         _mraise(rc, mlp)
 
 
+def rwgt_mlp_set_features(mlp, kind, npart, res=(2, 3), orig=(0.0, 0.0)):
+    rc = load().rwgt_mlp_set_features(mlp, int(kind), int(npart), int(res[0]), int(res[1]), float(orig[0]),
+                                      float(orig[1]))
+    if rc != 0:
+        _mraise(rc, mlp)
+
+
+def rwgt_mlp_set_target_scale(mlp, mean, std):
+    rc = load().rwgt_mlp_set_target_scale(mlp, float(mean), float(std))
+    if rc != 0:
+        _mraise(rc, mlp)
+
+
+def rwgt_mlp_fit_normalisation(mlp, momenta, event_index, card_index, card_params, n):
+    rc = load().rwgt_mlp_fit_normalisation(mlp, _dp(momenta), momenta.shape[1], _dp(event_index), _dp(card_index),
+                                           _dp(card_params), int(n))
+    if rc != 0:
+        _mraise(rc, mlp)
+
+
+def rwgt_mlp_get_normalisation(mlp, n_in):
+    """(mean [n_in], std [n_in], (y_mean, y_std))."""
+    mean = np.zeros(n_in, dtype=np.float32)
+    std = np.zeros(n_in, dtype=np.float32)
+    ys = np.zeros(2, dtype=np.float32)
+    rc = load().rwgt_mlp_get_normalisation(mlp, _fptr(mean), _fptr(std), _fptr(ys))
+    if rc != 0:
+        _mraise(rc, mlp)
+    return mean, std, (float(ys[0]), float(ys[1]))
+
+
+def rwgt_mlp_fit_target_scale(mlp, y, n=None):
+    rc = load().rwgt_mlp_fit_target_scale(mlp, _dp(y), int(y.numel() if n is None else n))
+    if rc != 0:
+        _mraise(rc, mlp)
+
+
 def rwgt_mlp_set_training(mlp, lam=0.1, beta1=0.9, beta2=0.999, eps=1e-8):
     rc = load().rwgt_mlp_set_training(mlp, lam, beta1, beta2, eps)
     if rc != 0:
@@ -445,6 +499,14 @@ def rwgt_mlp_forward(mlp, x, n, heads_out=None):
         _mraise(rc, mlp)
 
 
+def rwgt_mlp_predict(mlp, momenta, event_index, card_index, card_params, n, heads_out):
+    """Fused forward pass: heads_out [n, 2] f32 (mu, s) for rows (event_index[r] or r, card_index[r])."""
+    rc = load().rwgt_mlp_predict(mlp, _dp(momenta), momenta.shape[1], _dp(event_index), _dp(card_index),
+                                 _dp(card_params), int(n), _dp(heads_out))
+    if rc != 0:
+        _mraise(rc, mlp)
+
+
 def rwgt_mlp_train_step(mlp, x, y, n, lr, loss_out=None):
     rc = load().rwgt_mlp_train_step(mlp, _dp(x), _dp(y), int(n), float(lr), _dp(loss_out))
     if rc != 0:
@@ -455,6 +517,18 @@ def rwgt_mlp_targets(mlp, w_new, w_old, y):
     rc = load().rwgt_mlp_targets(mlp, _dp(w_new), _dp(w_old), int(w_new.numel()), _dp(y))
     if rc != 0:
         _mraise(rc, mlp)
+
+
+def rwgt_eval_cards(ctx, momenta, weights_in, param_table, card_index, weights_out):
+    """Exact w' with a card per event: weights_out[i] under param_table[card_index[i]]."""
+    _check_device(momenta, "momenta")
+    _check_device(weights_in, "weights_in")
+    _check_device(weights_out, "weights_out")
+    table, tptr = _host_params(param_table)
+    rc = load().rwgt_eval_cards(ctx, _dp(momenta), momenta.shape[0], _dp(weights_in), tptr, table.shape[0],
+                                _dp(card_index), _dp(weights_out))
+    if rc != 0:
+        _raise(rc, ctx)
 
 
 def rwgt_sur_eval(ctx, mlp, momenta, weights_in, param_table, card_index, err_threshold, weights_out):

@@ -74,35 +74,36 @@ static hipError_t launch_batch_t(const BatchSeg* segs, int nseg, int64_t ntiles,
 
 // Exact reweighting of the events listed by the surrogate gate: lane i takes
 // list[i] < *count (grid-stride, the count stays on the device), card
-// cards[1 + card_index[e]] against the original cards[0].
+// cards[1 + card_index[e]] against the original cards[0].  Without a list
+// every event 0..n_all-1 is taken.
 template <class R, class... PROCS>
 __global__ __launch_bounds__(256) void exact_list_kernel(int proc, const double* __restrict__ mom,
                                                          const int32_t* __restrict__ list,
-                                                         const unsigned int* __restrict__ count,
+                                                         const unsigned int* __restrict__ count, int64_t n_all,
                                                          const int32_t* __restrict__ card_index,
                                                          const CardPair* __restrict__ cards,
                                                          const double* __restrict__ w_in, double* __restrict__ w_out) {
-  const unsigned int n = *count;
+  const int64_t n = list ? int64_t(*count) : n_all;
   BatchSeg sg{};
   sg.mom = mom;
   sg.w_in = w_in;
   sg.w_out = w_out;
-  for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int64_t e = list[i];
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t e = list ? int64_t(list[i]) : i;
     batch_dispatch<R, PROCS...>(proc, sg, e, cards[0], cards[1 + card_index[e]]);
   }
 }
 
 hipError_t launch_exact_list(int family, int precision, int proc, const double* mom, const int32_t* list,
-                             const unsigned int* count, const int32_t* card_index, const CardPair* cards,
-                             const double* w_in, double* w_out, int grid, hipStream_t s) {
+                             const unsigned int* count, int64_t n_all, const int32_t* card_index,
+                             const CardPair* cards, const double* w_in, double* w_out, int grid, hipStream_t s) {
   if (family != kFamilyElectroweak) return hipErrorInvalidValue;
   if (precision == kPrecFP64)
     hipLaunchKernelGGL((exact_list_kernel<double, Proc_ee_mumu, Proc_uu_eeg>), dim3(grid), dim3(256), 0, s, proc, mom,
-                       list, count, card_index, cards, w_in, w_out);
+                       list, count, n_all, card_index, cards, w_in, w_out);
   else
     hipLaunchKernelGGL((exact_list_kernel<float, Proc_ee_mumu, Proc_uu_eeg>), dim3(grid), dim3(256), 0, s, proc, mom,
-                       list, count, card_index, cards, w_in, w_out);
+                       list, count, n_all, card_index, cards, w_in, w_out);
   return hipGetLastError();
 }
 

@@ -7,24 +7,78 @@
 
 namespace rwgt {
 
-enum { kMlpBF16 = 0, kMlpFP32 = 1 };   // operand type: BF16 on the matrix cores, or FP32 on the VALU
+// Operand type of one layer: BF16 on the matrix cores, or FP32 on the VALU.
+// kMlpSplit (forward GEMM only): FP32 operands on the matrix cores as high
+// and low BF16 parts.
+enum { kMlpBF16 = 0, kMlpFP32 = 1, kMlpSplit = 2 };
+// Input feature maps (rwgt_mlp_set_features).
+enum { kFeatRaw = 0, kFeatPhys = 1 };
+constexpr int kMlpMaxIn = 32;          // inputs are padded to one 32-wide block
+constexpr int kMlpCardParams = 3;      // M_Z, Gamma_Z, sin^2 theta_W
+constexpr int kMlpMaxHidden = 8;       // width x width layers of the fused inference kernel
 
-hipError_t mlp_gemm(int mode, const void* A, const void* B, int M, int N, int K, const float* bias, float* Cf,
-                    void* Ct, int act, hipStream_t s);
-hipError_t mlp_transpose(int mode, const void* in, bool in_f32, void* out, int R, int C, hipStream_t s);
-hipError_t mlp_silu_bwd(int mode, const float* dh, const float* z, float* g, void* gt, int64_t n, hipStream_t s);
+struct FeatureMap {
+  int kind = kFeatRaw;
+  int npart = 0;
+  int res_a = 2, res_b = 3;            // the resonant pair of the propagator features
+  double mz0 = 0.0, wz0 = 0.0;         // original card's Z mass and width
+};
+
+inline int feature_count(int kind, int npart) {
+  return kind == kFeatRaw ? npart * 4 + kMlpCardParams : 1 + npart * (npart - 1) / 2 + kMlpCardParams + 4;
+}
+
+// Arguments of the fused inference kernel (features, every layer, heads and
+// the gate in one pass; hidden width 128 or 256, BF16 hidden layers).
+struct InferArgs {
+  const double* mom = nullptr;         // [nevt][npart][4]
+  const int32_t* ev = nullptr;         // row -> event (NULL: identity)
+  const int32_t* cidx = nullptr;       // row -> card
+  const float* cpar = nullptr;         // [ncards][3]
+  int64_t n = 0;                       // rows
+  FeatureMap fm;
+  const float* mean = nullptr;         // [32] standardisation (padded: 0 / 1)
+  const float* stdv = nullptr;
+  const void* w0hi = nullptr;          // first layer, packed BF16 high and low parts
+  const void* w0lo = nullptr;
+  const float* b0 = nullptr;
+  const void* wh = nullptr;            // hidden layers, packed BF16, one after the other
+  const float* bh = nullptr;           // their biases, [nh][width]
+  int nh = 0;                          // number of width x width layers
+  const float* whead = nullptr;        // head layer FP32 [32][width] (rows 0, 1 used)
+  const float* bhead = nullptr;
+  float ym = 0.0f, ys = 1.0f;          // target scale: mu = mu' ys + ym, s = s' + log ys
+  float k_cal = 1.0f, threshold = 0.0f;
+  const double* w_in = nullptr;        // gate (w_out non-NULL)
+  double* w_out = nullptr;
+  int32_t* list = nullptr;
+  unsigned int* count = nullptr;
+  float* heads = nullptr;              // [n][2] (nullable)
+};
+
+hipError_t mlp_gemm(int tin, int tout, const void* A, const void* B, int M, int N, int K, const float* bias,
+                    float* Cf, void* Ct, int act, hipStream_t s);
+hipError_t mlp_transpose(int tin, int tout, const void* in, void* out, int R, int C, hipStream_t s);
+hipError_t mlp_silu_bwd(int tout, const float* dh, const float* z, float* g, void* gt, int64_t n, hipStream_t s);
 hipError_t mlp_colsum(const float* g, float* db, int R, int C, hipStream_t s);
-hipError_t mlp_loss_grad(int mode, const float* z, const float* y, int n_valid, int rows, int ld, float lambda,
-                         float* g, void* gt, float* loss, hipStream_t s);
-hipError_t mlp_adam(int mode, float* w, const float* grad, float* m, float* v, void* wt, void* wtt, int rows,
+hipError_t mlp_loss_grad(int tout, const float* z, const float* y, int n_valid, int rows, int ld, float lambda,
+                         float ym, float ys, float* g, void* gt, float* loss, hipStream_t s);
+hipError_t mlp_adam(int tout, float* w, const float* grad, float* m, float* v, void* wt, void* wtt, int rows,
                     int cols, int mask_rows, int mask_cols, float lr, float b1, float b2, float eps, float c1,
                     float c2, hipStream_t s);
-hipError_t mlp_convert(int mode, const float* in, void* out, void* outt, int rows, int cols, hipStream_t s);
-hipError_t mlp_features(int mode, const double* mom, int npart, const int32_t* ev, const int32_t* cidx,
-                        const float* cpar, int nparam, const float* mean, const float* stdv, void* x, int64_t n,
-                        int64_t rows, int ld, hipStream_t s);
+hipError_t mlp_convert(int tout, const float* in, void* out, void* outt, int rows, int cols, hipStream_t s);
+hipError_t mlp_features(const FeatureMap& fm, const double* mom, const int32_t* ev, const int32_t* cidx,
+                        const float* cpar, const float* mean, const float* stdv, float* x, int64_t n, int64_t rows,
+                        int ld, hipStream_t s);
+hipError_t mlp_heads(const float* z, int ld, int64_t n, float ym, float ys, float* out, int ld_out, hipStream_t s);
 hipError_t mlp_log_ratio(const double* w_new, const double* w_old, float* y, int64_t n, hipStream_t s);
-hipError_t mlp_gate(const float* z, int ld, int64_t n, float k_cal, float threshold, const double* w_in,
-                    double* w_out, int32_t* list, unsigned int* count, hipStream_t s);
+hipError_t mlp_gate(const float* z, int ld, int64_t n, float ym, float ys, float k_cal, float threshold,
+                    const double* w_in, double* w_out, int32_t* list, unsigned int* count, hipStream_t s);
+hipError_t mlp_pack(const float* w, int ld, int rows_used, int cols_used, int nblocks, int nchunks, void* hi,
+                    void* lo, hipStream_t s);
+hipError_t mlp_infer(int width, const InferArgs& a, hipStream_t s);
+// sums[0..ld) += column sums of x [n][ld], sums[ld..2ld) += sums of squares
+// (FP64); clear: zero sums first.
+hipError_t mlp_moments(const float* x, int64_t n, int ld, double* sums, bool clear, hipStream_t s);
 
 }  // namespace rwgt

@@ -2,18 +2,27 @@
 // layers) predicting the log of the reweighting ratio and the log of its own
 // error, trained and evaluated on the GPU.
 //
-//   gemm_nt    C[M x N] = A[M x K] . B[N x K]^T (row-major, K contiguous), FP32
-//              accumulation; BF16 operands on v_mfma_f32_32x32x16_bf16 (one
-//              wave per 32 x 32 tile) or FP32 operands on the VALU (the
-//              gradient-check form).  Epilogue: + bias, the FP32 result and/or
-//              the SiLU (or identity) in the operand type for the next layer.
+// Training runs layer by layer; each layer has its own operand type.  In a
+// BF16 network the first layer (whose inputs locate the Z resonance) and the
+// two-row head are FP32 on the VALU and the width x width hidden layers are
+// BF16 on the matrix cores, all with FP32 accumulation and FP32 master
+// weights.
+//
+//   gemm_nt    C[M x N] = A[M x K] . B[N x K]^T (row-major, K contiguous).
+//              BF16 operands on v_mfma_f32_32x32x16_bf16 (one wave per
+//              32 x 32 tile) or FP32 operands on the VALU.  Epilogue: + bias,
+//              the FP32 result and/or the SiLU (or identity) in the next
+//              layer's operand type.
 //   silu_bwd   G = dH * silu'(Z)
 //   colsum     db = sum over rows of G
 //   loss_grad  Gaussian-error loss of the two heads and its gradient
 //   adam       FP32 master weights, moments, and the operand-type copies W, W^T
-//   features   standardised [momenta, card parameters] rows
+//   features   standardised input rows (raw or physics feature map)
 //   gate       w' = w exp(mu) where the predicted error is small; the others
 //              are listed for the exact path
+//   pack       weights in the per-lane order of the fused kernel's A operands
+//   infer      the fused inference pass: features, every layer, the heads and
+//              the gate for 32 rows per wave, activations kept in registers
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -32,9 +41,71 @@ __device__ __forceinline__ float silu_grad(float z) {
   return s * (1.0f + z * (1.0f - s));
 }
 
+// ------------------------------------------------------------ feature maps
+// Raw map: [momenta (NPART x 4), M_Z, Gamma_Z, sin^2 theta_W].
+// Physics map: with s_hat = 2 p0.p1 and s_ij = 2 pi.pj,
+//   [log s_hat, log(|s_ij| / s_hat) for i < j, M_Z, Gamma_Z, sin^2 theta_W,
+//    asinh Re chi, asinh Im chi, asinh Re chi0, asinh Im chi0]
+// where chi = s / (s - M^2 + i M Gamma) at s = s_ab of the resonant pair,
+// under the card (chi) and under the original card (chi0).  Computed in FP64
+// from the FP64 momenta, stored as FP32; unused slots are zero.
+template <int NPART, int KIND>
+__device__ __forceinline__ void feature_row(const FeatureMap& fm, const double (&p)[NPART * 4], const float (&card)[3],
+                                            float (&f)[kMlpMaxIn]) {
+#pragma unroll
+  for (int k = 0; k < kMlpMaxIn; ++k) f[k] = 0.0f;
+  if constexpr (KIND == kFeatRaw) {
+#pragma unroll
+    for (int k = 0; k < NPART * 4; ++k) f[k] = float(p[k]);
+#pragma unroll
+    for (int j = 0; j < kMlpCardParams; ++j) f[NPART * 4 + j] = card[j];
+  } else {
+    auto dot2 = [&](int i, int j) {
+      return 2.0 * (p[4 * i] * p[4 * j] - p[4 * i + 1] * p[4 * j + 1] - p[4 * i + 2] * p[4 * j + 2] -
+                    p[4 * i + 3] * p[4 * j + 3]);
+    };
+    const double shat = dot2(0, 1);
+    f[0] = float(log(shat));
+    double s_res = 0.0;
+    int k = 1;
+#pragma unroll
+    for (int i = 0; i < NPART; ++i)
+#pragma unroll
+      for (int j = i + 1; j < NPART; ++j) {
+        const double sij = dot2(i, j);
+        f[k++] = float(log(fmax(fabs(sij) / shat, 1e-300)));
+        if ((i == fm.res_a && j == fm.res_b) || (i == fm.res_b && j == fm.res_a)) s_res = sij;
+      }
+#pragma unroll
+    for (int j = 0; j < kMlpCardParams; ++j) f[k++] = card[j];
+    auto chi = [&](double m, double w, float& re, float& im) {
+      const double x = s_res - m * m, y = m * w;
+      const double d = x * x + y * y;
+      re = float(asinh(s_res * x / d));
+      im = float(asinh(-s_res * y / d));
+    };
+    chi(double(card[0]), double(card[1]), f[k], f[k + 1]);
+    chi(fm.mz0, fm.wz0, f[k + 2], f[k + 3]);
+  }
+}
+
+__device__ __forceinline__ void standardise(float (&f)[kMlpMaxIn], const float* __restrict__ mean,
+                                            const float* __restrict__ stdv) {
+#pragma unroll
+  for (int k = 0; k < kMlpMaxIn; ++k) f[k] = (f[k] - mean[k]) / stdv[k];
+}
+
+template <int NPART>
+__device__ __forceinline__ void load_event(const double* __restrict__ mom, int64_t e, double (&p)[NPART * 4]) {
+#pragma unroll
+  for (int k = 0; k < NPART * 4; ++k) p[k] = mom[e * (NPART * 4) + k];
+}
+
+// ------------------------------------------------------------------ GEMMs
+template <class TO>
 __global__ __launch_bounds__(64) void gemm_nt_bf16(const bf16* __restrict__ A, const bf16* __restrict__ B, int M,
                                                    int N, int K, const float* __restrict__ bias,
-                                                   float* __restrict__ Cf, bf16* __restrict__ Ct, int act) {
+                                                   float* __restrict__ Cf, TO* __restrict__ Ct, int act) {
   const int ntn = N / 32;
   const int tm = blockIdx.x / ntn, tn = blockIdx.x % ntn;
   const int l = threadIdx.x;
@@ -53,13 +124,52 @@ __global__ __launch_bounds__(64) void gemm_nt_bf16(const bf16* __restrict__ A, c
     const int row = tm * 32 + 8 * (i >> 2) + 4 * (l >> 5) + (i & 3);
     const float v = acc[i] + bb;
     if (Cf) Cf[size_t(row) * N + col] = v;
-    if (Ct) Ct[size_t(row) * N + col] = bf16(act ? silu(v) : v);
+    if (Ct) Ct[size_t(row) * N + col] = TO(act ? silu(v) : v);
   }
 }
 
+// FP32 operands through the matrix cores as high and low BF16 parts: three
+// products hi.hi + hi.lo + lo.hi per step (relative error about 2^-16), the
+// same arithmetic as the fused kernel's first layer.
+template <class TO>
+__global__ __launch_bounds__(64) void gemm_nt_split(const float* __restrict__ A, const float* __restrict__ B, int M,
+                                                    int N, int K, const float* __restrict__ bias,
+                                                    float* __restrict__ Cf, TO* __restrict__ Ct, int act) {
+  const int ntn = N / 32;
+  const int tm = blockIdx.x / ntn, tn = blockIdx.x % ntn;
+  const int l = threadIdx.x;
+  const float* a_row = A + size_t(tm * 32 + (l & 31)) * K + 8 * (l >> 5);
+  const float* b_row = B + size_t(tn * 32 + (l & 31)) * K + 8 * (l >> 5);
+  f32x16_t acc = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    bf16x8_t ah, al, bh, bl;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const float a = a_row[k0 + s], b = b_row[k0 + s];
+      ah[s] = bf16(a);
+      al[s] = bf16(a - float(ah[s]));
+      bh[s] = bf16(b);
+      bl[s] = bf16(b - float(bh[s]));
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+  }
+  const int col = tn * 32 + (l & 31);
+  const float bb = bias ? bias[col] : 0.0f;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int row = tm * 32 + 8 * (i >> 2) + 4 * (l >> 5) + (i & 3);
+    const float v = acc[i] + bb;
+    if (Cf) Cf[size_t(row) * N + col] = v;
+    if (Ct) Ct[size_t(row) * N + col] = TO(act ? silu(v) : v);
+  }
+}
+
+template <class TO>
 __global__ __launch_bounds__(256) void gemm_nt_f32(const float* __restrict__ A, const float* __restrict__ B, int M,
                                                    int N, int K, const float* __restrict__ bias,
-                                                   float* __restrict__ Cf, float* __restrict__ Ct, int act) {
+                                                   float* __restrict__ Cf, TO* __restrict__ Ct, int act) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(M) * N) return;
   const int row = int(idx / N), col = int(idx % N);
@@ -69,7 +179,7 @@ __global__ __launch_bounds__(256) void gemm_nt_f32(const float* __restrict__ A, 
   for (int k = 0; k < K; ++k) s = fmaf(a[k], b[k], s);
   const float v = s + (bias ? bias[col] : 0.0f);
   if (Cf) Cf[idx] = v;
-  if (Ct) Ct[idx] = act ? silu(v) : v;
+  if (Ct) Ct[idx] = TO(act ? silu(v) : v);
 }
 
 // out[c][r] = in[r][c] converted to TO
@@ -114,14 +224,16 @@ __global__ __launch_bounds__(256) void colsum(const float* __restrict__ g, float
   if (threadIdx.x == 0) db[c] = part[0];
 }
 
-// Heads: mu = z[r][0] (log ratio), s = z[r][1] (log of its error).  Per row
-//   loss = 1/2 (y - mu)^2 + lambda (1/2 r^2 exp(-2 s) + s),  r = y - mu held fixed
-// averaged over the n_valid rows; the gradient goes to g (both as FP32 and in
-// the operand type), the loss sum to *loss.
+// Heads: mu = z[r][0], s = z[r][1] in standardised target units
+// (y' = (y - ym) / ys).  Per row
+//   loss = 1/2 (y' - mu)^2 + lambda (1/2 r^2 exp(-2 s) + s),  r = y' - mu held fixed
+// averaged over the n_valid rows; the gradient goes to g (FP32) and gt (the
+// head's operand type), the loss sum to *loss.
 template <class T>
 __global__ __launch_bounds__(256) void loss_grad(const float* __restrict__ z, const float* __restrict__ y, int n_valid,
-                                                 int rows, int ld, float lambda, float* __restrict__ g,
-                                                 T* __restrict__ gt, float* __restrict__ loss) {
+                                                 int rows, int ld, float lambda, float ym, float ys,
+                                                 float* __restrict__ g, T* __restrict__ gt,
+                                                 float* __restrict__ loss) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= rows) return;
   float l = 0.0f;
@@ -132,7 +244,7 @@ __global__ __launch_bounds__(256) void loss_grad(const float* __restrict__ z, co
   if (r < n_valid) {
     // log-error head clamped at -15 (its gradient is zero below)
     const float mu = z[size_t(r) * ld], s_raw = z[size_t(r) * ld + 1], s = fmaxf(s_raw, -15.0f);
-    const float res = y[r] - mu;
+    const float res = (y[r] - ym) / ys - mu;
     const float e2 = __expf(-2.0f * s);
     const float inv = 1.0f / float(n_valid);
     const float g0 = -res * inv;
@@ -149,8 +261,8 @@ __global__ __launch_bounds__(256) void loss_grad(const float* __restrict__ z, co
 }
 
 // Adam on FP32 master weights w [rows][cols]; writes the operand-type copy wt
-// and its transpose wtt [cols][rows] (if non-null).  mask_rows: rows beyond it
-// are padding and stay zero.
+// and its transpose wtt [cols][rows] (if non-null).  mask_rows/mask_cols:
+// entries beyond them are padding and stay zero.
 template <class T>
 __global__ __launch_bounds__(256) void adam(float* __restrict__ w, const float* __restrict__ grad,
                                             float* __restrict__ m, float* __restrict__ v, T* __restrict__ wt,
@@ -182,37 +294,53 @@ __global__ __launch_bounds__(256) void convert_k(const float* __restrict__ in, T
   if (outt) outt[size_t(i % cols) * rows + i / cols] = T(in[i]);
 }
 
-// x[r][0..n_in) = (raw - mean) / std, raw = [momenta of event ev[r] (npart*4),
-// params of card cidx[r] (nparam)], padded with zeros to ld columns; rows
-// >= n are zero.
-template <class T>
-__global__ __launch_bounds__(256) void features_k(const double* __restrict__ mom, int npart,
+// x[r][0..ld) = standardised feature row of (event ev[r] (NULL: r), card
+// cidx[r]); rows >= n are zero.
+template <int NPART, int KIND>
+__global__ __launch_bounds__(256) void features_k(const FeatureMap fm, const double* __restrict__ mom,
                                                   const int32_t* __restrict__ ev, const int32_t* __restrict__ cidx,
-                                                  const float* __restrict__ cpar, int nparam,
-                                                  const float* __restrict__ mean, const float* __restrict__ stdv,
-                                                  T* __restrict__ x, int64_t n, int64_t rows, int ld) {
+                                                  const float* __restrict__ cpar, const float* __restrict__ mean,
+                                                  const float* __restrict__ stdv, float* __restrict__ x, int64_t n,
+                                                  int64_t rows, int ld) {
   const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= rows) return;
-  const int nin = npart * 4 + nparam;
-  for (int c = 0; c < ld; ++c) {
-    float v = 0.0f;
-    if (r < n && c < nin) {
-      const int64_t e = ev ? ev[r] : r;
-      const float raw = c < npart * 4 ? float(mom[e * npart * 4 + c]) : cpar[size_t(cidx[r]) * nparam + c - npart * 4];
-      v = (raw - mean[c]) / stdv[c];
-    }
-    x[size_t(r) * ld + c] = T(v);
+  float f[kMlpMaxIn];
+  if (r < n) {
+    const int64_t e = ev ? int64_t(ev[r]) : r;
+    const int c = cidx[r];
+    double p[NPART * 4];
+    load_event<NPART>(mom, e, p);
+    const float card[3] = {cpar[3 * c], cpar[3 * c + 1], cpar[3 * c + 2]};
+    feature_row<NPART, KIND>(fm, p, card, f);
+    standardise(f, mean, stdv);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kMlpMaxIn; ++k) f[k] = 0.0f;
   }
+#pragma unroll
+  for (int k = 0; k < kMlpMaxIn; ++k)
+    if (k < ld) x[size_t(r) * ld + k] = f[k];
+}
+
+// Heads in target units: out[r][0] = z0 ys + ym, out[r][1] = z1 + log ys,
+// further columns (ld_out > 2) copied.
+__global__ __launch_bounds__(256) void heads_k(const float* __restrict__ z, int ld, int64_t n, float ym, float ys,
+                                               float* __restrict__ out, int ld_out) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  out[size_t(r) * ld_out] = z[size_t(r) * ld] * ys + ym;
+  out[size_t(r) * ld_out + 1] = z[size_t(r) * ld + 1] + logf(ys);
+  for (int c = 2; c < ld_out; ++c) out[size_t(r) * ld_out + c] = z[size_t(r) * ld + c];
 }
 
 // Surrogate weights where k exp(s) <= threshold; the other events are listed.
-__global__ __launch_bounds__(256) void gate_k(const float* __restrict__ z, int ld, int64_t n, float k_cal,
-                                              float threshold, const double* __restrict__ w_in,
+__global__ __launch_bounds__(256) void gate_k(const float* __restrict__ z, int ld, int64_t n, float ym, float ys,
+                                              float k_cal, float threshold, const double* __restrict__ w_in,
                                               double* __restrict__ w_out, int32_t* __restrict__ list,
                                               unsigned int* __restrict__ count) {
   const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  const float mu = z[size_t(r) * ld], s = z[size_t(r) * ld + 1];
+  const float mu = z[size_t(r) * ld] * ys + ym, s = z[size_t(r) * ld + 1] + logf(ys);
   if (k_cal * __expf(s) <= threshold && isfinite(mu)) {
     w_out[r] = w_in[r] * exp(double(mu));
   } else {
@@ -230,44 +358,243 @@ __global__ __launch_bounds__(256) void log_ratio_k(const double* __restrict__ w_
   y[i] = o != 0.0 ? float(log(w_new[i] / o)) : 0.0f;
 }
 
+// A-operand order of the fused kernel: block b of 32 output rows, chunk c of
+// 16 inputs, lane l, slot s holds W[32 b + l % 32][16 c + 8 (s / 4) + 4 (l / 32) + s % 4]
+// (the order in which a wave's accumulators come out, so one layer's output
+// is the next layer's B operand without moving data between lanes).  hi is
+// the BF16 rounding of W, lo (optional) the BF16 rounding of the remainder.
+__global__ __launch_bounds__(256) void pack_k(const float* __restrict__ w, int ld, int rows_used, int cols_used,
+                                              int nblocks, int nchunks, bf16* __restrict__ hi, bf16* __restrict__ lo) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(nblocks) * nchunks * 512) return;
+  const int s = int(t & 7), l = int((t >> 3) & 63);
+  const int64_t q = t >> 9;
+  const int c = int(q % nchunks), b = int(q / nchunks);
+  const int row = 32 * b + (l & 31);
+  const int col = 16 * c + 8 * (s >> 2) + 4 * (l >> 5) + (s & 3);
+  const float v = (row < rows_used && col < cols_used) ? w[size_t(row) * ld + col] : 0.0f;
+  const bf16 vh = bf16(v);
+  hi[t] = vh;
+  if (lo) lo[t] = bf16(v - float(vh));
+}
+
+// Column sums of x and x^2 (FP64) over n rows of ld columns, added to
+// sums[0..ld) and sums[ld..2 ld).
+__global__ __launch_bounds__(256) void moments_k(const float* __restrict__ x, int64_t n, int ld,
+                                                 double* __restrict__ sums) {
+  __shared__ double part[2][kMlpMaxIn][8];
+  const int c = threadIdx.x % kMlpMaxIn, q = threadIdx.x / kMlpMaxIn;   // 32 columns x 8 row groups
+  double s1 = 0.0, s2 = 0.0;
+  if (c < ld)
+    for (int64_t r = int64_t(blockIdx.x) * 8 + q; r < n; r += int64_t(gridDim.x) * 8) {
+      const double v = x[r * ld + c];
+      s1 += v;
+      s2 += v * v;
+    }
+  part[0][c][q] = s1;
+  part[1][c][q] = s2;
+  __syncthreads();
+  if (q == 0 && c < ld) {
+    double t1 = 0.0, t2 = 0.0;
+    for (int k = 0; k < 8; ++k) {
+      t1 += part[0][c][k];
+      t2 += part[1][c][k];
+    }
+    atomicAdd(&sums[c], t1);
+    atomicAdd(&sums[ld + c], t2);
+  }
+}
+
+__global__ void zero_f64(double* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
 __global__ void zero_u32(unsigned int* p) { *p = 0u; }
 __global__ void zero_f32(float* p) { *p = 0.0f; }
+
+__device__ __forceinline__ f32x16_t mfma_bf16(bf16x8_t a, bf16x8_t b, f32x16_t c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// Fused inference: one wave per 32 rows (lanes l and l + 32 share row l % 32
+// and hold complementary halves of its features).  Transposed products
+// H'^T = W H^T: A = packed weights, B = this wave's activations, so the
+// accumulators of output block b are chunks 2b and 2b+1 of the next B operand.
+// The first layer runs on the high and low BF16 parts of its FP32 weights and
+// inputs (three products: hi.hi + hi.lo + lo.hi); the hidden layers on BF16
+// weights and activations as in training; the head in FP32 on the VALU.
+template <int W, int NPART, int KIND>
+__global__ __launch_bounds__(256) void infer_k(const InferArgs a) {
+  constexpr int NB = W / 32, NC = W / 16;
+  const int lane = threadIdx.x & 63, h = lane >> 5;
+  const int64_t e0 = ((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6) * 32;
+  if (e0 >= a.n) return;                              // whole waves only
+  const int64_t r = e0 + (lane & 31);
+  const bool valid = r < a.n;
+  const int64_t rr = valid ? r : a.n - 1;
+
+  float f[kMlpMaxIn];
+  {
+    const int64_t e = a.ev ? int64_t(a.ev[rr]) : rr;
+    const int c = a.cidx[rr];
+    double p[NPART * 4];
+    load_event<NPART>(a.mom, e, p);
+    const float card[3] = {a.cpar[3 * c], a.cpar[3 * c + 1], a.cpar[3 * c + 2]};
+    feature_row<NPART, KIND>(a.fm, p, card, f);
+    standardise(f, a.mean, a.stdv);
+  }
+  // this lane's half of the inputs (a bitwise blend, so that the choice does
+  // not become a lane-dependent index into f)
+  const unsigned int pick = h ? ~0u : 0u;
+  bf16x8_t xh[2], xl[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int k = 16 * c + 8 * (s >> 2) + (s & 3);
+      const unsigned int u0 = __float_as_uint(f[k]), u1 = __float_as_uint(f[k + 4]);
+      const float v = __uint_as_float(u0 ^ ((u0 ^ u1) & pick));
+      const bf16 vh = bf16(v);
+      xh[c][s] = vh;
+      xl[c][s] = bf16(v - float(vh));
+    }
+
+  bf16x8_t act[NC];
+  {
+    const bf16x8_t* w0h = static_cast<const bf16x8_t*>(a.w0hi);
+    const bf16x8_t* w0l = static_cast<const bf16x8_t*>(a.w0lo);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      f32x16_t acc = {};
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const bf16x8_t ah = w0h[(b * 2 + c) * 64 + lane];
+        const bf16x8_t al = w0l[(b * 2 + c) * 64 + lane];
+        acc = mfma_bf16(ah, xh[c], acc);
+        acc = mfma_bf16(ah, xl[c], acc);
+        acc = mfma_bf16(al, xh[c], acc);
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int fo = 32 * b + 8 * (i >> 2) + 4 * h + (i & 3);
+        act[2 * b + (i >> 3)][i & 7] = bf16(silu(acc[i] + a.b0[fo]));
+      }
+    }
+  }
+  const bf16x8_t* wh = static_cast<const bf16x8_t*>(a.wh);
+  for (int l = 0; l + 1 < a.nh; ++l) {
+    const bf16x8_t* wl = wh + size_t(l) * NB * NC * 64;
+    const float* bl = a.bh + size_t(l) * W;
+    bf16x8_t nxt[NC];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      f32x16_t acc = {};
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc = mfma_bf16(wl[(b * NC + c) * 64 + lane], act[c], acc);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int fo = 32 * b + 8 * (i >> 2) + 4 * h + (i & 3);
+        nxt[2 * b + (i >> 3)][i & 7] = bf16(silu(acc[i] + bl[fo]));
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) act[c] = nxt[c];
+  }
+  // last hidden layer, straight into the two FP32 heads
+  float mu = 0.0f, sg = 0.0f;
+  {
+    const bf16x8_t* wl = wh + size_t(a.nh - 1) * NB * NC * 64;
+    const float* bl = a.bh + size_t(a.nh - 1) * W;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      f32x16_t acc = {};
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc = mfma_bf16(wl[(b * NC + c) * 64 + lane], act[c], acc);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int fo = 32 * b + 8 * (i >> 2) + 4 * h + (i & 3);
+        const float v = silu(acc[i] + bl[fo]);
+        mu = fmaf(v, a.whead[fo], mu);
+        sg = fmaf(v, a.whead[W + fo], sg);
+      }
+    }
+  }
+  mu += __shfl_xor(mu, 32);
+  sg += __shfl_xor(sg, 32);
+  mu = (mu + a.bhead[0]) * a.ys + a.ym;
+  sg = sg + a.bhead[1] + logf(a.ys);
+
+  const bool mine = lane < 32 && valid;
+  if (a.heads && mine) {
+    a.heads[2 * r] = mu;
+    a.heads[2 * r + 1] = sg;
+  }
+  if (a.w_out) {
+    bool fb = false;
+    if (mine) {
+      if (a.k_cal * __expf(sg) <= a.threshold && isfinite(mu))
+        a.w_out[r] = a.w_in[r] * exp(double(mu));
+      else
+        fb = true;
+    }
+    const uint64_t m = __ballot(fb);
+    if (m) {                                          // wave-uniform
+      unsigned int base = 0;
+      if (lane == 0) base = atomicAdd(a.count, unsigned(__popcll(m)));
+      base = __shfl(base, 0);
+      if (fb) a.list[base + __popcll(m & ((uint64_t(1) << lane) - 1))] = int32_t(r);
+    }
+  }
+}
 
 // ----------------------------------------------------------------- launchers
 static unsigned blocks_for(int64_t n, int b = 256) { return unsigned((n + b - 1) / b); }
 
-hipError_t mlp_gemm(int mode, const void* A, const void* B, int M, int N, int K, const float* bias, float* Cf,
-                    void* Ct, int act, hipStream_t s) {
-  if (M % 32 || N % 32 || K % 16) return hipErrorInvalidValue;
-  if (mode == kMlpBF16) {
-    hipLaunchKernelGGL(gemm_nt_bf16, dim3((M / 32) * (N / 32)), dim3(64), 0, s, static_cast<const bf16*>(A),
-                       static_cast<const bf16*>(B), M, N, K, bias, Cf, static_cast<bf16*>(Ct), act);
-  } else {
-    hipLaunchKernelGGL(gemm_nt_f32, dim3(blocks_for(int64_t(M) * N)), dim3(256), 0, s,
+template <class TO>
+static void gemm_launch(int tin, const void* A, const void* B, int M, int N, int K, const float* bias, float* Cf,
+                        void* Ct, int act, hipStream_t s) {
+  if (tin == kMlpSplit)
+    hipLaunchKernelGGL(gemm_nt_split<TO>, dim3((M / 32) * (N / 32)), dim3(64), 0, s, static_cast<const float*>(A),
+                       static_cast<const float*>(B), M, N, K, bias, Cf, static_cast<TO*>(Ct), act);
+  else if (tin == kMlpBF16)
+    hipLaunchKernelGGL(gemm_nt_bf16<TO>, dim3((M / 32) * (N / 32)), dim3(64), 0, s, static_cast<const bf16*>(A),
+                       static_cast<const bf16*>(B), M, N, K, bias, Cf, static_cast<TO*>(Ct), act);
+  else
+    hipLaunchKernelGGL(gemm_nt_f32<TO>, dim3(blocks_for(int64_t(M) * N)), dim3(256), 0, s,
                        static_cast<const float*>(A), static_cast<const float*>(B), M, N, K, bias, Cf,
-                       static_cast<float*>(Ct), act);
-  }
+                       static_cast<TO*>(Ct), act);
+}
+
+hipError_t mlp_gemm(int tin, int tout, const void* A, const void* B, int M, int N, int K, const float* bias,
+                    float* Cf, void* Ct, int act, hipStream_t s) {
+  if (tin != kMlpFP32 && (M % 32 || N % 32 || K % 16)) return hipErrorInvalidValue;
+  if (tout == kMlpBF16)
+    gemm_launch<bf16>(tin, A, B, M, N, K, bias, Cf, Ct, act, s);
+  else
+    gemm_launch<float>(tin, A, B, M, N, K, bias, Cf, Ct, act, s);
   return hipGetLastError();
 }
 
-hipError_t mlp_transpose(int mode, const void* in, bool in_f32, void* out, int R, int C, hipStream_t s) {
+hipError_t mlp_transpose(int tin, int tout, const void* in, void* out, int R, int C, hipStream_t s) {
   const dim3 grid((C + 31) / 32, (R + 31) / 32);
-  if (mode == kMlpBF16) {
-    if (in_f32)
-      hipLaunchKernelGGL((transpose_k<float, bf16>), grid, dim3(256), 0, s, static_cast<const float*>(in),
-                         static_cast<bf16*>(out), R, C);
-    else
-      hipLaunchKernelGGL((transpose_k<bf16, bf16>), grid, dim3(256), 0, s, static_cast<const bf16*>(in),
-                         static_cast<bf16*>(out), R, C);
-  } else {
+  if (tin == kMlpFP32 && tout == kMlpBF16)
+    hipLaunchKernelGGL((transpose_k<float, bf16>), grid, dim3(256), 0, s, static_cast<const float*>(in),
+                       static_cast<bf16*>(out), R, C);
+  else if (tin == kMlpFP32)
     hipLaunchKernelGGL((transpose_k<float, float>), grid, dim3(256), 0, s, static_cast<const float*>(in),
                        static_cast<float*>(out), R, C);
-  }
+  else if (tout == kMlpBF16)
+    hipLaunchKernelGGL((transpose_k<bf16, bf16>), grid, dim3(256), 0, s, static_cast<const bf16*>(in),
+                       static_cast<bf16*>(out), R, C);
+  else
+    hipLaunchKernelGGL((transpose_k<bf16, float>), grid, dim3(256), 0, s, static_cast<const bf16*>(in),
+                       static_cast<float*>(out), R, C);
   return hipGetLastError();
 }
 
-hipError_t mlp_silu_bwd(int mode, const float* dh, const float* z, float* g, void* gt, int64_t n, hipStream_t s) {
-  if (mode == kMlpBF16)
+hipError_t mlp_silu_bwd(int tout, const float* dh, const float* z, float* g, void* gt, int64_t n, hipStream_t s) {
+  if (tout == kMlpBF16)
     hipLaunchKernelGGL(silu_bwd<bf16>, dim3(blocks_for(n)), dim3(256), 0, s, dh, z, g, static_cast<bf16*>(gt), n);
   else
     hipLaunchKernelGGL(silu_bwd<float>, dim3(blocks_for(n)), dim3(256), 0, s, dh, z, g, static_cast<float*>(gt), n);
@@ -279,23 +606,23 @@ hipError_t mlp_colsum(const float* g, float* db, int R, int C, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t mlp_loss_grad(int mode, const float* z, const float* y, int n_valid, int rows, int ld, float lambda,
-                         float* g, void* gt, float* loss, hipStream_t s) {
+hipError_t mlp_loss_grad(int tout, const float* z, const float* y, int n_valid, int rows, int ld, float lambda,
+                         float ym, float ys, float* g, void* gt, float* loss, hipStream_t s) {
   hipLaunchKernelGGL(zero_f32, dim3(1), dim3(1), 0, s, loss);
-  if (mode == kMlpBF16)
-    hipLaunchKernelGGL(loss_grad<bf16>, dim3(blocks_for(rows)), dim3(256), 0, s, z, y, n_valid, rows, ld, lambda, g,
-                       static_cast<bf16*>(gt), loss);
+  if (tout == kMlpBF16)
+    hipLaunchKernelGGL(loss_grad<bf16>, dim3(blocks_for(rows)), dim3(256), 0, s, z, y, n_valid, rows, ld, lambda, ym,
+                       ys, g, static_cast<bf16*>(gt), loss);
   else
-    hipLaunchKernelGGL(loss_grad<float>, dim3(blocks_for(rows)), dim3(256), 0, s, z, y, n_valid, rows, ld, lambda, g,
-                       static_cast<float*>(gt), loss);
+    hipLaunchKernelGGL(loss_grad<float>, dim3(blocks_for(rows)), dim3(256), 0, s, z, y, n_valid, rows, ld, lambda, ym,
+                       ys, g, static_cast<float*>(gt), loss);
   return hipGetLastError();
 }
 
-hipError_t mlp_adam(int mode, float* w, const float* grad, float* m, float* v, void* wt, void* wtt, int rows,
+hipError_t mlp_adam(int tout, float* w, const float* grad, float* m, float* v, void* wt, void* wtt, int rows,
                     int cols, int mask_rows, int mask_cols, float lr, float b1, float b2, float eps, float c1,
                     float c2, hipStream_t s) {
   const int64_t n = int64_t(rows) * cols;
-  if (mode == kMlpBF16)
+  if (tout == kMlpBF16)
     hipLaunchKernelGGL(adam<bf16>, dim3(blocks_for(n)), dim3(256), 0, s, w, grad, m, v, static_cast<bf16*>(wt),
                        static_cast<bf16*>(wtt), rows, cols, mask_rows, mask_cols, lr, b1, b2, eps, c1, c2);
   else
@@ -304,9 +631,9 @@ hipError_t mlp_adam(int mode, float* w, const float* grad, float* m, float* v, v
   return hipGetLastError();
 }
 
-hipError_t mlp_convert(int mode, const float* in, void* out, void* outt, int rows, int cols, hipStream_t s) {
+hipError_t mlp_convert(int tout, const float* in, void* out, void* outt, int rows, int cols, hipStream_t s) {
   const int64_t n = int64_t(rows) * cols;
-  if (mode == kMlpBF16)
+  if (tout == kMlpBF16)
     hipLaunchKernelGGL(convert_k<bf16>, dim3(blocks_for(n)), dim3(256), 0, s, in, static_cast<bf16*>(out),
                        static_cast<bf16*>(outt), rows, cols);
   else
@@ -315,15 +642,25 @@ hipError_t mlp_convert(int mode, const float* in, void* out, void* outt, int row
   return hipGetLastError();
 }
 
-hipError_t mlp_features(int mode, const double* mom, int npart, const int32_t* ev, const int32_t* cidx,
-                        const float* cpar, int nparam, const float* mean, const float* stdv, void* x, int64_t n,
-                        int64_t rows, int ld, hipStream_t s) {
-  if (mode == kMlpBF16)
-    hipLaunchKernelGGL(features_k<bf16>, dim3(blocks_for(rows)), dim3(256), 0, s, mom, npart, ev, cidx, cpar, nparam,
-                       mean, stdv, static_cast<bf16*>(x), n, rows, ld);
+hipError_t mlp_features(const FeatureMap& fm, const double* mom, const int32_t* ev, const int32_t* cidx,
+                        const float* cpar, const float* mean, const float* stdv, float* x, int64_t n, int64_t rows,
+                        int ld, hipStream_t s) {
+  const dim3 g(blocks_for(rows)), b(256);
+  if (fm.npart == 4 && fm.kind == kFeatRaw)
+    hipLaunchKernelGGL((features_k<4, kFeatRaw>), g, b, 0, s, fm, mom, ev, cidx, cpar, mean, stdv, x, n, rows, ld);
+  else if (fm.npart == 4)
+    hipLaunchKernelGGL((features_k<4, kFeatPhys>), g, b, 0, s, fm, mom, ev, cidx, cpar, mean, stdv, x, n, rows, ld);
+  else if (fm.npart == 5 && fm.kind == kFeatRaw)
+    hipLaunchKernelGGL((features_k<5, kFeatRaw>), g, b, 0, s, fm, mom, ev, cidx, cpar, mean, stdv, x, n, rows, ld);
+  else if (fm.npart == 5)
+    hipLaunchKernelGGL((features_k<5, kFeatPhys>), g, b, 0, s, fm, mom, ev, cidx, cpar, mean, stdv, x, n, rows, ld);
   else
-    hipLaunchKernelGGL(features_k<float>, dim3(blocks_for(rows)), dim3(256), 0, s, mom, npart, ev, cidx, cpar,
-                       nparam, mean, stdv, static_cast<float*>(x), n, rows, ld);
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t mlp_heads(const float* z, int ld, int64_t n, float ym, float ys, float* out, int ld_out, hipStream_t s) {
+  hipLaunchKernelGGL(heads_k, dim3(blocks_for(n)), dim3(256), 0, s, z, ld, n, ym, ys, out, ld_out);
   return hipGetLastError();
 }
 
@@ -332,12 +669,55 @@ hipError_t mlp_log_ratio(const double* w_new, const double* w_old, float* y, int
   return hipGetLastError();
 }
 
-hipError_t mlp_gate(const float* z, int ld, int64_t n, float k_cal, float threshold, const double* w_in,
-                    double* w_out, int32_t* list, unsigned int* count, hipStream_t s) {
+hipError_t mlp_gate(const float* z, int ld, int64_t n, float ym, float ys, float k_cal, float threshold,
+                    const double* w_in, double* w_out, int32_t* list, unsigned int* count, hipStream_t s) {
   hipLaunchKernelGGL(zero_u32, dim3(1), dim3(1), 0, s, count);
-  hipLaunchKernelGGL(gate_k, dim3(blocks_for(n)), dim3(256), 0, s, z, ld, n, k_cal, threshold, w_in, w_out, list,
-                     count);
+  hipLaunchKernelGGL(gate_k, dim3(blocks_for(n)), dim3(256), 0, s, z, ld, n, ym, ys, k_cal, threshold, w_in, w_out,
+                     list, count);
   return hipGetLastError();
+}
+
+hipError_t mlp_pack(const float* w, int ld, int rows_used, int cols_used, int nblocks, int nchunks, void* hi,
+                    void* lo, hipStream_t s) {
+  hipLaunchKernelGGL(pack_k, dim3(blocks_for(int64_t(nblocks) * nchunks * 512)), dim3(256), 0, s, w, ld, rows_used,
+                     cols_used, nblocks, nchunks, static_cast<bf16*>(hi), static_cast<bf16*>(lo));
+  return hipGetLastError();
+}
+
+hipError_t mlp_moments(const float* x, int64_t n, int ld, double* sums, bool clear, hipStream_t s) {
+  if (ld < 1 || ld > kMlpMaxIn) return hipErrorInvalidValue;
+  if (clear) hipLaunchKernelGGL(zero_f64, dim3(1), dim3(64), 0, s, sums, 2 * ld);
+  if (n > 0) {
+    const int64_t groups = (n + 7) / 8;
+    const unsigned grid = unsigned(groups < 4096 ? groups : 4096);
+    hipLaunchKernelGGL(moments_k, dim3(grid), dim3(256), 0, s, x, n, ld, sums);
+  }
+  return hipGetLastError();
+}
+
+template <int W>
+static hipError_t infer_launch(const InferArgs& a, hipStream_t s) {
+  const dim3 g(blocks_for(a.n, 128)), b(256);        // 4 waves x 32 rows per workgroup
+  if (a.fm.npart == 4 && a.fm.kind == kFeatRaw)
+    hipLaunchKernelGGL((infer_k<W, 4, kFeatRaw>), g, b, 0, s, a);
+  else if (a.fm.npart == 4)
+    hipLaunchKernelGGL((infer_k<W, 4, kFeatPhys>), g, b, 0, s, a);
+  else if (a.fm.npart == 5 && a.fm.kind == kFeatRaw)
+    hipLaunchKernelGGL((infer_k<W, 5, kFeatRaw>), g, b, 0, s, a);
+  else if (a.fm.npart == 5)
+    hipLaunchKernelGGL((infer_k<W, 5, kFeatPhys>), g, b, 0, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t mlp_infer(int width, const InferArgs& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  if (a.nh < 1 || a.nh > kMlpMaxHidden) return hipErrorInvalidValue;
+  if (a.w_out) hipLaunchKernelGGL(zero_u32, dim3(1), dim3(1), 0, s, a.count);
+  if (width == 128) return infer_launch<128>(a, s);
+  if (width == 256) return infer_launch<256>(a, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace rwgt

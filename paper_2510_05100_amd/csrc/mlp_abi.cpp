@@ -1,9 +1,11 @@
 // Host side of the surrogate network (rwgt_mlp_* in include/rwgt.h): FP32
-// master parameters and Adam moments on the device, operand-type copies
-// (BF16 or FP32) of every weight matrix and of its transpose, and the
-// forward / backward / update sequence of kernel launches.
+// master parameters and Adam moments on the device, operand-type copies of
+// every weight matrix and of its transpose, the forward / backward / update
+// sequence of kernel launches, and the packed weights of the fused inference
+// kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -22,17 +24,18 @@ namespace {
 
 size_t esize(int mode) { return mode == kMlpBF16 ? 2 : 4; }
 int pad32(int x) { return (x + 31) / 32 * 32; }
+int64_t pad64(int64_t x) { return (x + 63) / 64 * 64; }
+constexpr size_t kPackBytes = 512 * 2;      // one packed (block, chunk): 64 lanes x 8 BF16
 
 }  // namespace
-
 
 int rwgt_mlp::ensure_batch(int64_t rows) {
   if (rows <= bcap) return RWGT_OK;
   for (void* p : work) hipFree(p);
   work.clear();
   const int L = int(layers.size());
-  h.assign(L + 1, nullptr);
-  ht.assign(L + 1, nullptr);
+  h.assign(L, nullptr);
+  ht.assign(L, nullptr);
   z.assign(L, nullptr);
   g.assign(L, nullptr);
   gt.assign(L, nullptr);
@@ -44,18 +47,17 @@ int rwgt_mlp::ensure_batch(int64_t rows) {
     return e;
   };
   hipError_t e = hipSuccess;
-  for (int l = 0; l <= L && e == hipSuccess; ++l) {
-    const int width = l < L ? layers[l].in : layers[L - 1].out;
-    e = alloc(size_t(rows) * width * esize(mode), &h[l]);
-    if (e == hipSuccess) e = alloc(size_t(rows) * width * esize(mode), &ht[l]);
-  }
   for (int l = 0; l < L && e == hipSuccess; ++l) {
-    const size_t n = size_t(rows) * layers[l].out;
-    e = alloc(n * 4, reinterpret_cast<void**>(&z[l]));
+    const Layer& ly = layers[l];
+    const size_t es = esize(ly.mode);
+    if (l > 0) e = alloc(size_t(rows) * ly.in * es, &h[l]);     // h[0]: the caller's input rows
+    if (e == hipSuccess) e = alloc(size_t(rows) * ly.in * es, &ht[l]);
+    const size_t n = size_t(rows) * ly.out;
+    if (e == hipSuccess) e = alloc(n * 4, reinterpret_cast<void**>(&z[l]));
     if (e == hipSuccess) e = alloc(n * 4, reinterpret_cast<void**>(&g[l]));
-    if (e == hipSuccess) e = alloc(n * esize(mode), &gt[l]);
-    if (e == hipSuccess) e = alloc(n * esize(mode), &gtt[l]);
-    if (e == hipSuccess) e = alloc(size_t(rows) * layers[l].in * 4, reinterpret_cast<void**>(&dh[l]));
+    if (e == hipSuccess) e = alloc(n * es, &gt[l]);
+    if (e == hipSuccess) e = alloc(n * es, &gtt[l]);
+    if (e == hipSuccess && l > 0) e = alloc(size_t(rows) * ly.in * 4, reinterpret_cast<void**>(&dh[l]));
   }
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(mlp workspace)");
   bcap = rows;
@@ -64,23 +66,26 @@ int rwgt_mlp::ensure_batch(int64_t rows) {
 
 int rwgt_mlp::refresh_copies() {
   for (auto& ly : layers) {
-    hipError_t e = rwgt::mlp_convert(mode, ly.w, ly.wc, ly.wct, ly.out, ly.in, stream);
+    hipError_t e = rwgt::mlp_convert(ly.mode, ly.w, ly.wc, ly.wct, ly.out, ly.in, stream);
     if (e != hipSuccess) return hip_fail(e, "convert");
   }
+  pack_dirty = true;
   return RWGT_OK;
 }
 
-// Forward over rows (multiple of 64) of x (operand type, [rows][in0]); the
-// output head z[L-1] stays in FP32.
+// Forward over rows (multiple of 64) of x (FP32, [rows][in0]); z[l] holds
+// each layer's FP32 pre-activation, the head's output stays in z[L-1].
 int rwgt_mlp::forward(const void* x, int64_t rows) {
   const int L = int(layers.size());
   int rc = ensure_batch(rows);
   if (rc != RWGT_OK) return rc;
-  hipError_t e = hipMemcpyAsync(h[0], x, size_t(rows) * layers[0].in * esize(mode), hipMemcpyDeviceToDevice, stream);
+  x_in = x;
+  hipError_t e = hipSuccess;
   for (int l = 0; l < L && e == hipSuccess; ++l) {
     const bool last = l == L - 1;
-    e = rwgt::mlp_gemm(mode, h[l], layers[l].wc, int(rows), layers[l].out, layers[l].in, layers[l].b, z[l],
-                       last ? nullptr : h[l + 1], last ? 0 : 1, stream);
+    const Layer& ly = layers[l];
+    e = rwgt::mlp_gemm(ly.split ? rwgt::kMlpSplit : ly.mode, last ? ly.mode : layers[l + 1].mode, input(l), ly.wc,
+                       int(rows), ly.out, ly.in, ly.b, z[l], last ? nullptr : h[l + 1], last ? 0 : 1, stream);
   }
   if (e != hipSuccess) return hip_fail(e, "mlp forward");
   return RWGT_OK;
@@ -89,20 +94,24 @@ int rwgt_mlp::forward(const void* x, int64_t rows) {
 // Gradients of the loss into the per-layer gw/gb buffers (after forward).
 int rwgt_mlp::backward(const float* y, int64_t n_valid, int64_t rows) {
   const int L = int(layers.size());
-  const int ld = layers[L - 1].out;
-  hipError_t e = rwgt::mlp_loss_grad(mode, z[L - 1], y, int(n_valid), int(rows), ld, lambda, g[L - 1], gt[L - 1],
-                                     loss, stream);
+  const Layer& head = layers[L - 1];
+  hipError_t e = rwgt::mlp_loss_grad(head.mode, z[L - 1], y, int(n_valid), int(rows), head.out, lambda, ym, ys,
+                                     g[L - 1], gt[L - 1], loss, stream);
   for (int l = L - 1; l >= 0 && e == hipSuccess; --l) {
-    const auto& ly = layers[l];
-    // dW = G^T H: operands G^T [out][rows], H^T [in][rows]
-    e = rwgt::mlp_transpose(mode, g[l], true, gtt[l], int(rows), ly.out, stream);
-    if (e == hipSuccess) e = rwgt::mlp_transpose(mode, h[l], false, ht[l], int(rows), ly.in, stream);
-    if (e == hipSuccess) e = rwgt::mlp_gemm(mode, gtt[l], ht[l], ly.out, ly.in, int(rows), nullptr, ly.gw, nullptr, 0, stream);
+    const Layer& ly = layers[l];
+    // dW = G^T H: operands G^T [out][rows], H^T [in][rows] in this layer's type
+    e = rwgt::mlp_transpose(kMlpFP32, ly.mode, g[l], gtt[l], int(rows), ly.out, stream);
+    if (e == hipSuccess) e = rwgt::mlp_transpose(ly.mode, ly.mode, input(l), ht[l], int(rows), ly.in, stream);
+    if (e == hipSuccess)
+      e = rwgt::mlp_gemm(ly.mode, ly.mode, gtt[l], ht[l], ly.out, ly.in, int(rows), nullptr, ly.gw, nullptr, 0, stream);
     if (e == hipSuccess) e = rwgt::mlp_colsum(g[l], ly.gb, int(rows), ly.out, stream);
     if (l == 0 || e != hipSuccess) continue;
-    // dH = G W: operands G [rows][out], W^T [in][out]; then through SiLU
-    e = rwgt::mlp_gemm(mode, gt[l], ly.wct, int(rows), ly.in, ly.out, nullptr, dh[l], nullptr, 0, stream);
-    if (e == hipSuccess) e = rwgt::mlp_silu_bwd(mode, dh[l], z[l - 1], g[l - 1], gt[l - 1], rows * layers[l - 1].out, stream);
+    // dH = G W: operands G [rows][out], W^T [in][out]; then through SiLU into
+    // the previous layer's gradient (FP32 and its operand type)
+    e = rwgt::mlp_gemm(ly.mode, ly.mode, gt[l], ly.wct, int(rows), ly.in, ly.out, nullptr, dh[l], nullptr, 0, stream);
+    if (e == hipSuccess)
+      e = rwgt::mlp_silu_bwd(layers[l - 1].mode, dh[l], z[l - 1], g[l - 1], gt[l - 1], rows * layers[l - 1].out,
+                             stream);
   }
   if (e != hipSuccess) return hip_fail(e, "mlp backward");
   return RWGT_OK;
@@ -113,14 +122,74 @@ int rwgt_mlp::update(float lr) {
   const float c1 = 1.0f / (1.0f - std::pow(b1, float(t)));
   const float c2 = 1.0f / (1.0f - std::pow(b2, float(t)));
   for (auto& ly : layers) {
-    hipError_t e = rwgt::mlp_adam(mode, ly.w, ly.gw, ly.mw, ly.vw, ly.wc, ly.wct, ly.out, ly.in, ly.out_used, ly.in_used,
-                                  lr, b1, b2, eps, c1, c2, stream);
+    hipError_t e = rwgt::mlp_adam(ly.mode, ly.w, ly.gw, ly.mw, ly.vw, ly.wc, ly.wct, ly.out, ly.in, ly.out_used,
+                                  ly.in_used, lr, b1, b2, eps, c1, c2, stream);
     if (e == hipSuccess)
       e = rwgt::mlp_adam(kMlpFP32, ly.b, ly.gb, ly.mb, ly.vb, nullptr, nullptr, 1, ly.out, 1, ly.out_used, lr, b1, b2,
                          eps, c1, c2, stream);
     if (e != hipSuccess) return hip_fail(e, "adam");
   }
+  pack_dirty = true;
   return RWGT_OK;
+}
+
+bool rwgt_mlp::fused() const {
+  const int L = int(layers.size());
+  return p0hi && L >= 3 && fm.npart >= 4 && fm.npart <= 5 && n_in == rwgt::feature_count(fm.kind, fm.npart);
+}
+
+int rwgt_mlp::pack() {
+  if (!pack_dirty) return RWGT_OK;
+  const int L = int(layers.size());
+  const int nb = width / 32, nc = width / 16;
+  const Layer& l0 = layers[0];
+  hipError_t e = rwgt::mlp_pack(l0.w, l0.in, l0.out_used, l0.in_used, nb, 2, p0hi, p0lo, stream);
+  for (int l = 1; l + 1 < L && e == hipSuccess; ++l) {
+    const Layer& ly = layers[l];
+    char* dst = static_cast<char*>(phid) + size_t(l - 1) * nb * nc * kPackBytes;
+    e = rwgt::mlp_pack(ly.w, ly.in, ly.out_used, ly.in_used, nb, nc, dst, nullptr, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(pbias + size_t(l - 1) * width, ly.b, size_t(width) * 4, hipMemcpyDeviceToDevice, stream);
+  }
+  if (e != hipSuccess) return hip_fail(e, "pack");
+  pack_dirty = false;
+  return RWGT_OK;
+}
+
+int rwgt_mlp::infer(const double* mom, const int32_t* ev, const int32_t* cidx, const float* cpar, int64_t n,
+                    float* heads, const double* w_in, double* w_out, int32_t* list, unsigned int* count,
+                    float threshold) {
+  int rc = pack();
+  if (rc != RWGT_OK) return rc;
+  const int L = int(layers.size());
+  rwgt::InferArgs a;
+  a.mom = mom;
+  a.ev = ev;
+  a.cidx = cidx;
+  a.cpar = cpar;
+  a.n = n;
+  a.fm = fm;
+  a.mean = mean;
+  a.stdv = stdv;
+  a.w0hi = p0hi;
+  a.w0lo = p0lo;
+  a.b0 = layers[0].b;
+  a.wh = phid;
+  a.bh = pbias;
+  a.nh = L - 2;
+  a.whead = layers[L - 1].w;
+  a.bhead = layers[L - 1].b;
+  a.ym = ym;
+  a.ys = ys;
+  a.k_cal = k_cal;
+  a.threshold = threshold;
+  a.w_in = w_in;
+  a.w_out = w_out;
+  a.list = list;
+  a.count = count;
+  a.heads = heads;
+  hipError_t e = rwgt::mlp_infer(width, a, stream);
+  return e == hipSuccess ? RWGT_OK : hip_fail(e, "fused inference");
 }
 
 rwgt_mlp::~rwgt_mlp() {
@@ -135,30 +204,38 @@ int rwgt_mlp_create(int32_t n_in, int32_t width, int32_t depth, int32_t n_out, i
                     rwgt_mlp** out) {
   if (!out) return RWGT_EINVAL;
   *out = nullptr;
-  if (n_in < 1 || width < 32 || width % 32 || depth < 1 || n_out < 2 || n_out > 32 ||
+  if (n_in < 1 || n_in > rwgt::kMlpMaxIn || width < 32 || width % 32 || depth < 1 || n_out < 2 || n_out > 32 ||
       (precision != RWGT_MLP_BF16 && precision != RWGT_MLP_FP32))
     return RWGT_EINVAL;
   rwgt_mlp* m = new (std::nothrow) rwgt_mlp;
   if (!m) return RWGT_ENOMEM;
-  m->mode = precision == RWGT_MLP_BF16 ? kMlpBF16 : rwgt::kMlpFP32;
+  m->mode = precision == RWGT_MLP_BF16 ? kMlpBF16 : kMlpFP32;
   m->n_in = n_in;
   m->n_out = n_out;
-  // layer shapes: in0 = n_in padded to 32; hidden width; head padded to 32
-  std::vector<std::pair<int, int>> shape;   // (in, out), padded
-  std::vector<std::pair<int, int>> used;
-  shape.push_back({pad32(n_in), width});
-  used.push_back({n_in, width});
-  for (int d = 1; d < depth; ++d) { shape.push_back({width, width}); used.push_back({width, width}); }
-  shape.push_back({width, 32});
-  used.push_back({width, n_out});
+  m->width = width;
+  // layer shapes: in0 = n_in padded to 32; hidden width; head padded to 32.
+  // BF16 networks: FP32 first layer (forward product as split BF16, the
+  // arithmetic of the fused inference kernel) and head, BF16 hidden layers.
+  struct Shape { int in, out, in_used, out_used, mode; };
+  std::vector<Shape> shape;
+  const int hidden_mode = m->mode;
+  shape.push_back({pad32(n_in), width, n_in, width, kMlpFP32});
+  for (int d = 1; d < depth; ++d) shape.push_back({width, width, width, width, hidden_mode});
+  shape.push_back({width, 32, width, n_out, kMlpFP32});
   std::mt19937_64 rng(seed);
   hipError_t e = hipGetDevice(&m->device);
+  auto dalloc = [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes);
+    if (e == hipSuccess) m->params.push_back(*p);
+  };
   for (size_t l = 0; l < shape.size() && e == hipSuccess; ++l) {
     rwgt_mlp::Layer ly;
-    ly.in = shape[l].first;
-    ly.out = shape[l].second;
-    ly.in_used = used[l].first;
-    ly.out_used = used[l].second;
+    ly.mode = shape[l].mode;
+    ly.split = l == 0 && m->mode == kMlpBF16;
+    ly.in = shape[l].in;
+    ly.out = shape[l].out;
+    ly.in_used = shape[l].in_used;
+    ly.out_used = shape[l].out_used;
     const size_t nw = size_t(ly.in) * ly.out;
     // uniform(-a, a) with a = sqrt(6 / fan_in) on the used block (He-uniform),
     // zero biases and zero padding
@@ -167,27 +244,35 @@ int rwgt_mlp_create(int32_t n_in, int32_t width, int32_t depth, int32_t n_out, i
     std::uniform_real_distribution<float> U(-a, a);
     for (int r = 0; r < ly.out_used; ++r)
       for (int c = 0; c < ly.in_used; ++c) w[size_t(r) * ly.in + c] = U(rng) * (l + 1 == shape.size() ? 0.1f : 1.0f);
-    float** f32[] = {&ly.w, &ly.gw, &ly.mw, &ly.vw};
-    for (float** p : f32) {
-      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(p), nw * 4);
-      if (e == hipSuccess) { m->params.push_back(*p); e = hipMemset(*p, 0, nw * 4); }
+    for (float** p : {&ly.w, &ly.gw, &ly.mw, &ly.vw}) {
+      dalloc(reinterpret_cast<void**>(p), nw * 4);
+      if (e == hipSuccess) e = hipMemset(*p, 0, nw * 4);
     }
-    float** bias[] = {&ly.b, &ly.gb, &ly.mb, &ly.vb};
-    for (float** p : bias) {
-      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(p), ly.out * 4);
-      if (e == hipSuccess) { m->params.push_back(*p); e = hipMemset(*p, 0, ly.out * 4); }
+    for (float** p : {&ly.b, &ly.gb, &ly.mb, &ly.vb}) {
+      dalloc(reinterpret_cast<void**>(p), size_t(ly.out) * 4);
+      if (e == hipSuccess) e = hipMemset(*p, 0, size_t(ly.out) * 4);
     }
-    if (e == hipSuccess) e = hipMalloc(&ly.wc, nw * esize(m->mode));
-    if (e == hipSuccess) { m->params.push_back(ly.wc); e = hipMalloc(&ly.wct, nw * esize(m->mode)); }
-    if (e == hipSuccess) { m->params.push_back(ly.wct); e = hipMemcpy(ly.w, w.data(), nw * 4, hipMemcpyHostToDevice); }
+    dalloc(&ly.wc, nw * esize(ly.mode));
+    dalloc(&ly.wct, nw * esize(ly.mode));
+    if (e == hipSuccess) e = hipMemcpy(ly.w, w.data(), nw * 4, hipMemcpyHostToDevice);
     m->layers.push_back(ly);
   }
-  std::vector<float> ones(32 * ((n_in + 31) / 32), 1.0f), zeros(ones.size(), 0.0f);
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&m->mean), ones.size() * 4);
-  if (e == hipSuccess) { m->params.push_back(m->mean); e = hipMalloc(reinterpret_cast<void**>(&m->stdv), ones.size() * 4); }
-  if (e == hipSuccess) { m->params.push_back(m->stdv); e = hipMalloc(reinterpret_cast<void**>(&m->loss), 4); }
-  if (e == hipSuccess) { m->params.push_back(m->loss); e = hipMemcpy(m->mean, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice); }
+  std::vector<float> ones(rwgt::kMlpMaxIn, 1.0f), zeros(rwgt::kMlpMaxIn, 0.0f);
+  dalloc(reinterpret_cast<void**>(&m->mean), ones.size() * 4);
+  dalloc(reinterpret_cast<void**>(&m->stdv), ones.size() * 4);
+  dalloc(reinterpret_cast<void**>(&m->loss), 4);
+  if (e == hipSuccess) e = hipMemcpy(m->mean, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(m->stdv, ones.data(), ones.size() * 4, hipMemcpyHostToDevice);
+  // packed weights of the fused inference kernel (BF16 networks of width 128
+  // or 256 with 1..kMlpMaxHidden hidden width x width layers)
+  const int nh = depth - 1;
+  if (m->mode == kMlpBF16 && (width == 128 || width == 256) && nh >= 1 && nh <= rwgt::kMlpMaxHidden) {
+    const size_t nb = width / 32, nc = width / 16;
+    dalloc(&m->p0hi, nb * 2 * kPackBytes);
+    dalloc(&m->p0lo, nb * 2 * kPackBytes);
+    dalloc(&m->phid, size_t(nh) * nb * nc * kPackBytes);
+    dalloc(reinterpret_cast<void**>(&m->pbias), size_t(nh) * width * 4);
+  }
   if (e == hipSuccess && m->refresh_copies() != RWGT_OK) e = hipErrorUnknown;
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) { delete m; return e == hipErrorOutOfMemory ? RWGT_ENOMEM : RWGT_EDEVICE; }
@@ -212,23 +297,22 @@ int rwgt_mlp_num_params(const rwgt_mlp* m, int64_t* n) {
 }
 
 // Parameters packed layer by layer as W[out_used][in_used] then b[out_used].
-static int pack(rwgt_mlp* m, bool to_host, float* host, bool grads) {
+static int pack_params(rwgt_mlp* m, bool to_host, float* host, bool grads) {
   hipError_t e = hipStreamSynchronize(m->stream);
   size_t off = 0;
   for (auto& ly : m->layers) {
     float* w = grads ? ly.gw : ly.w;
     float* b = grads ? ly.gb : ly.b;
     std::vector<float> full(size_t(ly.in) * ly.out);
-    if (e == hipSuccess && to_host) e = hipMemcpy(full.data(), w, full.size() * 4, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && !to_host) {
-      e = hipMemcpy(full.data(), w, full.size() * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(full.data(), w, full.size() * 4, hipMemcpyDeviceToHost);
+    if (to_host) {
+      for (int r = 0; r < ly.out_used; ++r)
+        std::memcpy(host + off + size_t(r) * ly.in_used, &full[size_t(r) * ly.in], ly.in_used * 4);
+    } else {
       for (int r = 0; r < ly.out_used; ++r)
         std::memcpy(&full[size_t(r) * ly.in], host + off + size_t(r) * ly.in_used, ly.in_used * 4);
       if (e == hipSuccess) e = hipMemcpy(w, full.data(), full.size() * 4, hipMemcpyHostToDevice);
     }
-    if (to_host)
-      for (int r = 0; r < ly.out_used; ++r)
-        std::memcpy(host + off + size_t(r) * ly.in_used, &full[size_t(r) * ly.in], ly.in_used * 4);
     off += size_t(ly.in_used) * ly.out_used;
     if (e == hipSuccess)
       e = to_host ? hipMemcpy(host + off, b, ly.out_used * 4, hipMemcpyDeviceToHost)
@@ -240,17 +324,57 @@ static int pack(rwgt_mlp* m, bool to_host, float* host, bool grads) {
   return RWGT_OK;
 }
 
-int rwgt_mlp_get_params(rwgt_mlp* m, float* host) { return (m && host) ? pack(m, true, host, false) : RWGT_EINVAL; }
+int rwgt_mlp_get_params(rwgt_mlp* m, float* host) { return (m && host) ? pack_params(m, true, host, false) : RWGT_EINVAL; }
 int rwgt_mlp_set_params(rwgt_mlp* m, const float* host) {
-  return (m && host) ? pack(m, false, const_cast<float*>(host), false) : RWGT_EINVAL;
+  return (m && host) ? pack_params(m, false, const_cast<float*>(host), false) : RWGT_EINVAL;
 }
-int rwgt_mlp_get_grads(rwgt_mlp* m, float* host) { return (m && host) ? pack(m, true, host, true) : RWGT_EINVAL; }
+int rwgt_mlp_get_grads(rwgt_mlp* m, float* host) { return (m && host) ? pack_params(m, true, host, true) : RWGT_EINVAL; }
 
 int rwgt_mlp_set_normalisation(rwgt_mlp* m, const float* mean, const float* stdv) {
   if (!m || !mean || !stdv) return RWGT_EINVAL;
+  for (int k = 0; k < m->n_in; ++k)
+    if (!(stdv[k] > 0.0f) || !std::isfinite(stdv[k]) || !std::isfinite(mean[k]))
+      return m->fail(RWGT_EINVAL, "standard deviations must be positive and finite");
   hipError_t e = hipMemcpy(m->mean, mean, m->n_in * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(m->stdv, stdv, m->n_in * 4, hipMemcpyHostToDevice);
   return e == hipSuccess ? RWGT_OK : m->hip_fail(e, "normalisation");
+}
+
+int rwgt_mlp_set_features(rwgt_mlp* m, int32_t kind, int32_t npart, int32_t res_a, int32_t res_b, double mz0,
+                          double wz0) {
+  if (!m) return RWGT_EINVAL;
+  if (kind != RWGT_FEAT_RAW && kind != RWGT_FEAT_PHYS) return m->fail(RWGT_EINVAL, "unknown feature map");
+  if (npart < 4 || npart > 5) return m->fail(RWGT_EINVAL, "feature maps cover 4 or 5 external particles");
+  if (m->n_in != rwgt::feature_count(kind, npart))
+    return m->fail(RWGT_EINVAL, "the feature map's width differs from the network's n_in");
+  if (kind == RWGT_FEAT_PHYS &&
+      (res_a < 0 || res_b < 0 || res_a >= npart || res_b >= npart || res_a == res_b || !(mz0 > 0.0) || !(wz0 > 0.0)))
+    return m->fail(RWGT_EINVAL, "bad resonant pair or original Z mass / width");
+  m->fm.kind = kind;
+  m->fm.npart = npart;
+  m->fm.res_a = res_a;
+  m->fm.res_b = res_b;
+  m->fm.mz0 = mz0;
+  m->fm.wz0 = wz0;
+  return RWGT_OK;
+}
+
+int rwgt_mlp_get_normalisation(rwgt_mlp* m, float* mean, float* stdv, float* y_scale) {
+  if (!m || !mean || !stdv || !y_scale) return RWGT_EINVAL;
+  hipError_t e = hipStreamSynchronize(m->stream);
+  if (e == hipSuccess) e = hipMemcpy(mean, m->mean, m->n_in * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(stdv, m->stdv, m->n_in * 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return m->hip_fail(e, "normalisation");
+  y_scale[0] = m->ym;
+  y_scale[1] = m->ys;
+  return RWGT_OK;
+}
+
+int rwgt_mlp_set_target_scale(rwgt_mlp* m, float mean, float stdv) {
+  if (!m || !(stdv > 0.0f) || !std::isfinite(stdv) || !std::isfinite(mean)) return RWGT_EINVAL;
+  m->ym = mean;
+  m->ys = stdv;
+  return RWGT_OK;
 }
 
 int rwgt_mlp_set_training(rwgt_mlp* m, float lambda, float beta1, float beta2, float eps) {
@@ -268,31 +392,127 @@ int rwgt_mlp_set_calibration(rwgt_mlp* m, float k) {
   return RWGT_OK;
 }
 
+// The feature map of a network that has none yet: the raw map of npart
+// particles.  Errors when the map and the network's width disagree.
+static int resolve_map(rwgt_mlp* m, int32_t npart) {
+  if (m->fm.npart == 0) {
+    if (m->n_in != rwgt::feature_count(RWGT_FEAT_RAW, npart))
+      return m->fail(RWGT_EINVAL, "feature count differs from the input width");
+    m->fm.kind = RWGT_FEAT_RAW;
+    m->fm.npart = npart;
+  }
+  if (npart != m->fm.npart) return m->fail(RWGT_EINVAL, "particle count differs from the feature map");
+  return RWGT_OK;
+}
+
 int rwgt_mlp_features(rwgt_mlp* m, const double* momenta, int32_t npart, const int32_t* event_index,
                       const int32_t* card_index, const float* card_params, int32_t nparam, int64_t n, void* x_out) {
   if (!m || !momenta || !card_index || !card_params || !x_out || n < 0) return RWGT_EINVAL;
-  if (npart * 4 + nparam != m->n_in) return m->fail(RWGT_EINVAL, "feature count differs from the input width");
-  const int64_t rows = (n + 63) / 64 * 64;
-  hipError_t e = rwgt::mlp_features(m->mode, momenta, npart, event_index, card_index, card_params, nparam, m->mean,
-                                    m->stdv, x_out, n, rows, m->layers[0].in, m->stream);
+  if (nparam != rwgt::kMlpCardParams) return m->fail(RWGT_EINVAL, "cards carry (M_Z, Gamma_Z, sin^2 theta_W)");
+  int rc = resolve_map(m, npart);
+  if (rc != RWGT_OK) return rc;
+  const int64_t rows = pad64(n);
+  hipError_t e = rwgt::mlp_features(m->fm, momenta, event_index, card_index, card_params, m->mean, m->stdv,
+                                    static_cast<float*>(x_out), n, rows, m->layers[0].in, m->stream);
   return e == hipSuccess ? RWGT_OK : m->hip_fail(e, "features");
 }
 
-int rwgt_mlp_forward(rwgt_mlp* m, const void* x, int64_t n, float* heads_out) {
-  if (!m || !x || n < 1) return RWGT_EINVAL;
-  const int64_t rows = (n + 63) / 64 * 64;
-  int rc = m->forward(x, rows);
-  if (rc != RWGT_OK) return rc;
-  if (heads_out) {
-    hipError_t e = hipMemcpyAsync(heads_out, m->z.back(), size_t(n) * 32 * 4, hipMemcpyDeviceToDevice, m->stream);
-    if (e != hipSuccess) return m->hip_fail(e, "copy heads");
+}  // extern "C"
+
+// Mean and population standard deviation of columns [0, ncol) of FP32 rows
+// produced chunk by chunk by fill(a, b, buffer) (rows a..b), FP64 sums on the
+// device.  Constant columns get standard deviation 1.
+template <class Fill>
+static int column_stats(rwgt_mlp* m, int64_t n, int ld, int ncol, Fill fill, std::vector<float>& mean,
+                        std::vector<float>& stdv) {
+  const int64_t chunk = int64_t(1) << 18;
+  void* x = nullptr;
+  double* sums = nullptr;
+  hipError_t e = hipMalloc(&x, size_t(std::min(n, chunk)) * ld * 4);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sums), size_t(2 * ld) * 8);
+  for (int64_t a = 0; a < n && e == hipSuccess; a += chunk) {
+    const int64_t b = std::min(n, a + chunk);
+    e = fill(a, b, static_cast<float*>(x));
+    if (e == hipSuccess) e = rwgt::mlp_moments(static_cast<float*>(x), b - a, ld, sums, a == 0, m->stream);
+  }
+  std::vector<double> h(size_t(2 * ld), 0.0);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), sums, h.size() * 8, hipMemcpyDeviceToHost, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (x) (void)hipFree(x);
+  if (sums) (void)hipFree(sums);
+  if (e != hipSuccess) return m->hip_fail(e, "column statistics");
+  mean.assign(ncol, 0.0f);
+  stdv.assign(ncol, 1.0f);
+  for (int c = 0; c < ncol; ++c) {
+    const double mu = h[c] / double(n);
+    const double var = std::max(h[ld + c] / double(n) - mu * mu, 0.0);
+    const double sd = std::sqrt(var);
+    mean[c] = float(mu);
+    stdv[c] = sd > 1e-12 * std::max(1.0, std::fabs(mu)) ? float(sd) : 1.0f;
   }
   return RWGT_OK;
 }
 
+extern "C" {
+
+int rwgt_mlp_fit_normalisation(rwgt_mlp* m, const double* momenta, int32_t npart, const int32_t* event_index,
+                               const int32_t* card_index, const float* card_params, int64_t n) {
+  if (!m || !momenta || !card_index || !card_params || n < 1) return RWGT_EINVAL;
+  int rc = resolve_map(m, npart);
+  if (rc != RWGT_OK) return rc;
+  const std::vector<float> zeros(rwgt::kMlpMaxIn, 0.0f), ones(rwgt::kMlpMaxIn, 1.0f);
+  hipError_t e = hipMemcpy(m->mean, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->stdv, ones.data(), ones.size() * 4, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return m->hip_fail(e, "normalisation");
+  const int ld = m->layers[0].in;
+  auto fill = [&](int64_t a, int64_t b, float* x) {
+    const double* mom = event_index ? momenta : momenta + a * npart * 4;
+    return rwgt::mlp_features(m->fm, mom, event_index ? event_index + a : nullptr, card_index + a, card_params,
+                              m->mean, m->stdv, x, b - a, b - a, ld, m->stream);
+  };
+  std::vector<float> mean, stdv;
+  rc = column_stats(m, n, ld, m->n_in, fill, mean, stdv);
+  if (rc != RWGT_OK) return rc;
+  return rwgt_mlp_set_normalisation(m, mean.data(), stdv.data());
+}
+
+int rwgt_mlp_fit_target_scale(rwgt_mlp* m, const float* y, int64_t n) {
+  if (!m || !y || n < 1) return RWGT_EINVAL;
+  auto fill = [&](int64_t a, int64_t b, float* x) {
+    return hipMemcpyAsync(x, y + a, size_t(b - a) * 4, hipMemcpyDeviceToDevice, m->stream);
+  };
+  std::vector<float> mean, stdv;
+  int rc = column_stats(m, n, 1, 1, fill, mean, stdv);
+  if (rc != RWGT_OK) return rc;
+  return rwgt_mlp_set_target_scale(m, mean[0], stdv[0]);
+}
+
+int rwgt_mlp_forward(rwgt_mlp* m, const void* x, int64_t n, float* heads_out) {
+  if (!m || !x || n < 1) return RWGT_EINVAL;
+  int rc = m->forward(x, pad64(n));
+  if (rc != RWGT_OK) return rc;
+  if (heads_out) {
+    hipError_t e = rwgt::mlp_heads(m->z.back(), 32, n, m->ym, m->ys, heads_out, 32, m->stream);
+    if (e != hipSuccess) return m->hip_fail(e, "heads");
+  }
+  return RWGT_OK;
+}
+
+int rwgt_mlp_predict(rwgt_mlp* m, const double* momenta, int32_t npart, const int32_t* event_index,
+                     const int32_t* card_index, const float* card_params, int64_t n, float* heads_out) {
+  if (!m || !momenta || !card_index || !card_params || !heads_out || n < 0) return RWGT_EINVAL;
+  int rc = resolve_map(m, npart);
+  if (rc != RWGT_OK) return rc;
+  if (!m->fused()) return m->fail(RWGT_EINVAL, "network not eligible for the fused kernel (BF16, width 128 or 256, "
+                                               "depth 2..9, 4 or 5 particles)");
+  if (n == 0) return RWGT_OK;
+  return m->infer(momenta, event_index, card_index, card_params, n, heads_out, nullptr, nullptr, nullptr, nullptr,
+                  0.0f);
+}
+
 int rwgt_mlp_train_step(rwgt_mlp* m, const void* x, const float* y, int64_t n, float lr, float* loss_out) {
   if (!m || !x || !y || n < 1) return RWGT_EINVAL;
-  const int64_t rows = (n + 63) / 64 * 64;
+  const int64_t rows = pad64(n);
   int rc = m->forward(x, rows);
   if (rc == RWGT_OK) rc = m->backward(y, n, rows);
   if (rc == RWGT_OK && lr > 0.0f) rc = m->update(lr);
@@ -304,8 +524,8 @@ int rwgt_mlp_train_step(rwgt_mlp* m, const void* x, const float* y, int64_t n, f
 }
 
 int rwgt_mlp_input_bytes(const rwgt_mlp* m, int64_t n, int64_t* bytes) {
-  if (!m || !bytes) return RWGT_EINVAL;
-  *bytes = (n + 63) / 64 * 64 * m->layers[0].in * int64_t(esize(m->mode));
+  if (!m || !bytes || n < 0) return RWGT_EINVAL;
+  *bytes = pad64(n) * m->layers[0].in * 4;
   return RWGT_OK;
 }
 

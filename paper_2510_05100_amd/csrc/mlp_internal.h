@@ -7,24 +7,35 @@
 #include <string>
 #include <vector>
 
+#include "mlp.h"
+
 struct rwgt_mlp {
   struct Layer {
+    int mode = 0;                                         // operand type (rwgt::kMlpBF16 / kMlpFP32)
+    bool split = false;                                   // FP32 forward product as split BF16 (kMlpSplit)
     int in = 0, out = 0, in_used = 0, out_used = 0;      // padded and used shapes
     float *w = nullptr, *b = nullptr;                     // FP32 master parameters
     float *gw = nullptr, *gb = nullptr;                   // gradients
     float *mw = nullptr, *vw = nullptr, *mb = nullptr, *vb = nullptr;   // Adam moments
     void *wc = nullptr, *wct = nullptr;                   // operand-type W [out][in] and W^T [in][out]
   };
-  int mode = 0;
+  int mode = 0;                                           // network precision (RWGT_MLP_*)
   int device = 0;
-  int n_in = 0, n_out = 0;
+  int n_in = 0, n_out = 0, width = 0;
   std::vector<Layer> layers;
+  rwgt::FeatureMap fm;
   float *mean = nullptr, *stdv = nullptr, *loss = nullptr;
   float lambda = 0.1f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f, k_cal = 3.3f;
+  float ym = 0.0f, ys = 1.0f;                             // target standardisation
   long long t = 0;
   hipStream_t stream = nullptr;
+  // fused inference: packed weights (valid while !pack_dirty)
+  void *p0hi = nullptr, *p0lo = nullptr, *phid = nullptr;
+  float* pbias = nullptr;
+  bool pack_dirty = true;
   // batch workspace
   int64_t bcap = 0;
+  const void* x_in = nullptr;                             // the current batch's input rows (FP32)
   std::vector<void*> h, ht, gt, gtt;
   std::vector<float*> z, g, dh;
   std::vector<void*> work, params;
@@ -35,6 +46,12 @@ struct rwgt_mlp {
     err = std::string(what) + ": " + hipGetErrorString(e);
     return e == hipErrorOutOfMemory ? -5 : -4;
   }
+  const void* input(int l) const { return l == 0 ? x_in : h[l]; }
+  bool fused() const;                                     // eligible for the fused inference kernel
+  int pack();                                             // refresh the packed weights if stale
+  // fused pass over n rows (see rwgt::InferArgs); gate when w_out is non-NULL
+  int infer(const double* mom, const int32_t* ev, const int32_t* cidx, const float* cpar, int64_t n,
+            float* heads, const double* w_in, double* w_out, int32_t* list, unsigned int* count, float threshold);
   int ensure_batch(int64_t rows);
   int refresh_copies();
   int forward(const void* x, int64_t rows);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cctype>
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -755,6 +756,86 @@ int rwgt_batch_tune(rwgt_batch* b, const rwgt_segment* segs, int32_t nseg, int32
 
 const char* rwgt_batch_last_error(const rwgt_batch* b) { return b ? b->err.c_str() : "batch is NULL"; }
 
+// Device tables of the card-per-event paths: cards[0] = original, cards[1 + k]
+// = param_table row k; the network's card inputs (M_Z, Gamma_Z,
+// sin^2 theta_W) per row; the gate list and count for up to rows events, and
+// (need_x) the input rows of a layered network.
+static int per_event_tables(rwgt_ctx* c, const rwgt_mlp* m, const double* param_table, int32_t ncards, int64_t rows,
+                            bool need_x) {
+  constexpr int kNparam = rwgt::kMlpCardParams;
+  std::vector<CardPair> cards;
+  int rc = build_cards(c, param_table, ncards, true, cards);
+  if (rc != RWGT_OK) return rc;
+  const auto& layout = c->def->layout;
+  auto col = [&](const char* name) {
+    for (size_t j = 0; j < layout.size(); ++j)
+      if (layout[j] == name) return int(j);
+    return -1;
+  };
+  const int jm = col("MASS 23"), jw = col("DECAY 23"), js = col("RWGTEW 1");
+  std::vector<float> cpar(size_t(ncards) * kNparam);
+  for (int k = 0; k < ncards; ++k) {
+    const double* row = param_table + size_t(k) * layout.size();
+    cpar[k * kNparam + 0] = float(row[jm]);
+    cpar[k * kNparam + 1] = float(row[jw]);
+    cpar[k * kNparam + 2] = float(row[js]);
+  }
+  hipError_t e = hipSetDevice(c->device);
+  hipStream_t st = c->stream;
+  if (e == hipSuccess && (rows > c->sur_cap || ncards + 1 > c->sur_card_cap || (need_x && !c->sur_x))) {
+    e = hipStreamSynchronize(st);
+    for (void* p : {c->sur_x, static_cast<void*>(c->sur_list), static_cast<void*>(c->sur_count),
+                    static_cast<void*>(c->sur_heads), static_cast<void*>(c->sur_cards), static_cast<void*>(c->sur_cpar)})
+      if (p) (void)hipFree(p);
+    c->sur_x = nullptr; c->sur_list = nullptr; c->sur_count = nullptr; c->sur_heads = nullptr;
+    c->sur_cards = nullptr; c->sur_cpar = nullptr; c->sur_cap = 0; c->sur_card_cap = 0;
+    const int64_t cap = std::max<int64_t>(rows, 64);
+    const int cc = std::max(ncards + 1, 64);
+    int64_t xbytes = 0;
+    if (need_x) rwgt_mlp_input_bytes(m, cap, &xbytes);
+    if (e == hipSuccess && need_x) e = hipMalloc(&c->sur_x, size_t(xbytes));
+    if (e == hipSuccess) e = hipMalloc(&c->sur_list, size_t(cap) * 4);
+    if (e == hipSuccess) e = hipMalloc(&c->sur_count, 4);
+    if (e == hipSuccess) e = hipMalloc(&c->sur_cards, size_t(cc) * sizeof(CardPair));
+    if (e == hipSuccess) e = hipMalloc(&c->sur_cpar, size_t(cc) * kNparam * 4);
+    if (e == hipSuccess) { c->sur_cap = cap; c->sur_card_cap = cc; }
+  }
+  if (e != hipSuccess) return c->hip_fail(e, "per-event workspace");
+  // small tables: synchronous copies (pageable host memory)
+  e = hipMemcpyAsync(c->sur_cards, cards.data(), cards.size() * sizeof(CardPair), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->sur_cpar, cpar.data(), cpar.size() * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? RWGT_OK : c->hip_fail(e, "per-event tables");
+}
+
+static int compute_units(int device) {
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu < 1) ncu = 256;
+  return ncu;
+}
+
+int rwgt_eval_cards(rwgt_ctx* c, const double* momenta, int64_t nevt, const double* w_in, const double* param_table,
+                    int32_t ncards, const int32_t* card_index, double* w_out) {
+  if (!c) return RWGT_EINVAL;
+  c->err.clear();
+  if (nevt < 0 || ncards < 1 || !param_table) return c->fail(RWGT_EINVAL, "bad sizes or NULL param_table");
+  const int proc = family_index(c->def->id);
+  if (proc < 0) return c->fail(RWGT_EPROCESS, "the card-per-event path covers the electroweak family");
+  if (nevt == 0) return RWGT_OK;
+  if (!momenta || !w_in || !w_out || !card_index) return c->fail(RWGT_EINVAL, "NULL device pointer");
+  try {
+    int rc = per_event_tables(c, nullptr, param_table, ncards, 0, false);
+    if (rc != RWGT_OK) return rc;
+    hipError_t e = rwgt::launch_exact_list(rwgt::kFamilyElectroweak,
+                                           c->precision == RWGT_FP64 ? rwgt::kPrecFP64 : rwgt::kPrecMixedFP16, proc,
+                                           momenta, nullptr, nullptr, nevt, card_index, c->sur_cards, w_in, w_out,
+                                           4 * compute_units(c->device), c->stream);
+    return e == hipSuccess ? RWGT_OK : c->hip_fail(e, "card-per-event evaluation");
+  } catch (const std::exception& ex) {
+    return c->fail(RWGT_ENOMEM, ex.what());
+  }
+}
+
 int rwgt_sur_eval(rwgt_ctx* c, rwgt_mlp* m, const double* momenta, int64_t nevt, const double* w_in,
                   const double* param_table, int32_t ncards, const int32_t* card_index, double threshold,
                   double* w_out, int64_t* n_fallback) {
@@ -764,70 +845,36 @@ int rwgt_sur_eval(rwgt_ctx* c, rwgt_mlp* m, const double* momenta, int64_t nevt,
   if (nevt < 0 || ncards < 1 || !param_table) return c->fail(RWGT_EINVAL, "bad sizes or NULL param_table");
   const int proc = family_index(c->def->id);
   if (proc < 0) return c->fail(RWGT_EPROCESS, "the surrogate path covers the electroweak family");
-  constexpr int kNparam = 3;                                 // M_Z, Gamma_Z, sin^2 theta_W
-  if (m->n_in != c->def->npart * 4 + kNparam) return c->fail(RWGT_EINVAL, "network input width mismatch");
+  constexpr int kNparam = rwgt::kMlpCardParams;              // M_Z, Gamma_Z, sin^2 theta_W
+  const int npart = c->def->npart;
+  if (m->fm.npart != 0 ? m->fm.npart != npart : m->n_in != rwgt::feature_count(rwgt::kFeatRaw, npart))
+    return c->fail(RWGT_EINVAL, "the network's feature map does not fit this process");
   if (nevt == 0) return RWGT_OK;
   if (!momenta || !w_in || !w_out || !card_index) return c->fail(RWGT_EINVAL, "NULL device pointer");
   try {
-    // cards: original, then the table; network inputs per card
-    std::vector<CardPair> cards;
-    int rc = build_cards(c, param_table, ncards, true, cards);
-    if (rc != RWGT_OK) return rc;
-    const auto& layout = c->def->layout;
-    auto col = [&](const char* name) {
-      for (size_t j = 0; j < layout.size(); ++j)
-        if (layout[j] == name) return int(j);
-      return -1;
-    };
-    const int jm = col("MASS 23"), jw = col("DECAY 23"), js = col("RWGTEW 1");
-    std::vector<float> cpar(size_t(ncards) * kNparam);
-    for (int k = 0; k < ncards; ++k) {
-      const double* row = param_table + size_t(k) * layout.size();
-      cpar[k * kNparam + 0] = float(row[jm]);
-      cpar[k * kNparam + 1] = float(row[jw]);
-      cpar[k * kNparam + 2] = float(row[js]);
-    }
-    hipError_t e = hipSetDevice(c->device);
-    hipStream_t st = c->stream;
     const int64_t rows = (nevt + 63) / 64 * 64;
-    if (e == hipSuccess && (rows > c->sur_cap || ncards + 1 > c->sur_card_cap)) {
-      hipStreamSynchronize(st);
-      for (void* p : {c->sur_x, static_cast<void*>(c->sur_list), static_cast<void*>(c->sur_count),
-                      static_cast<void*>(c->sur_heads), static_cast<void*>(c->sur_cards), static_cast<void*>(c->sur_cpar)})
-        if (p) hipFree(p);
-      c->sur_x = nullptr; c->sur_list = nullptr; c->sur_count = nullptr; c->sur_heads = nullptr;
-      c->sur_cards = nullptr; c->sur_cpar = nullptr; c->sur_cap = 0; c->sur_card_cap = 0;
-      int64_t xbytes = 0;
-      rwgt_mlp_input_bytes(m, rows, &xbytes);
-      const int cc = ncards + 1 < 64 ? 64 : ncards + 1;
-      e = hipMalloc(&c->sur_x, size_t(xbytes));
-      if (e == hipSuccess) e = hipMalloc(&c->sur_list, size_t(rows) * 4);
-      if (e == hipSuccess) e = hipMalloc(&c->sur_count, 4);
-      if (e == hipSuccess) e = hipMalloc(&c->sur_heads, size_t(rows) * 32 * 4);
-      if (e == hipSuccess) e = hipMalloc(&c->sur_cards, size_t(cc) * sizeof(CardPair));
-      if (e == hipSuccess) e = hipMalloc(&c->sur_cpar, size_t(cc) * kNparam * 4);
-      if (e == hipSuccess) { c->sur_cap = rows; c->sur_card_cap = cc; }
-    }
-    if (e != hipSuccess) return c->hip_fail(e, "surrogate workspace");
-    // small tables: synchronous copies (pageable host memory)
-    e = hipMemcpyAsync(c->sur_cards, cards.data(), cards.size() * sizeof(CardPair), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(c->sur_cpar, cpar.data(), cpar.size() * 4, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return c->hip_fail(e, "surrogate tables");
+    int rc = per_event_tables(c, m, param_table, ncards, rows, !m->fused());
+    if (rc != RWGT_OK) return rc;
+    hipStream_t st = c->stream;
+    hipError_t e = hipSuccess;
     rwgt_mlp_set_stream(m, st);
-    rc = rwgt_mlp_features(m, momenta, c->def->npart, nullptr, card_index, c->sur_cpar, kNparam, nevt, c->sur_x);
-    if (rc == RWGT_OK) rc = rwgt_mlp_forward(m, c->sur_x, nevt, nullptr);
-    if (rc != RWGT_OK) return c->fail(rc, m->err);
-    e = rwgt::mlp_gate(m->z.back(), 32, nevt, m->k_cal, float(threshold), w_in, w_out, c->sur_list, c->sur_count, st);
-    if (e == hipSuccess) {
-      int ncu = 256;
-      hipDeviceProp_t prop;
-      if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) ncu = prop.multiProcessorCount;
-      e = rwgt::launch_exact_list(rwgt::kFamilyElectroweak, c->precision == RWGT_FP64 ? rwgt::kPrecFP64 : rwgt::kPrecMixedFP16,
-                                  proc, momenta, c->sur_list, c->sur_count, card_index, c->sur_cards, w_in, w_out,
-                                  4 * ncu, st);
+    if (m->fused()) {
+      // one pass: features, layers, heads, gate (w' or an entry in the list)
+      rc = m->infer(momenta, nullptr, card_index, c->sur_cpar, nevt, nullptr, w_in, w_out, c->sur_list, c->sur_count,
+                    float(threshold));
+      if (rc != RWGT_OK) return c->fail(rc, m->err);
+    } else {
+      rc = rwgt_mlp_features(m, momenta, npart, nullptr, card_index, c->sur_cpar, kNparam, nevt, c->sur_x);
+      if (rc == RWGT_OK) rc = rwgt_mlp_forward(m, c->sur_x, nevt, nullptr);
+      if (rc != RWGT_OK) return c->fail(rc, m->err);
+      e = rwgt::mlp_gate(m->z.back(), 32, nevt, m->ym, m->ys, m->k_cal, float(threshold), w_in, w_out, c->sur_list,
+                         c->sur_count, st);
     }
+    if (e == hipSuccess)
+      e = rwgt::launch_exact_list(rwgt::kFamilyElectroweak,
+                                  c->precision == RWGT_FP64 ? rwgt::kPrecFP64 : rwgt::kPrecMixedFP16, proc, momenta,
+                                  c->sur_list, c->sur_count, 0, card_index, c->sur_cards, w_in, w_out,
+                                  4 * compute_units(c->device), st);
     if (e != hipSuccess) return c->hip_fail(e, "surrogate gate / exact fallback");
     if (n_fallback) {
       unsigned int cnt = 0;

@@ -1,12 +1,18 @@
 """Learned surrogate for the reweighting ratio of u u~ -> e+ e- g.
 
-A network maps (the five four-momenta, M_Z, Gamma_Z, sin^2 theta_W) to
-mu = log(w'/w) and to s, the log of the error of mu.  It is trained on ratios
-produced by the exact matrix-element path and used with an exact fallback:
-where the calibrated error bound k exp(s) exceeds a threshold the event is
-reweighted exactly (rwgt_sur_eval).  Every numerical step runs in the
-library's kernels; this module only sequences the calls (data set assembly,
-shuffling, learning-rate schedule, calibration quantile, checkpoints).
+A network maps an (event, card) pair to mu = log(w'/w) and to s, the log of
+the error of mu.  Inputs: the physics feature map (log s_hat, the ten pair
+invariants log(s_ij / s_hat), the card's M_Z, Gamma_Z, sin^2 theta_W, and
+asinh of the real and imaginary parts of the Z-to-photon propagator ratio of
+the lepton pair under the card and under the original card: 18 inputs), or
+the raw map (momenta and card, 23 inputs).  It is trained on ratios from the
+exact matrix-element path and used with an exact fallback: where the
+calibrated error bound k exp(s) exceeds a threshold the event is reweighted
+exactly (rwgt_sur_eval).  Every numerical step of training and inference runs
+in the library's kernels (features, normalisation statistics, forward,
+backward, Adam, fused inference and gate); this module sequences the calls
+(data set assembly, shuffling, learning-rate schedule, the calibration
+quantile, checkpoints).
 
 Workload: 64 cards on the (M_Z, Gamma_Z, sin^2 theta_W) grid; training on
 62,500 events x 64 cards = 4e6 (event, card) pairs (seed 3000); calibration on
@@ -23,20 +29,22 @@ import numpy as np
 from . import _abi
 
 PROCESS = "u u~ > e+ e- g"
-N_IN = 23            # 5 x 4 momenta + 3 card parameters
+NPART = 5
+RESONANT_PAIR = (2, 3)          # e+ e-
 SEED_CALIBRATION = 3002
 
 
 @dataclasses.dataclass
 class Config:
-    width: int = 256
-    depth: int = 4
+    width: int = 128
+    depth: int = 3
     precision: int = _abi.RWGT_MLP_BF16
+    features: int = _abi.RWGT_FEAT_PHYS
     batch: int = 4096
-    epochs: int = 12
+    epochs: int = 20
     lr: float = 2e-3
     lr_final: float = 2e-5
-    lam: float = 0.1
+    lam: float = 0.02
     seed: int = 1
     coverage: float = 0.999     # quantile of |r| / exp(s) taken as k
 
@@ -58,20 +66,21 @@ def exact_ratios(ctx, torch, mom_dev, rows):
     return out
 
 
-def raw_feature_stats(p, net_cards):
-    """Mean and standard deviation of the 23 raw inputs over the (event, card)
-    pairs of the training set (host, float64)."""
-    mom = p.reshape(p.shape[0], -1)
-    mean = np.concatenate([mom.mean(axis=0), net_cards.mean(axis=0)])
-    std = np.concatenate([mom.std(axis=0), net_cards.std(axis=0)])
-    std[std == 0] = 1.0
-    return mean.astype(np.float32), std.astype(np.float32)
+def _pairs(torch, n_events, n_cards):
+    """Event and card index of every (event, card) pair, card-major."""
+    idx = torch.arange(n_events * n_cards, device="cuda")
+    return (idx % n_events).to(torch.int32), (idx // n_events).to(torch.int32)
 
 
 class Surrogate:
-    def __init__(self, cfg: Config | None = None):
+    def __init__(self, cfg: Config | None = None, orig=None):
+        import synth
         self.cfg = cfg or Config()
-        self.mlp = _abi.rwgt_mlp_create(N_IN, self.cfg.width, self.cfg.depth, 2, self.cfg.precision, self.cfg.seed)
+        self.orig = orig or (synth.ORIG_EW.MZ, synth.ORIG_EW.WZ)
+        self.n_in = _abi.n_features(self.cfg.features, NPART)
+        self.mlp = _abi.rwgt_mlp_create(self.n_in, self.cfg.width, self.cfg.depth, 2, self.cfg.precision,
+                                        self.cfg.seed)
+        _abi.rwgt_mlp_set_features(self.mlp, self.cfg.features, NPART, RESONANT_PAIR, self.orig)
         _abi.rwgt_mlp_set_training(self.mlp, self.cfg.lam)
         self.k = None
         self.history = []
@@ -82,16 +91,19 @@ class Surrogate:
             self.mlp = None
 
     # ------------------------------------------------------------- training
-    def fit(self, torch, mom_dev, net_cards_dev, y_dev, n_events, n_cards, mean, std, log=print):
+    def fit(self, torch, mom_dev, net_cards_dev, y_dev, n_events, n_cards, log=print):
         """y_dev: log ratios [n_cards][n_events] (float32, device)."""
         cfg = self.cfg
         _abi.rwgt_mlp_set_stream(self.mlp, None)
-        _abi.rwgt_mlp_set_normalisation(self.mlp, mean, std)
         total = n_events * n_cards
+        ev_all, cd_all = _pairs(torch, n_events, n_cards)
+        yflat = y_dev.reshape(-1)
+        _abi.rwgt_mlp_fit_normalisation(self.mlp, mom_dev, ev_all, cd_all, net_cards_dev, total)
+        _abi.rwgt_mlp_fit_target_scale(self.mlp, yflat, total)
+        del ev_all, cd_all
         steps_per_epoch = total // cfg.batch
         xbuf = torch.empty(_abi.rwgt_mlp_input_bytes(self.mlp, cfg.batch), dtype=torch.uint8, device="cuda")
         loss = torch.zeros(1, dtype=torch.float32, device="cuda")
-        yflat = y_dev.reshape(-1)
         gen = torch.Generator(device="cuda")
         gen.manual_seed(cfg.seed)
         nsteps = steps_per_epoch * cfg.epochs
@@ -117,49 +129,42 @@ class Surrogate:
         return time.perf_counter() - t0
 
     def predict(self, torch, mom_dev, card_index_dev, net_cards_dev, event_index_dev=None):
-        """(mu, s) for each row, in chunks (device float32 tensors)."""
+        """(mu, s) for each row from the fused kernel (device float32 tensors)."""
         n = card_index_dev.shape[0]
-        chunk = 1 << 18
-        mu = torch.empty(n, dtype=torch.float32, device="cuda")
-        s = torch.empty(n, dtype=torch.float32, device="cuda")
-        xbuf = torch.empty(_abi.rwgt_mlp_input_bytes(self.mlp, chunk), dtype=torch.uint8, device="cuda")
-        heads = torch.empty((chunk, 32), dtype=torch.float32, device="cuda")
+        heads = torch.empty((n, 2), dtype=torch.float32, device="cuda")
         _abi.rwgt_mlp_set_stream(self.mlp, None)
-        for a in range(0, n, chunk):
-            b = min(n, a + chunk)
-            evi = None if event_index_dev is None else event_index_dev[a:b]
-            mom = mom_dev if event_index_dev is not None else mom_dev[a:b]
-            _abi.rwgt_mlp_features(self.mlp, mom, evi, card_index_dev[a:b], net_cards_dev, b - a, xbuf)
-            _abi.rwgt_mlp_forward(self.mlp, xbuf, b - a, heads)
-            mu[a:b] = heads[:b - a, 0]
-            s[a:b] = heads[:b - a, 1]
-        return mu, s
+        _abi.rwgt_mlp_predict(self.mlp, mom_dev, event_index_dev, card_index_dev, net_cards_dev, n, heads)
+        return heads[:, 0], heads[:, 1]
 
     def calibrate(self, torch, mom_dev, net_cards_dev, y_dev, n_events, n_cards):
         """k = quantile of |y - mu| / exp(s) over the calibration pairs."""
-        total = n_events * n_cards
-        idx = torch.arange(total, device="cuda")
-        ev = (idx % n_events).to(torch.int32)
-        cd = (idx // n_events).to(torch.int32)
+        ev, cd = _pairs(torch, n_events, n_cards)
         mu, s = self.predict(torch, mom_dev, cd, net_cards_dev, ev)
-        z = (torch.abs(y_dev.reshape(-1) - mu) / torch.exp(s)).cpu().numpy()
+        resid = torch.abs(y_dev.reshape(-1) - mu)
+        z = (resid / torch.exp(s)).cpu().numpy()
         self.k = float(np.quantile(z, self.cfg.coverage))
         _abi.rwgt_mlp_set_calibration(self.mlp, self.k)
-        resid = (y_dev.reshape(-1) - mu).abs().cpu().numpy()
-        return {"k": self.k, "median_abs_err": float(np.median(resid)), "p999_abs_err": float(np.quantile(resid, 0.999))}
+        r = resid.cpu().numpy()
+        return {"k": self.k, "median_abs_err": float(np.median(r)), "p90_abs_err": float(np.quantile(r, 0.9)),
+                "p999_abs_err": float(np.quantile(r, 0.999))}
 
     # ---------------------------------------------------------- checkpoints
-    def save(self, path, mean, std):
-        np.savez(path, params=_abi.rwgt_mlp_get_params(self.mlp), mean=mean, std=std,
+    def save(self, path):
+        mean, std, (ym, ys) = _abi.rwgt_mlp_get_normalisation(self.mlp, self.n_in)
+        np.savez(path, params=_abi.rwgt_mlp_get_params(self.mlp), mean=mean, std=std, y_scale=np.array([ym, ys]),
                  k=np.float64(self.k or 0.0), width=self.cfg.width, depth=self.cfg.depth,
-                 precision=self.cfg.precision, history=np.array(self.history))
+                 precision=self.cfg.precision, features=self.cfg.features, orig=np.array(self.orig),
+                 history=np.array(self.history))
 
     @classmethod
     def load(cls, path):
         d = np.load(path)
-        s = cls(Config(width=int(d["width"]), depth=int(d["depth"]), precision=int(d["precision"])))
+        cfg = Config(width=int(d["width"]), depth=int(d["depth"]), precision=int(d["precision"]),
+                     features=int(d["features"]))
+        s = cls(cfg, orig=tuple(float(v) for v in d["orig"]))
         _abi.rwgt_mlp_set_params(s.mlp, d["params"])
         _abi.rwgt_mlp_set_normalisation(s.mlp, d["mean"], d["std"])
+        _abi.rwgt_mlp_set_target_scale(s.mlp, float(d["y_scale"][0]), float(d["y_scale"][1]))
         if float(d["k"]) > 0:
             s.k = float(d["k"])
             _abi.rwgt_mlp_set_calibration(s.mlp, s.k)
@@ -167,7 +172,7 @@ class Surrogate:
 
 
 def run(torch, cfg: Config | None = None, n_train=62_500, n_heldout=1_000_000, threshold=1e-3, log=print):
-    """Train, calibrate and evaluate; returns a summary dictionary."""
+    """Train, calibrate and evaluate; returns (summary, surrogate)."""
     import synth
     cfg = cfg or Config()
     grid = synth.batch_grid()
@@ -189,21 +194,22 @@ def run(torch, cfg: Config | None = None, n_train=62_500, n_heldout=1_000_000, t
         _abi.rwgt_mlp_targets(sur.mlp, exact_ratios(ctx, torch, mom_c, rows), None, y_c)
         torch.cuda.synchronize()
         data_s = time.perf_counter() - t0
-        mean, std = raw_feature_stats(p_train, net_cards)
-        train_s = sur.fit(torch, mom_t, net_dev, y_t, n_train, ncards, mean, std, log=log)
+        train_s = sur.fit(torch, mom_t, net_dev, y_t, n_train, ncards, log=log)
         cal = sur.calibrate(torch, mom_c, net_dev, y_c, n_train, ncards)
         log(f"calibration: {cal}")
-        summary = {"train_pairs": n_train * ncards, "epochs": cfg.epochs, "data_seconds": data_s,
+        summary = {"features": "physics" if cfg.features == _abi.RWGT_FEAT_PHYS else "raw",
+                   "network": f"{sur.n_in}-{'-'.join([str(cfg.width)] * cfg.depth)}-2",
+                   "train_pairs": n_train * ncards, "epochs": cfg.epochs, "data_seconds": data_s,
                    "train_seconds": train_s, "final_loss": sur.history[-1], "calibration": cal}
         summary.update(evaluate(torch, ctx, sur, rows, net_dev, n_heldout, threshold, log=log))
-        return summary, sur, (mean, std)
+        return summary, sur
     finally:
         _abi.rwgt_destroy(ctx)
 
 
-def evaluate(torch, ctx, sur, rows, net_dev, n_heldout, threshold, log=print, reps=5):
-    """Surrogate path (with exact fallback) against the exact path on held-out
-    events with uniformly drawn cards."""
+def evaluate(torch, ctx, sur, rows, net_dev, n_heldout, threshold, log=print, reps=5, extra_thresholds=(1e-2,)):
+    """Surrogate path (with exact fallback) against the exact card-per-event
+    path on held-out events with uniformly drawn cards."""
     import synth
     p = synth.events("uu_eeg", n_heldout, seed=synth.workloads.SEED_SUR_HELDOUT)
     cidx = synth.surrogate_cards(n_heldout).astype(np.int32)
@@ -214,33 +220,31 @@ def evaluate(torch, ctx, sur, rows, net_dev, n_heldout, threshold, log=print, re
     sur_w = torch.empty(n_heldout, dtype=torch.float64, device="cuda")
     _abi.rwgt_set_stream(ctx, None)
 
-    def timed(thr, out):
-        nfb = _abi.rwgt_sur_eval(ctx, sur.mlp, mom, w, rows, cd, thr, out)
+    def timed(fn):
+        r = fn()
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(reps):
-            nfb = _abi.rwgt_sur_eval(ctx, sur.mlp, mom, w, rows, cd, thr, out)
+            r = fn()
         torch.cuda.synchronize()
-        return (time.perf_counter() - t) / reps * 1e3, nfb
-    exact_ms, _ = timed(0.0, exact)          # threshold 0: every event exact
-    sur_ms, nfb = timed(threshold, sur_w)
+        return (time.perf_counter() - t) / reps * 1e3, r
+
+    exact_ms, _ = timed(lambda: _abi.rwgt_eval_cards(ctx, mom, w, rows, cd, exact))
     e = exact.cpu().numpy()
-    s = sur_w.cpu().numpy()
-    rel = np.abs(s / e - 1.0)
-    used = rel > 0
-    # network-only throughput (features + forward) for reference
-    mu, _ = sur.predict(torch, mom, cd, net_dev)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(reps):
-        sur.predict(torch, mom, cd, net_dev)
-    torch.cuda.synchronize()
-    net_ms = (time.perf_counter() - t) / reps * 1e3
-    res = {"heldout_events": n_heldout, "threshold": threshold, "fallback": int(nfb),
-           "fallback_fraction": nfb / n_heldout, "max_rel_err": float(rel.max()),
-           "p999_rel_err": float(np.quantile(rel, 0.999)), "events_beyond_threshold": int(np.sum(rel > threshold)),
-           "surrogate_path_ms": sur_ms, "exact_path_ms": exact_ms, "network_only_ms": net_ms,
-           "gain": exact_ms / sur_ms, "surrogate_value": n_heldout / (sur_ms * 1e-3),
-           "exact_value": n_heldout / (exact_ms * 1e-3), "n_network_evaluated": int(used.sum())}
+    # network only (fused features + layers + heads, no gate) for reference
+    net_ms, _ = timed(lambda: sur.predict(torch, mom, cd, net_dev))
+    points = []
+    for thr in (threshold,) + tuple(extra_thresholds):
+        sur_ms, nfb = timed(lambda: _abi.rwgt_sur_eval(ctx, sur.mlp, mom, w, rows, cd, thr, sur_w))
+        s = sur_w.cpu().numpy()
+        rel = np.abs(s / e - 1.0)
+        points.append({"threshold": thr, "fallback": int(nfb), "fallback_fraction": nfb / n_heldout,
+                       "max_rel_err": float(rel.max()), "p999_rel_err": float(np.quantile(rel, 0.999)),
+                       "events_beyond_threshold": int(np.sum(rel > thr)), "surrogate_path_ms": sur_ms,
+                       "gain": exact_ms / sur_ms, "surrogate_value": n_heldout / (sur_ms * 1e-3)})
+    res = {"heldout_events": n_heldout, "exact_path_ms": exact_ms, "exact_value": n_heldout / (exact_ms * 1e-3),
+           "network_only_ms": net_ms}
+    res.update(points[0])
+    res["other_thresholds"] = points[1:]
     log(f"held-out: {res}")
     return res

@@ -1,11 +1,22 @@
 """Surrogate network kernels against the FP64 reference network (oracle/mlp.py)
 and the surrogate reweighting path against the exact one.
 
-Tolerances: the FP32 form (VALU GEMM, FP32 activations) differs from the
+Tolerances: an FP32 network (VALU GEMMs, FP32 activations) differs from the
 FP64 reference by FP32 rounding accumulated over sums of at most 256 terms
-per layer: 1e-5 relative on each layer's gradient norm and on the heads.  The
-BF16 form rounds weights, activations and backpropagated gradients to 8
-significant bits: 2e-2 relative.
+per layer: 1e-5 relative on each layer's gradient norm and on the heads.  A
+BF16 network keeps its first layer and head in FP32 but rounds the hidden
+weights, the activations entering the hidden layers and the gradients
+flowing back through them to 8 significant bits: 2e-2 relative.  Features
+are computed in FP64 and stored in FP32: 2e-6 relative (plus 1e-6 absolute
+for values near zero).  The fused kernel against the layered forward pass:
+both evaluate the same BF16 network with the same arithmetic (first layer as
+three BF16 products of split FP32 operands, BF16 hidden layers, FP32 head)
+in different summation orders.  Rows agree to FP32 rounding (median 1e-5 of
+the heads' spread, 95 % of rows within 1e-4) except where a hidden activation
+lands on the other side of a BF16 rounding boundary (one BF16 step, 2^-8 of
+that activation); in an untrained network whose layers amplify perturbations
+such a cascade stays below 0.1 of the spread.  A wrong packing or lane order
+moves every row by O(spread).
 """
 import numpy as np
 import pytest
@@ -28,25 +39,18 @@ def _bf16(a):
     return r.astype(np.uint32).view(np.float32)
 
 
-def _params(seed):
+def _params(seed, shapes=SHAPES):
     rng = np.random.default_rng(seed)
-    ps = [(rng.uniform(-1, 1, s) * np.sqrt(6.0 / s[1]), rng.normal(size=s[0]) * 0.05) for s in SHAPES]
+    ps = [(rng.uniform(-1, 1, s) * np.sqrt(6.0 / s[1]), rng.normal(size=s[0]) * 0.05) for s in shapes]
     return omlp.pack(ps).astype(np.float32)
 
 
-def _inputs(rows, n, seed, bf16):
+def _inputs(rows, n, seed):
     rng = np.random.default_rng(seed)
     x = np.zeros((rows, 32), dtype=np.float32)
     x[:n, :N_IN] = rng.normal(size=(n, N_IN)).astype(np.float32)
     y = (rng.normal(size=rows) * 0.2).astype(np.float32)
-    if bf16:
-        x = _bf16(x)
     return x, y
-
-
-def _device_x(torch, x, bf16):
-    t = torch.as_tensor(x).cuda()
-    return t.to(torch.bfloat16).contiguous() if bf16 else t
 
 
 @pytest.mark.parametrize("mode,tol", [(1, 1e-5), (0, 2e-2)])
@@ -54,17 +58,17 @@ def test_gradients_and_heads_vs_reference(mode, tol):
     print(f"[case] mlp gradients mode={mode}", flush=True)
     torch = torch_cuda()
     import paper_2510_05100_amd as rw
-    bf16 = mode == 0
-    n, lam = 200, 0.3
+    n, lam, scale = 200, 0.3, (0.05, 0.4)
     flat = _params(11)
     m = rw.rwgt_mlp_create(N_IN, WIDTH, DEPTH, 2, mode, 1)
     try:
         rw.rwgt_mlp_set_stream(m, None)
         rw.rwgt_mlp_set_training(m, lam)
+        rw.rwgt_mlp_set_target_scale(m, *scale)
         rw.rwgt_mlp_set_params(m, flat)
         np.testing.assert_array_equal(rw.rwgt_mlp_get_params(m), flat)
-        x, y = _inputs(256, n, 5, bf16)
-        xd, yd = _device_x(torch, x, bf16), torch.as_tensor(y).cuda()
+        x, y = _inputs(256, n, 5)
+        xd, yd = torch.as_tensor(x).cuda(), torch.as_tensor(y).cuda()
         heads = torch.zeros((n, 32), dtype=torch.float32, device="cuda")
         rw.rwgt_mlp_forward(m, xd, n, heads)
         rw.rwgt_mlp_train_step(m, xd, yd, n, 0.0)
@@ -73,13 +77,15 @@ def test_gradients_and_heads_vs_reference(mode, tol):
     finally:
         rw.rwgt_mlp_destroy(m)
     ref_params = omlp.unpack(flat.astype(np.float64), SHAPES)
-    if bf16:                                   # the device multiplies with BF16 copies of the weights
-        ref_params = [(_bf16(w.astype(np.float32)).astype(np.float64), b) for w, b in ref_params]
+    if mode == 0:                              # BF16 copies of the hidden (width x width) weights
+        ref_params = [(_bf16(w.astype(np.float32)).astype(np.float64) if 0 < i < len(SHAPES) - 1 else w, b)
+                      for i, (w, b) in enumerate(ref_params)]
     xr = x[:n, :N_IN].astype(np.float64)
     ref_heads, _ = omlp.forward(ref_params, xr)
+    ref_out = np.stack([ref_heads[:, 0] * scale[1] + scale[0], ref_heads[:, 1] + np.log(scale[1])], axis=1)
     got = heads.cpu().numpy()[:, :2]
-    assert np.max(np.abs(got - ref_heads)) <= tol * np.max(np.abs(ref_heads)) + 1e-7
-    ref_g = omlp.gradients(ref_params, xr, y[:n].astype(np.float64), lam)
+    assert np.max(np.abs(got - ref_out)) <= tol * np.max(np.abs(ref_out)) + 1e-6
+    ref_g = omlp.gradients(ref_params, xr, y[:n].astype(np.float64), lam, scale=scale)
     got_g = omlp.unpack(grads.astype(np.float64), SHAPES)
     for (gw, gb), (rw_, rb) in zip(got_g, ref_g):
         assert np.linalg.norm(gw - rw_) <= tol * np.linalg.norm(rw_) + 1e-12
@@ -112,6 +118,83 @@ def test_features_kernel():
     assert np.all(got[:100, N_IN:] == 0) and np.all(got[100:] == 0)
 
 
+def test_phys_features_and_normalisation_vs_oracle():
+    print("[case] mlp physics features", flush=True)
+    torch = torch_cuda()
+    import paper_2510_05100_amd as rw
+    n = 400
+    p = synth.events("uu_eeg", 150)
+    rng = np.random.default_rng(8)
+    ev = rng.integers(0, 150, n).astype(np.int32)
+    cards = np.array([[91.0, 2.5, 0.23], [90.5, 2.3, 0.22], [91.9, 2.7, 0.2312]], dtype=np.float32)
+    cidx = rng.integers(0, 3, n).astype(np.int32)
+    orig = (synth.ORIG_EW.MZ, synth.ORIG_EW.WZ)
+    n_in = rw.n_features(rw.RWGT_FEAT_PHYS, 5)
+    m = rw.rwgt_mlp_create(n_in, 128, 3, 2, 0, 0)
+    try:
+        rw.rwgt_mlp_set_stream(m, None)
+        rw.rwgt_mlp_set_features(m, rw.RWGT_FEAT_PHYS, 5, (2, 3), orig)
+        pd, evd, cd = dev(p), torch.as_tensor(ev).cuda(), torch.as_tensor(cidx).cuda()
+        card_d = torch.as_tensor(cards).cuda()
+        x = torch.zeros(rw.rwgt_mlp_input_bytes(m, n) // 4, dtype=torch.float32, device="cuda")
+        rw.rwgt_mlp_features(m, pd, evd, cd, card_d, n, x)
+        torch.cuda.synchronize()
+        got = x.cpu().numpy().reshape(-1, 32)
+        rw.rwgt_mlp_fit_normalisation(m, pd, evd, cd, card_d, n)
+        mean, std, _ = rw.rwgt_mlp_get_normalisation(m, n_in)
+    finally:
+        rw.rwgt_mlp_destroy(m)
+    want = omlp.phys_features(p[ev], cards[cidx].astype(np.float64), (2, 3), orig)
+    assert want.shape == (n, n_in)
+    np.testing.assert_allclose(got[:n, :n_in], want, rtol=2e-6, atol=1e-6)
+    assert np.all(got[:n, n_in:] == 0) and np.all(got[n:] == 0)
+    sd = want.std(axis=0)
+    np.testing.assert_allclose(mean, want.mean(axis=0), rtol=1e-5, atol=1e-5 * sd.max())
+    np.testing.assert_allclose(std, np.where(sd > 0, sd, 1.0), rtol=1e-4)
+
+
+@pytest.mark.parametrize("width,depth,kind", [(128, 3, 1), (256, 4, 1), (256, 2, 0)])
+def test_fused_predict_matches_layered_forward(width, depth, kind):
+    print(f"[case] fused predict width={width} depth={depth} kind={kind}", flush=True)
+    torch = torch_cuda()
+    import paper_2510_05100_amd as rw
+    n = 3000 + 37                              # many 128-row workgroups and a ragged tail
+    p = synth.events("uu_eeg", 1000)
+    rng = np.random.default_rng(12)
+    ev = rng.integers(0, 1000, n).astype(np.int32)
+    cards = np.stack([[c.MZ, c.WZ, c.sw2] for c in synth.batch_grid()]).astype(np.float32)
+    cidx = rng.integers(0, len(cards), n).astype(np.int32)
+    n_in = rw.n_features(kind, 5)
+    shapes = [(width, n_in)] + [(width, width)] * (depth - 1) + [(2, width)]
+    m = rw.rwgt_mlp_create(n_in, width, depth, 2, 0, 0)
+    try:
+        rw.rwgt_mlp_set_stream(m, None)
+        rw.rwgt_mlp_set_features(m, kind, 5, (2, 3), (synth.ORIG_EW.MZ, synth.ORIG_EW.WZ))
+        rw.rwgt_mlp_set_params(m, _params(21, shapes))
+        pd, evd, cd = dev(p), torch.as_tensor(ev).cuda(), torch.as_tensor(cidx).cuda()
+        card_d = torch.as_tensor(cards).cuda()
+        rw.rwgt_mlp_fit_normalisation(m, pd, evd, cd, card_d, n)
+        rw.rwgt_mlp_set_target_scale(m, 0.01, 0.06)
+        x = torch.zeros(rw.rwgt_mlp_input_bytes(m, n) // 4, dtype=torch.float32, device="cuda")
+        rw.rwgt_mlp_features(m, pd, evd, cd, card_d, n, x)
+        layered = torch.zeros((n, 32), dtype=torch.float32, device="cuda")
+        rw.rwgt_mlp_forward(m, x, n, layered)
+        fused = torch.full((n, 2), np.nan, dtype=torch.float32, device="cuda")
+        rw.rwgt_mlp_predict(m, pd, evd, cd, card_d, n, fused)
+        torch.cuda.synchronize()
+        a, b = layered.cpu().numpy()[:, :2], fused.cpu().numpy()
+    finally:
+        rw.rwgt_mlp_destroy(m)
+    assert np.all(np.isfinite(b))
+    for col in range(2):
+        d = np.abs(a[:, col] - b[:, col])
+        spread = a[:, col].std()
+        print(f"head {col}: median |diff| {np.median(d):.3g}, max {d.max():.3g}, spread {spread:.3g}", flush=True)
+        assert np.median(d) <= 1e-5 * spread
+        assert np.mean(d <= 1e-4 * spread) >= 0.95
+        assert d.max() <= 0.1 * spread
+
+
 def test_training_reduces_loss():
     print("[case] mlp training", flush=True)
     torch = torch_cuda()
@@ -125,8 +208,9 @@ def test_training_reduces_loss():
     try:
         rw.rwgt_mlp_set_stream(m, None)
         rw.rwgt_mlp_set_training(m, 0.05)
-        xd = torch.as_tensor(x).cuda().to(torch.bfloat16).contiguous()
+        xd = torch.as_tensor(x).cuda()
         yd = torch.as_tensor(y).cuda()
+        rw.rwgt_mlp_fit_target_scale(m, yd)
         loss = torch.zeros(1, dtype=torch.float32, device="cuda")
         losses = []
         for step in range(300):
@@ -173,6 +257,11 @@ def test_surrogate_path_fallback_is_exact():
             torch.cuda.synchronize()
             ref[sel] = o.cpu().numpy()[0]
         assert np.max(rel_err(exact.cpu().numpy(), ref)) < 1e-14
+        # the exact card-per-event entry point: the same values, bit for bit
+        direct = torch.empty(n, dtype=torch.float64, device="cuda")
+        rw.rwgt_eval_cards(ctx, pd, wd, table, cd, direct)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(direct.cpu().numpy(), exact.cpu().numpy())
         # huge threshold: no exact evaluation, w' = w exp(mu)
         nfb = rw.rwgt_sur_eval(ctx, m, pd, wd, table, cd, 1e30, out)
         assert nfb == 0
@@ -194,14 +283,68 @@ def test_surrogate_path_fallback_is_exact():
         rw.rwgt_destroy(ctx)
 
 
+@pytest.mark.parametrize("fused", [False, True])
+def test_fused_gate_fallback_is_exact(fused):
+    """Gate of a fused-eligible network (one kernel) and of a layered one:
+    events it sends to the exact path carry the exact w' bit for bit, the
+    others w exp(mu) of that network's own prediction."""
+    print(f"[case] gate fused={fused}", flush=True)
+    torch = torch_cuda()
+    import paper_2510_05100_amd as rw
+    n = 5000
+    p = synth.events("uu_eeg", n)
+    grid = synth.batch_grid()
+    table = np.stack([c.row("uu_eeg") for c in grid])
+    cards = np.stack([[c.MZ, c.WZ, c.sw2] for c in grid]).astype(np.float32)
+    cidx = (np.arange(n) * 7 % len(grid)).astype(np.int32)
+    w = np.linspace(0.5, 2, n)
+    kind = rw.RWGT_FEAT_PHYS
+    n_in = rw.n_features(kind, 5)
+    ctx = rw.rwgt_create(PROCESS_TEXT["uu_eeg"], synth.ORIG_EW.slha(), 0)
+    m = rw.rwgt_mlp_create(n_in, 128 if fused else 96, 3, 2, 0, 3)
+    try:
+        rw.rwgt_set_stream(ctx, None)
+        rw.rwgt_mlp_set_stream(m, None)
+        rw.rwgt_mlp_set_features(m, kind, 5, (2, 3), (synth.ORIG_EW.MZ, synth.ORIG_EW.WZ))
+        pd, wd, cd = dev(p), dev(w), torch.as_tensor(cidx).cuda()
+        card_d = torch.as_tensor(cards).cuda()
+        rw.rwgt_mlp_fit_normalisation(m, pd, None, cd, card_d, n)
+        rw.rwgt_mlp_set_target_scale(m, 0.0, 0.02)
+        exact = torch.empty(n, dtype=torch.float64, device="cuda")
+        assert rw.rwgt_sur_eval(ctx, m, pd, wd, table, cd, 0.0, exact) == n
+        # heads of the same network, then a threshold at their median error bound
+        x = torch.zeros(rw.rwgt_mlp_input_bytes(m, n) // 4, dtype=torch.float32, device="cuda")
+        rw.rwgt_mlp_features(m, pd, None, cd, card_d, n, x)
+        heads = torch.zeros((n, 32), dtype=torch.float32, device="cuda")
+        rw.rwgt_mlp_forward(m, x, n, heads)
+        torch.cuda.synchronize()
+        h = heads.cpu().numpy()
+        thr = float(np.median(3.3 * np.exp(h[:, 1])))
+        out = torch.full((n,), np.nan, dtype=torch.float64, device="cuda")
+        nfb = rw.rwgt_sur_eval(ctx, m, pd, wd, table, cd, thr, out)
+        torch.cuda.synchronize()
+        o, e = out.cpu().numpy(), exact.cpu().numpy()
+    finally:
+        rw.rwgt_mlp_destroy(m)
+        rw.rwgt_destroy(ctx)
+    assert 0 < nfb < n and np.all(np.isfinite(o))
+    same = o == e
+    assert same.sum() >= nfb                   # every fallback event is exact, bit for bit
+    net = ~same
+    approx = w[net] * np.exp(h[net, 0].astype(np.float64))
+    np.testing.assert_allclose(o[net], approx, rtol=2e-3)   # the fused heads agree with the layered ones
+    # the sum of the two sets is every event once
+    assert net.sum() <= n - nfb
+
+
 def test_surrogate_workflow_small():
-    """Train on exact ratios, calibrate, evaluate with fallback (small sizes)."""
+    """Train, calibrate, evaluate with fallback (small sizes)."""
     print("[case] surrogate workflow", flush=True)
     torch = torch_cuda()
     from paper_2510_05100_amd import surrogate
-    cfg = surrogate.Config(width=64, depth=2, epochs=3, batch=1024)
-    summary, sur, (mean, std) = surrogate.run(torch, cfg, n_train=2000, n_heldout=20000, threshold=1e-2,
-                                              log=lambda *a: print(*a, flush=True))
+    cfg = surrogate.Config(width=128, depth=2, epochs=3, batch=1024)
+    summary, sur = surrogate.run(torch, cfg, n_train=2000, n_heldout=20000, threshold=1e-2,
+                                 log=lambda *a: print(*a, flush=True))
     try:
         assert summary["train_pairs"] == 2000 * 64
         assert summary["calibration"]["k"] > 0
