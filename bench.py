@@ -70,6 +70,7 @@ def parse():
     ap.add_argument("--modes", default="fp64,mixed")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-factored", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 512 MiB device copy (scale reference for HBM byte counters)")
     return ap.parse_args()
@@ -186,6 +187,38 @@ def batched_leg(rw, torch, precision, steps, warmup):
             "max_rel_diff_vs_plain": diff, "unit": "reweighted events/s"}
 
 
+def factored_leg(rw, torch, steps, warmup, n=1_000_000):
+    """u u~ -> e+ e- g, n events x the 64-card grid: the full path (1 + 64
+    matrix-element evaluations per event) against the coupling-factored path
+    (4 probe evaluations per event, then a few operations per card)."""
+    import synth
+    p = synth.events("uu_eeg", n)
+    rows = np.stack([c.row("uu_eeg") for c in synth.batch_grid()])
+    p_dev = torch.as_tensor(p).cuda()
+    w_dev = torch.ones(n, dtype=torch.float64, device="cuda")
+    full = torch.empty((rows.shape[0], n), dtype=torch.float64, device="cuda")
+    fac = torch.empty_like(full)
+    r = rw.Reweighter("u u~ > e+ e- g", synth.ORIG_EW.slha())
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps * 1e3
+    full_ms = timed(lambda: r.eval(p_dev, w_dev, rows, full))
+    fac_ms = timed(lambda: r.eval_factored(p_dev, w_dev, rows, fac))
+    diff = float(torch.max(torch.abs(fac - full) / torch.abs(full)).item())
+    r.close()
+    pairs = n * rows.shape[0]
+    return {"events": n, "cards": int(rows.shape[0]), "full_ms": full_ms, "factored_ms": fac_ms,
+            "full_value": pairs / (full_ms * 1e-3), "factored_value": pairs / (fac_ms * 1e-3),
+            "speedup": full_ms / fac_ms, "max_rel_diff": diff, "unit": "reweighted (event, card) pairs/s"}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -244,6 +277,9 @@ def main():
             line["batched"][mode] = batched_leg(rw, torch, prec, steps=5, warmup=2)
             log(f"batched {mode}: {line['batched'][mode]['batched_ms']:.2f} ms vs plain "
                 f"{line['batched'][mode]['plain_ms']:.2f} ms")
+    if not a.no_factored:
+        line["factored"] = factored_leg(rw, torch, steps=5, warmup=2)
+        log(f"factored: {line['factored']['factored_ms']:.2f} ms vs full {line['factored']['full_ms']:.2f} ms")
     if not a.no_surrogate:
         from paper_2510_05100_amd import surrogate
         summary, sur = surrogate.run(torch, surrogate.Config(), log=log)

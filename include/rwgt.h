@@ -87,6 +87,20 @@ int rwgt_set_stream(rwgt_ctx *ctx, void *stream);
 int rwgt_eval(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const double *weights_in,
               const double *param_sets, int32_t nsets, double *weights_out);
 
+/* Coupling-factored reweighting: the same result as rwgt_eval (up to
+ * rounding), cheaper when there are many cards.  For e+ e- > mu+ mu- and
+ * u u~ > e+ e- g every helicity amplitude factorises into a card-independent
+ * kinematic part and F = A/s + B/(s - M_Z^2 + i M_Z Gamma_Z), with A and B
+ * products of the two fermion lines' photon and Z couplings (B per chirality
+ * class of the lines) and s the lepton pair's invariant mass; four probe
+ * evaluations per event (Z couplings on one class) give the class weights,
+ * then each card costs a few operations per event.  For g g > t t~ g g the
+ * cards change alpha_s only and |M|^2 scales as alpha_s^4 (one evaluation).
+ * Cost: 4 (or 1) matrix-element evaluations per event instead of 1 + nsets.
+ * Errors as rwgt_eval. */
+int rwgt_eval_factored(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const double *weights_in,
+                       const double *param_sets, int32_t nsets, double *weights_out);
+
 /* |M|^2 itself for each card of param_sets: me2_out[k][i].  Same rules as rwgt_eval. */
 int rwgt_me2(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const double *param_sets, int32_t nsets,
              double *me2_out);

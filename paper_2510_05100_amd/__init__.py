@@ -19,7 +19,7 @@ from ._abi import (  # noqa: F401
 from ._abi import (  # noqa: F401
     RWGT_FP64, RWGT_MIXED_BF16, RWGT_MIXED_FP16, RwgtError, load, rwgt_create, rwgt_destroy, rwgt_eval,
     rwgt_flops, rwgt_kernel_times, rwgt_me2, rwgt_original_params, rwgt_param_layout, rwgt_process_info,
-    rwgt_set_profiling, rwgt_set_stream, rwgt_xsec,
+    rwgt_set_profiling, rwgt_set_stream, rwgt_xsec, rwgt_eval_factored,
 )
 
 
@@ -33,6 +33,10 @@ class Reweighter:
     def eval(self, momenta, weights_in, param_sets, weights_out, stream=None):
         rwgt_set_stream(self.ctx, stream)
         rwgt_eval(self.ctx, momenta, weights_in, param_sets, weights_out)
+
+    def eval_factored(self, momenta, weights_in, param_sets, weights_out, stream=None):
+        rwgt_set_stream(self.ctx, stream)
+        rwgt_eval_factored(self.ctx, momenta, weights_in, param_sets, weights_out)
 
     def me2(self, momenta, param_sets, me2_out, stream=None):
         rwgt_set_stream(self.ctx, stream)

@@ -28,6 +28,8 @@ SIGNATURES = {
     "rwgt_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rwgt_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                   ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_void_p]),
+    "rwgt_eval_factored": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_void_p]),
     "rwgt_me2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                  ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_void_p]),
     "rwgt_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
@@ -207,6 +209,21 @@ def rwgt_eval(ctx, momenta, weights_in, param_sets, weights_out):
     if weights_out.numel() != params.shape[0] * nevt or weights_in.numel() != nevt:
         raise ValueError("weights_in must be [nevt] and weights_out [nsets, nevt]")
     rc = load().rwgt_eval(ctx, _ptr(momenta), nevt, _ptr(weights_in), pptr, params.shape[0], _ptr(weights_out))
+    if rc != 0:
+        _raise(rc, ctx)
+
+
+def rwgt_eval_factored(ctx, momenta, weights_in, param_sets, weights_out):
+    """As rwgt_eval, through the coupling-factored path."""
+    _check_device(momenta, "momenta")
+    _check_device(weights_in, "weights_in")
+    _check_device(weights_out, "weights_out")
+    nevt = momenta.shape[0] if momenta.dim() > 0 else 0
+    params, pptr = _host_params(param_sets)
+    if weights_out.numel() != params.shape[0] * nevt or weights_in.numel() != nevt:
+        raise ValueError("weights_in must be [nevt] and weights_out [nsets, nevt]")
+    rc = load().rwgt_eval_factored(ctx, _ptr(momenta), nevt, _ptr(weights_in), pptr, params.shape[0],
+                                   _ptr(weights_out))
     if rc != 0:
         _raise(rc, ctx)
 

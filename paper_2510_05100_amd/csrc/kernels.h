@@ -26,6 +26,20 @@ hipError_t launch_me(int proc, int precision, const double* soa, int64_t nevt, c
 hipError_t launch_xsec(const double* w_in, const double* w_out, int64_t nevt, int nsets, double sigma, double dsigma,
                        double norm, double* part, int nblocks, double* out, hipStream_t s);
 
+// One card of the coupling-factored path (kernels.hip, factored_kernel).
+struct FactorCard {
+  double A;        // product of the two fermion lines' photon couplings
+  double B[4];     // products of their Z couplings: LL, LR, RL, RR
+  double mz, wz;   // Z mass and width
+  double g;        // overall factor relative to the probe cards
+};
+
+// w_out[k-1][i] for cards fc[1..ncards) against fc[0] from the probe |M|^2
+// (ew: [4][nevt] class probes and the resonant pair (ia, ib); else [1][nevt]).
+hipError_t launch_factored(bool ew, const double* soa, int64_t nevt, int ia, int ib, const double* probe, double mzp,
+                           double wzp, const FactorCard* fc, int ncards, const double* w_in, double* w_out,
+                           hipStream_t s);
+
 void process_constants(int proc, int* npart, int* ngood, int* ncol, int* ndiag);
 double process_flops(int proc);
 

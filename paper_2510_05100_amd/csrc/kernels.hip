@@ -2,6 +2,8 @@
 //   ingest_kernel  AoS [nevt][npart][4] -> SoA [npart*4][nevt] through LDS
 //   launch_me      dispatch to the per-process matrix-element kernels
 //                  (me_kernel.h, proc_<name>.hip)
+//   xsec_*         reweighted cross sections and errors per card
+//   factored       coupling-factored reweighting of many cards
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -89,6 +91,75 @@ hipError_t launch_xsec(const double* w_in, const double* w_out, int64_t nevt, in
                        double norm, double* part, int nblocks, double* out, hipStream_t s) {
   hipLaunchKernelGGL(xsec_partial, dim3(nblocks, nsets), dim3(kXsecBlock), 0, s, w_in, w_out, nevt, part);
   hipLaunchKernelGGL(xsec_final, dim3(nsets), dim3(64), 0, s, part, nblocks, nevt, sigma, dsigma, norm, out);
+  return hipGetLastError();
+}
+
+// Coupling-factored reweighting.  Electroweak family: every kept helicity
+// amplitude is K_h(p) F_chi(card, s), chi the chirality class (LL, LR, RL, RR)
+// of the two fermion lines, s the invariant mass of the resonant pair and
+//   F_chi = A / s + B_chi / (s - M_Z^2 + i M_Z Gamma_Z)
+// (A: product of the lines' photon couplings, B_chi: of their Z couplings),
+// so |M|^2 = g sum_chi W_chi |F_chi|^2.  The class weights W_chi of an event
+// come from four probe cards (Z couplings 1 on one class, all others 0):
+// W_chi = |M|^2_probe,chi |s - M_p^2 + i M_p Gamma_p|^2.  QCD family (cards
+// change alpha_s only): |M|^2 = g |M|^2_probe with g = (g_s / g_s,0)^8.
+// Card 0 is the original card; w_out[k-1][i] = (w_in[i] / |M|^2_0) |M|^2_k.
+template <bool EW>
+__global__ __launch_bounds__(256) void factored_kernel(const double* __restrict__ soa, int64_t nevt, int ia, int ib,
+                                                       const double* __restrict__ probe, double mzp, double wzp,
+                                                       const FactorCard* __restrict__ fc, int ncards,
+                                                       const double* __restrict__ w_in, double* __restrict__ w_out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nevt) return;
+  double W[4] = {0.0, 0.0, 0.0, 0.0};
+  double s = 0.0;
+  if constexpr (EW) {
+    double pa[4], pb[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      pa[mu] = soa[int64_t(ia * 4 + mu) * nevt + i];
+      pb[mu] = soa[int64_t(ib * 4 + mu) * nevt + i];
+    }
+    s = 2.0 * (pa[0] * pb[0] - pa[1] * pb[1] - pa[2] * pb[2] - pa[3] * pb[3]);
+    const double xp = s - mzp * mzp, yp = mzp * wzp;
+    const double dp = xp * xp + yp * yp;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) W[c] = probe[int64_t(c) * nevt + i] * dp;
+  } else {
+    W[0] = probe[i];
+  }
+  auto me2 = [&](const FactorCard& k) {
+    if constexpr (EW) {
+      const double x = s - k.mz * k.mz, y = k.mz * k.wz;
+      const double d = x * x + y * y;
+      const double ga = k.A / s, gr = x / d, gi = -y / d;
+      double sum = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double re = ga + k.B[c] * gr, im = k.B[c] * gi;
+        sum += W[c] * (re * re + im * im);
+      }
+      return k.g * sum;
+    } else {
+      return k.g * W[0];
+    }
+  };
+  const double m0 = me2(fc[0]);
+  const double norm = m0 != 0.0 ? w_in[i] * (1.0 / m0) : 0.0;
+  for (int k = 1; k < ncards; ++k) w_out[int64_t(k - 1) * nevt + i] = norm * me2(fc[k]);
+}
+
+hipError_t launch_factored(bool ew, const double* soa, int64_t nevt, int ia, int ib, const double* probe, double mzp,
+                           double wzp, const FactorCard* fc, int ncards, const double* w_in, double* w_out,
+                           hipStream_t s) {
+  if (nevt <= 0) return hipSuccess;
+  const unsigned blocks = unsigned((nevt + 255) / 256);
+  if (ew)
+    hipLaunchKernelGGL(factored_kernel<true>, dim3(blocks), dim3(256), 0, s, soa, nevt, ia, ib, probe, mzp, wzp, fc,
+                       ncards, w_in, w_out);
+  else
+    hipLaunchKernelGGL(factored_kernel<false>, dim3(blocks), dim3(256), 0, s, soa, nevt, ia, ib, probe, mzp, wzp, fc,
+                       ncards, w_in, w_out);
   return hipGetLastError();
 }
 

@@ -169,6 +169,11 @@ struct rwgt_ctx {
   float* sur_cpar = nullptr;
   int64_t sur_cap = 0;
   int sur_card_cap = 0;
+  // coupling-factored path: probe |M|^2 and per-card factors
+  double* fac_probe = nullptr;
+  int64_t fac_probe_cap = 0;
+  rwgt::FactorCard* fac_cards = nullptr;
+  int fac_cards_cap = 0;
   std::string err;
 
   int fail(int code, const std::string& msg) {
@@ -188,7 +193,8 @@ struct rwgt_ctx {
     if (dcards) hipFree(dcards);
     if (hcards) hipHostFree(hcards);
     for (void* p : {sur_x, static_cast<void*>(sur_list), static_cast<void*>(sur_count), static_cast<void*>(sur_heads),
-                    static_cast<void*>(sur_cards), static_cast<void*>(sur_cpar)})
+                    static_cast<void*>(sur_cards), static_cast<void*>(sur_cpar), static_cast<void*>(fac_probe),
+                    static_cast<void*>(fac_cards)})
       if (p) hipFree(p);
   }
 };
@@ -352,6 +358,110 @@ int rwgt_eval(rwgt_ctx* ctx, const double* momenta, int64_t nevt, const double* 
     return run(ctx, true, momenta, nevt, weights_in, param_sets, nsets, weights_out, nullptr);
   } catch (const std::exception& ex) {
     return ctx->fail(RWGT_ENOMEM, ex.what());
+  }
+}
+
+// Coupling-factored reweighting (same result as rwgt_eval).  Electroweak
+// processes: the two fermion lines (species f1, f2 of the card's coupling
+// arrays) and the resonant pair (ia, ib); four probe cards give each event's
+// chirality-class weights, then every card costs a few operations per event.
+// QCD process: cards change alpha_s only and |M|^2 scales as g_s^8.
+int rwgt_eval_factored(rwgt_ctx* c, const double* momenta, int64_t nevt, const double* w_in,
+                       const double* param_sets, int32_t nsets, double* w_out) {
+  if (!c) return RWGT_EINVAL;
+  c->err.clear();
+  if (nevt < 0) return c->fail(RWGT_EINVAL, "nevt < 0");
+  if (nsets < 1) return c->fail(RWGT_EINVAL, "nsets < 1");
+  if (!param_sets) return c->fail(RWGT_EINVAL, "param_sets is NULL");
+  try {
+    std::vector<CardPair> cards;
+    int rc = build_cards(c, param_sets, nsets, true, cards);
+    if (rc != RWGT_OK) return rc;
+    if (nevt == 0) return RWGT_OK;
+    if (!momenta || !w_in || !w_out) return c->fail(RWGT_EINVAL, "NULL device pointer");
+    const int id = c->def->id;
+    const bool ew = id != rwgt::kProcGgTtgg;
+    const int f1 = id == rwgt::kProcUuEeg ? 2 : 0;         // u or e line
+    const int f2 = id == rwgt::kProcUuEeg ? 0 : 1;         // e or mu line
+    const int ia = 2, ib = 3;                              // the outgoing lepton pair
+    const Card<double>& o = cards[0].d;
+    std::vector<rwgt::FactorCard> fc(cards.size());
+    for (size_t k = 0; k < cards.size(); ++k) {
+      const Card<double>& q = cards[k].d;
+      rwgt::FactorCard& f = fc[k];
+      f.A = q.a[f1] * q.a[f2];
+      f.B[0] = q.zL[f1] * q.zL[f2];
+      f.B[1] = q.zL[f1] * q.zR[f2];
+      f.B[2] = q.zR[f1] * q.zL[f2];
+      f.B[3] = q.zR[f1] * q.zR[f2];
+      f.mz = q.mz;
+      f.wz = q.wz;
+      const double r = o.gqq != 0.0 ? q.gqq / o.gqq : 0.0;
+      f.g = id == rwgt::kProcEeMumu ? 1.0 : id == rwgt::kProcUuEeg ? r * r : std::pow(r, 8);
+    }
+    // probe cards: EW, the original with every photon and Z coupling zero but
+    // the Z couplings of one chirality class (1 x 1); QCD, the original card
+    std::vector<CardPair> probes;
+    if (ew) {
+      for (int cl = 0; cl < 4; ++cl) {
+        CardPair p = cards[0];
+        for (int f = 0; f < 4; ++f) {
+          p.d.a[f] = p.d.zL[f] = p.d.zR[f] = 0.0;
+          p.f.a[f] = p.f.zL[f] = p.f.zR[f] = 0.0f;
+        }
+        (cl & 2 ? p.d.zR : p.d.zL)[f1] = 1.0;
+        (cl & 1 ? p.d.zR : p.d.zL)[f2] = 1.0;
+        (cl & 2 ? p.f.zR : p.f.zL)[f1] = 1.0f;
+        (cl & 1 ? p.f.zR : p.f.zL)[f2] = 1.0f;
+        probes.push_back(p);
+      }
+    } else {
+      probes.push_back(cards[0]);
+    }
+    const int nprobe = int(probes.size());
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return c->hip_fail(e, "hipSetDevice");
+    rc = ensure_buffers(c, nevt, nprobe);
+    if (rc != RWGT_OK) return rc;
+    if (int64_t(nprobe) * nevt > c->fac_probe_cap) {
+      if (c->fac_probe) { (void)hipStreamSynchronize(c->stream); (void)hipFree(c->fac_probe); c->fac_probe = nullptr; }
+      c->fac_probe_cap = 0;
+      e = hipMalloc(&c->fac_probe, size_t(nprobe) * nevt * sizeof(double));
+      if (e != hipSuccess) return c->hip_fail(e, "hipMalloc(probe |M|^2)");
+      c->fac_probe_cap = int64_t(nprobe) * nevt;
+    }
+    if (int(fc.size()) > c->fac_cards_cap) {
+      if (c->fac_cards) { (void)hipStreamSynchronize(c->stream); (void)hipFree(c->fac_cards); c->fac_cards = nullptr; }
+      c->fac_cards_cap = 0;
+      e = hipMalloc(&c->fac_cards, fc.size() * sizeof(rwgt::FactorCard));
+      if (e != hipSuccess) return c->hip_fail(e, "hipMalloc(factor cards)");
+      c->fac_cards_cap = int(fc.size());
+    }
+    if (c->upload_pending) {
+      e = hipEventSynchronize(c->upload_done);
+      if (e != hipSuccess) return c->hip_fail(e, "hipEventSynchronize");
+      c->upload_pending = false;
+    }
+    std::memcpy(c->hcards, probes.data(), probes.size() * sizeof(CardPair));
+    e = hipMemcpyAsync(c->dcards, c->hcards, probes.size() * sizeof(CardPair), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->upload_done, c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "probe card upload");
+    c->upload_pending = true;
+    // the factor table comes from pageable memory: wait for that copy
+    e = hipMemcpyAsync(c->fac_cards, fc.data(), fc.size() * sizeof(rwgt::FactorCard), hipMemcpyHostToDevice,
+                       c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "factor card upload");
+    e = rwgt::launch_ingest(c->def->npart, momenta, c->soa, nevt, c->stream);
+    if (e == hipSuccess)
+      e = rwgt::launch_me(id, c->precision, c->soa, nevt, c->dcards, nprobe, nullptr, nullptr, c->fac_probe,
+                          c->stream);
+    if (e == hipSuccess)
+      e = rwgt::launch_factored(ew, c->soa, nevt, ia, ib, c->fac_probe, o.mz, o.wz, c->fac_cards, int(fc.size()), w_in,
+                                w_out, c->stream);
+    return e == hipSuccess ? RWGT_OK : c->hip_fail(e, "factored evaluation");
+  } catch (const std::exception& ex) {
+    return c->fail(RWGT_ENOMEM, ex.what());
   }
 }
 
