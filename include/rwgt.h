@@ -310,6 +310,63 @@ int rwgt_sur_eval(rwgt_ctx *ctx, rwgt_mlp *mlp, const double *momenta, int64_t n
                   const double *param_table, int32_t ncards, const int32_t *card_index, double err_threshold,
                   double *weights_out, int64_t *n_fallback);
 
+/* ------------------------------------------------------------------------
+ * Event files (host only, no device work).  An LHE v3 file is read into
+ * memory; its events can be sorted by process (external partons: status -1
+ * incoming, +1 outgoing, matched to the process string's particles by PDG
+ * code, each slot taking the first unused matching parton in file order),
+ * their momenta exported in the process's particle order as the AoS
+ * [n][npart][4] (E, px, py, pz) that rwgt_eval takes, and weights appended:
+ * each new weight id gets a <weight> entry in the header's <initrwgt> and a
+ * <wgt> in every event's <rwgt> block (0 for events it was not set on, the
+ * paper's zero weight for events without a matching process).  Everything
+ * else in the file is written back byte for byte.  Numbers are read
+ * correctly rounded (a leading '+' and Fortran 'D' exponents accepted) and
+ * weights written with 17 significant digits, so they round-trip exactly.
+ */
+typedef struct rwgt_lhe rwgt_lhe;
+
+/* Read a file (path) or a memory buffer (text, len bytes).  Errors:
+ * RWGT_EINVAL (NULL, unreadable file), RWGT_ECARD (malformed: message from
+ * rwgt_lhe_read_error), RWGT_ENOMEM. */
+int rwgt_lhe_read(const char *path, rwgt_lhe **out);
+int rwgt_lhe_parse(const char *text, int64_t len, rwgt_lhe **out);
+const char *rwgt_lhe_read_error(void);
+void rwgt_lhe_destroy(rwgt_lhe *lhe);
+const char *rwgt_lhe_last_error(const rwgt_lhe *lhe);
+int rwgt_lhe_num_events(const rwgt_lhe *lhe, int64_t *n);
+/* Event i: particle count, process id, info = (XWGTUP, SCALUP, AQEDUP, AQCDUP). */
+int rwgt_lhe_event_info(const rwgt_lhe *lhe, int64_t i, int32_t *nup, int32_t *idprup, double *info);
+/* Indices (file order) of the events of a process: *n_match gets the count,
+ * index_out (HOST, capacity cap) the first min(cap, count).  Errors:
+ * RWGT_EPROCESS (unknown particle name). */
+int rwgt_lhe_select(rwgt_lhe *lhe, const char *process, int64_t *index_out, int64_t cap, int64_t *n_match);
+/* HOST momenta [n][npart][4] and (optional) weights [n] = XWGTUP of the
+ * events index[0..n); RWGT_EPROCESS if one does not belong to the process. */
+int rwgt_lhe_momenta(rwgt_lhe *lhe, const char *process, const int64_t *index, int64_t n, double *momenta,
+                     double *weights);
+/* Set weight `id` (no quotes, spaces, '<', '>', '&') of events index[0..n)
+ * to w (HOST); a new id starts at 0 on every event. */
+int rwgt_lhe_add_weights(rwgt_lhe *lhe, const char *id, const char *description, const int64_t *index, int64_t n,
+                         const double *w);
+int rwgt_lhe_write(rwgt_lhe *lhe, const char *path);
+
+/* Layout of a process's param_sets rows without a context (as
+ * rwgt_param_layout); RWGT_EPROCESS for an unsupported process. */
+int rwgt_process_layout(const char *process, int32_t *npar, const char **names);
+
+/* Parameter sets from a reweighting card (the paper's SLHA reweighting:
+ * "launch rwgt_name=NAME" opens a set equal to the original card, "set BLOCK
+ * ID VALUE" overrides an entry; "change fptype X" is reported in fptype[0];
+ * '#' comments).  Rows follow the process's layout (rwgt_param_layout);
+ * entries outside it do not affect the process and are skipped.  Host only:
+ * param_sets [cap][npar], names [cap][name_len] (optional), fptype [2]
+ * (optional, untouched if the card has none).  *nsets gets the number of
+ * sets, possibly above cap (then only cap rows are filled).  Errors:
+ * RWGT_EINVAL, RWGT_EPROCESS, RWGT_ECARD (message from rwgt_create_error). */
+int rwgt_reweight_card(const char *process, const char *param_card, const char *rwgt_card, int32_t cap,
+                       double *param_sets, int32_t *nsets, char *names, int32_t name_len, char *fptype);
+
 #ifdef __cplusplus
 }
 #endif

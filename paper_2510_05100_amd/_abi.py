@@ -100,6 +100,31 @@ SIGNATURES.update({
                                       ctypes.POINTER(ctypes.c_int64)]),
 })
 
+SIGNATURES.update({
+    "rwgt_lhe_read": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "rwgt_lhe_parse": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p)]),
+    "rwgt_lhe_read_error": (ctypes.c_char_p, []),
+    "rwgt_lhe_destroy": (None, [ctypes.c_void_p]),
+    "rwgt_lhe_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "rwgt_lhe_num_events": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "rwgt_lhe_event_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+    "rwgt_lhe_select": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    "rwgt_lhe_momenta": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]),
+    "rwgt_lhe_add_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_char_p,
+                                             ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
+                                             ctypes.POINTER(ctypes.c_double)]),
+    "rwgt_lhe_write": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
+    "rwgt_process_layout": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_char_p)]),
+    "rwgt_reweight_card": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.c_char_p, ctypes.c_int32, ctypes.c_char_p]),
+})
+
 SIGNATURES["rwgt_xsec"] = (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                           ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -577,3 +602,126 @@ def rwgt_xsec(ctx, weights_in, weights_out, sigma, dsigma, norm):
     if rc != 0:
         _raise(rc, ctx)
     return xs, xe, fb.astype(bool)
+
+
+# ----------------------------------------------------------------- event files
+def _lraise(code, lhe):
+    raise RwgtError(code, (load().rwgt_lhe_last_error(lhe) or b"").decode())
+
+
+def _i64(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def _f64(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def rwgt_lhe_read(path):
+    out = ctypes.c_void_p()
+    rc = load().rwgt_lhe_read(str(path).encode(), ctypes.byref(out))
+    if rc != 0:
+        raise RwgtError(rc, (load().rwgt_lhe_read_error() or b"").decode())
+    return out
+
+
+def rwgt_lhe_parse(text):
+    data = text.encode() if isinstance(text, str) else bytes(text)
+    out = ctypes.c_void_p()
+    rc = load().rwgt_lhe_parse(data, len(data), ctypes.byref(out))
+    if rc != 0:
+        raise RwgtError(rc, (load().rwgt_lhe_read_error() or b"").decode())
+    return out
+
+
+def rwgt_lhe_destroy(lhe):
+    if lhe:
+        load().rwgt_lhe_destroy(lhe)
+
+
+def rwgt_lhe_num_events(lhe):
+    n = ctypes.c_int64()
+    rc = load().rwgt_lhe_num_events(lhe, ctypes.byref(n))
+    if rc != 0:
+        _lraise(rc, lhe)
+    return n.value
+
+
+def rwgt_lhe_event_info(lhe, i):
+    """(nup, idprup, (XWGTUP, SCALUP, AQEDUP, AQCDUP))."""
+    nup, idp = ctypes.c_int32(), ctypes.c_int32()
+    info = np.zeros(4)
+    rc = load().rwgt_lhe_event_info(lhe, int(i), ctypes.byref(nup), ctypes.byref(idp), _f64(info))
+    if rc != 0:
+        _lraise(rc, lhe)
+    return nup.value, idp.value, tuple(float(x) for x in info)
+
+
+def rwgt_lhe_select(lhe, process):
+    """Indices (int64 array) of the events of a process."""
+    n = ctypes.c_int64()
+    rc = load().rwgt_lhe_select(lhe, process.encode(), None, 0, ctypes.byref(n))
+    if rc != 0:
+        _lraise(rc, lhe)
+    idx = np.zeros(max(n.value, 1), dtype=np.int64)
+    rc = load().rwgt_lhe_select(lhe, process.encode(), _i64(idx), n.value, ctypes.byref(n))
+    if rc != 0:
+        _lraise(rc, lhe)
+    return idx[:n.value]
+
+
+def rwgt_lhe_momenta(lhe, process, index):
+    """(momenta [n, npart, 4] (E, px, py, pz), XWGTUP [n]) as host arrays."""
+    index = np.ascontiguousarray(index, dtype=np.int64)
+    npart = len(process.replace(">", " ").split())
+    mom = np.zeros((max(index.size, 1), npart, 4))
+    w = np.zeros(max(index.size, 1))
+    rc = load().rwgt_lhe_momenta(lhe, process.encode(), _i64(index), index.size, _f64(mom), _f64(w))
+    if rc != 0:
+        _lraise(rc, lhe)
+    return mom[:index.size], w[:index.size]
+
+
+def rwgt_lhe_add_weights(lhe, weight_id, description, index, w):
+    index = np.ascontiguousarray(index, dtype=np.int64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    if index.size != w.size:
+        raise ValueError("index and weights differ in length")
+    rc = load().rwgt_lhe_add_weights(lhe, weight_id.encode(), (description or "").encode(), _i64(index), index.size,
+                                     _f64(w))
+    if rc != 0:
+        _lraise(rc, lhe)
+
+
+def rwgt_lhe_write(lhe, path):
+    rc = load().rwgt_lhe_write(lhe, str(path).encode())
+    if rc != 0:
+        _lraise(rc, lhe)
+
+
+def rwgt_process_layout(process):
+    """Names of the columns of a process's param_sets rows."""
+    n = ctypes.c_int32()
+    rc = load().rwgt_process_layout(process.encode(), ctypes.byref(n), None)
+    if rc != 0:
+        raise RwgtError(rc, f"unsupported process '{process}'")
+    names = (ctypes.c_char_p * n.value)()
+    load().rwgt_process_layout(process.encode(), ctypes.byref(n), names)
+    return [x.decode() for x in names]
+
+
+def rwgt_reweight_card(process, param_card, rwgt_card, cap=4096, name_len=64):
+    """(param_sets [nsets, npar], names [nsets], fptype or None) from a reweighting card."""
+    npar = len(rwgt_process_layout(process))
+    buf = np.zeros((cap, npar))
+    n = ctypes.c_int32()
+    names = ctypes.create_string_buffer(cap * name_len)
+    fp = ctypes.create_string_buffer(2)
+    rc = load().rwgt_reweight_card(process.encode(), param_card.encode(), rwgt_card.encode(), cap, _f64(buf),
+                                   ctypes.byref(n), names, name_len, fp)
+    if rc != 0:
+        raise RwgtError(rc, (load().rwgt_create_error() or b"").decode())
+    if n.value > cap:
+        return rwgt_reweight_card(process, param_card, rwgt_card, cap=n.value, name_len=name_len)
+    out_names = [names.raw[i * name_len:(i + 1) * name_len].split(b"\0")[0].decode() for i in range(n.value)]
+    return buf[:n.value], out_names, (fp.value.decode() or None)

@@ -480,6 +480,116 @@ const char* rwgt_last_error(const rwgt_ctx* ctx) { return ctx ? ctx->err.c_str()
 
 const char* rwgt_create_error(void) { return g_create_error.c_str(); }
 
+int rwgt_process_layout(const char* process, int32_t* npar, const char** names) {
+  if (!process || !npar) return RWGT_EINVAL;
+  const std::string want = normalise_ws(process);
+  for (const auto& d : processes())
+    if (want == d.text) {
+      *npar = int32_t(d.layout.size());
+      if (names)
+        for (size_t j = 0; j < d.layout.size(); ++j) names[j] = d.layout[j].c_str();
+      return RWGT_OK;
+    }
+  return RWGT_EPROCESS;
+}
+
+// Reweighting card (MadtRex / teaRex SLHA reweighting): "launch
+// [--]rwgt_name=NAME" opens a parameter set initialised to the original
+// card, "set BLOCK ID VALUE" (or "set DECAY PDG VALUE") overrides one entry,
+// "change fptype X" records the requested precision, other "change" lines
+// and '#' comments are ignored.  Entries outside the process's layout do not
+// affect its |M|^2 and are skipped.
+int rwgt_reweight_card(const char* process, const char* param_card, const char* rwgt_card, int32_t cap,
+                       double* param_sets, int32_t* nsets, char* names, int32_t name_len, char* fptype) {
+  g_create_error.clear();
+  if (!process || !param_card || !rwgt_card || !nsets || cap < 0 || (cap > 0 && !param_sets) ||
+      (names && name_len < 2)) {
+    g_create_error = "NULL argument or bad size";
+    return RWGT_EINVAL;
+  }
+  *nsets = 0;
+  const std::string want = normalise_ws(process);
+  const ProcessDef* def = nullptr;
+  for (const auto& d : processes())
+    if (want == d.text) def = &d;
+  if (!def) { g_create_error = "unsupported process '" + want + "'"; return RWGT_EPROCESS; }
+  std::map<std::string, double> card;
+  std::string err;
+  if (!parse_slha(param_card, card, err)) { g_create_error = "param card: " + err; return RWGT_ECARD; }
+  const size_t npar = def->layout.size();
+  std::vector<double> orig(npar);
+  for (size_t j = 0; j < npar; ++j) {
+    auto it = card.find(def->layout[j]);
+    if (it == card.end()) { g_create_error = "param card lacks " + def->layout[j]; return RWGT_ECARD; }
+    orig[j] = it->second;
+  }
+  std::istringstream in(rwgt_card);
+  std::string line;
+  int lineno = 0;
+  int32_t n = 0;
+  std::vector<double> cur;
+  auto flush = [&]() {
+    if (!cur.empty() && n <= cap && n > 0) std::copy(cur.begin(), cur.end(), param_sets + size_t(n - 1) * npar);
+  };
+  while (std::getline(in, line)) {
+    ++lineno;
+    const auto hash = line.find('#');
+    if (hash != std::string::npos) line.resize(hash);
+    std::istringstream ls(line);
+    std::string cmd;
+    if (!(ls >> cmd)) continue;
+    cmd = upper(cmd);
+    const std::string where = "reweight card line " + std::to_string(lineno) + ": ";
+    if (cmd == "LAUNCH") {
+      flush();
+      cur = orig;
+      ++n;
+      std::string name = "rwgt_" + std::to_string(n), opt;
+      while (ls >> opt) {
+        const auto eq = opt.find('=');
+        std::string key = opt.substr(0, eq);
+        while (!key.empty() && key[0] == '-') key.erase(0, 1);
+        if (eq != std::string::npos && key == "rwgt_name") name = opt.substr(eq + 1);
+      }
+      if (names && n <= cap) {
+        char* dst = names + size_t(n - 1) * size_t(name_len);
+        std::snprintf(dst, size_t(name_len), "%s", name.c_str());
+      }
+    } else if (cmd == "SET") {
+      if (cur.empty()) { g_create_error = where + "'set' before the first 'launch'"; return RWGT_ECARD; }
+      std::string block, id, val;
+      if (!(ls >> block >> id >> val)) {
+        g_create_error = where + "expected 'set BLOCK ID VALUE'";
+        return RWGT_ECARD;
+      }
+      char* endp = nullptr;
+      const double v = std::strtod(val.c_str(), &endp);
+      char* endi = nullptr;
+      (void)std::strtol(id.c_str(), &endi, 10);
+      if (!endp || *endp != '\0' || !endi || *endi != '\0') {
+        g_create_error = where + "expected 'set BLOCK ID VALUE' with a numeric id and value";
+        return RWGT_ECARD;
+      }
+      const std::string key = upper(block) + " " + id;
+      for (size_t j = 0; j < npar; ++j)
+        if (def->layout[j] == key) cur[j] = v;
+    } else if (cmd == "CHANGE") {
+      std::string what, val;
+      ls >> what >> val;
+      if (fptype && upper(what) == "FPTYPE" && !val.empty()) {
+        fptype[0] = val[0];
+        fptype[1] = '\0';
+      }
+    } else {
+      g_create_error = where + "unknown command '" + cmd + "'";
+      return RWGT_ECARD;
+    }
+  }
+  flush();
+  *nsets = n;
+  return RWGT_OK;
+}
+
 int rwgt_process_info(const rwgt_ctx* ctx, int32_t* npart, int32_t* nhel_kept, int32_t* ncol, int32_t* ndiag) {
   if (!ctx) return RWGT_EINVAL;
   int np = 0, ng = 0, nc = 0, nd = 0;
