@@ -101,6 +101,20 @@ int rwgt_eval(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const double *
 int rwgt_eval_factored(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const double *weights_in,
                        const double *param_sets, int32_t nsets, double *weights_out);
 
+/* Reweighting with the strong coupling per event.  The original |M|^2 of
+ * event i uses alphas_orig[i] (DEVICE, the alpha_s the event was generated
+ * with, e.g. the LHE AQCDUP; NULL: the original card's alpha_s run to
+ * scales[i]); card k uses its alpha_s (SMINPUTS 3, taken as alpha_s at
+ * 91.1876 GeV) run to scales[i] (DEVICE, GeV) at one loop with five flavours:
+ * a(mu) = a / (1 + a b0 ln(mu^2/91.1876^2)), b0 = 23/(12 pi).  Every diagram
+ * of the supported processes carries the same power p of g_s (p = 0, 1, 4 for
+ * e+ e- > mu+ mu-, u u~ > e+ e- g, g g > t t~ g g), so this is the full path
+ * times (a_k(mu_i)/a_k)^p (a_0/a_0(i))^p per event; alphas_orig[i] = 0 gives
+ * w' = 0.  Errors as rwgt_eval. */
+int rwgt_eval_alphas(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const double *weights_in,
+                     const double *alphas_orig, const double *scales, const double *param_sets, int32_t nsets,
+                     double *weights_out);
+
 /* |M|^2 itself for each card of param_sets: me2_out[k][i].  Same rules as rwgt_eval. */
 int rwgt_me2(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const double *param_sets, int32_t nsets,
              double *me2_out);
@@ -337,6 +351,8 @@ const char *rwgt_lhe_last_error(const rwgt_lhe *lhe);
 int rwgt_lhe_num_events(const rwgt_lhe *lhe, int64_t *n);
 /* Event i: particle count, process id, info = (XWGTUP, SCALUP, AQEDUP, AQCDUP). */
 int rwgt_lhe_event_info(const rwgt_lhe *lhe, int64_t i, int32_t *nup, int32_t *idprup, double *info);
+/* info [n][4] (HOST) = (XWGTUP, SCALUP, AQEDUP, AQCDUP) of events index[0..n). */
+int rwgt_lhe_info(const rwgt_lhe *lhe, const int64_t *index, int64_t n, double *info);
 /* Indices (file order) of the events of a process: *n_match gets the count,
  * index_out (HOST, capacity cap) the first min(cap, count).  Errors:
  * RWGT_EPROCESS (unknown particle name). */

@@ -28,6 +28,9 @@ SIGNATURES = {
     "rwgt_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rwgt_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                   ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_void_p]),
+    "rwgt_eval_alphas": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.c_int32, ctypes.c_void_p]),
     "rwgt_eval_factored": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                            ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_void_p]),
     "rwgt_me2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
@@ -109,6 +112,8 @@ SIGNATURES.update({
     "rwgt_lhe_num_events": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "rwgt_lhe_event_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+    "rwgt_lhe_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
+                                      ctypes.POINTER(ctypes.c_double)]),
     "rwgt_lhe_select": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     "rwgt_lhe_momenta": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
@@ -234,6 +239,25 @@ def rwgt_eval(ctx, momenta, weights_in, param_sets, weights_out):
     if weights_out.numel() != params.shape[0] * nevt or weights_in.numel() != nevt:
         raise ValueError("weights_in must be [nevt] and weights_out [nsets, nevt]")
     rc = load().rwgt_eval(ctx, _ptr(momenta), nevt, _ptr(weights_in), pptr, params.shape[0], _ptr(weights_out))
+    if rc != 0:
+        _raise(rc, ctx)
+
+
+def rwgt_eval_alphas(ctx, momenta, weights_in, alphas_orig, scales, param_sets, weights_out):
+    """As rwgt_eval with the strong coupling per event (alphas_orig may be None)."""
+    _check_device(momenta, "momenta")
+    _check_device(weights_in, "weights_in")
+    _check_device(scales, "scales")
+    _check_device(weights_out, "weights_out")
+    if alphas_orig is not None:
+        _check_device(alphas_orig, "alphas_orig")
+    nevt = momenta.shape[0] if momenta.dim() > 0 else 0
+    params, pptr = _host_params(param_sets)
+    if weights_out.numel() != params.shape[0] * nevt or weights_in.numel() != nevt or scales.numel() != nevt:
+        raise ValueError("weights_in and scales must be [nevt] and weights_out [nsets, nevt]")
+    rc = load().rwgt_eval_alphas(ctx, _ptr(momenta), nevt, _ptr(weights_in),
+                                 None if alphas_orig is None else _ptr(alphas_orig), _ptr(scales), pptr,
+                                 params.shape[0], _ptr(weights_out))
     if rc != 0:
         _raise(rc, ctx)
 
@@ -655,6 +679,16 @@ def rwgt_lhe_event_info(lhe, i):
     if rc != 0:
         _lraise(rc, lhe)
     return nup.value, idp.value, tuple(float(x) for x in info)
+
+
+def rwgt_lhe_info(lhe, index):
+    """[n, 4] host array of (XWGTUP, SCALUP, AQEDUP, AQCDUP)."""
+    index = np.ascontiguousarray(index, dtype=np.int64)
+    out = np.zeros((max(index.size, 1), 4))
+    rc = load().rwgt_lhe_info(lhe, _i64(index), index.size, _f64(out))
+    if rc != 0:
+        _lraise(rc, lhe)
+    return out[:index.size]
 
 
 def rwgt_lhe_select(lhe, process):

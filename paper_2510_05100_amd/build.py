@@ -50,7 +50,8 @@ def _compile(src, verbose, incremental=False):
     t0 = time.time()
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {src}:\n{res.stderr[-4000:]}")
+        errors = "\n".join(ln for ln in res.stderr.splitlines() if " error:" in ln or ln.startswith("error"))
+        raise RuntimeError(f"hipcc failed for {src}:\n{errors}\n{res.stderr[-2000:]}")
     if verbose:
         print(f"  {src}: {time.time() - t0:.1f}s", flush=True)
     return obj

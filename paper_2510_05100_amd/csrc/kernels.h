@@ -40,6 +40,10 @@ hipError_t launch_factored(bool ew, const double* soa, int64_t nevt, int ia, int
                            double wzp, const FactorCard* fc, int ncards, const double* w_in, double* w_out,
                            hipStream_t s);
 
+// w_out[k][i] *= (alpha_k(mu_i)/alpha_k)^p (alpha_0/alpha_0(i))^p (per-event strong coupling).
+hipError_t launch_alphas(double* w_out, int64_t nevt, int nsets, const double* alphas_orig, const double* scales,
+                         double as0, const double* as_cards, int p, double b0, double mref2, hipStream_t s);
+
 void process_constants(int proc, int* npart, int* ngood, int* ncol, int* ndiag);
 double process_flops(int proc);
 

@@ -163,6 +163,45 @@ hipError_t launch_factored(bool ew, const double* soa, int64_t nevt, int ia, int
   return hipGetLastError();
 }
 
+// Per-event strong coupling on top of the fixed-coupling weights: every
+// diagram of these processes carries the same power p of g_s, so |M|^2 under
+// alpha_s(event) is |M|^2 under the card's alpha_s times (alpha_s(event) /
+// alpha_s(card))^p.  The original uses the event's own alpha_s (or the
+// original card's run to the event scale); card k its alpha_s run to the
+// event scale at one loop: a(mu) = a / (1 + a b0 ln(mu^2 / m_ref^2)).
+__device__ __forceinline__ double run_alphas(double a, double mu, double b0, double mref2) {
+  return a / (1.0 + a * b0 * log(mu * mu / mref2));
+}
+
+__global__ __launch_bounds__(256) void alphas_kernel(double* __restrict__ w_out, int64_t nevt, int nsets,
+                                                     const double* __restrict__ alphas_orig,
+                                                     const double* __restrict__ scales, double as0,
+                                                     const double* __restrict__ as_cards, int p, double b0,
+                                                     double mref2) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nevt) return;
+  const double mu = scales[i];
+  const double a0 = alphas_orig ? alphas_orig[i] : run_alphas(as0, mu, b0, mref2);
+  const bool zero = a0 == 0.0;             // |M|^2 of the original is 0: w' = 0
+  const double r0 = zero ? 0.0 : as0 / a0;
+  for (int k = 0; k < nsets; ++k) {
+    const double ak = as_cards[k];
+    const double rk = ak != 0.0 ? run_alphas(ak, mu, b0, mref2) / ak : 1.0;
+    double f = 1.0, x = rk * r0;
+    for (int q = 0; q < p; ++q) f *= x;
+    double& w = w_out[int64_t(k) * nevt + i];
+    w = zero ? 0.0 : w * f;
+  }
+}
+
+hipError_t launch_alphas(double* w_out, int64_t nevt, int nsets, const double* alphas_orig, const double* scales,
+                         double as0, const double* as_cards, int p, double b0, double mref2, hipStream_t s) {
+  if (nevt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(alphas_kernel, dim3(unsigned((nevt + 255) / 256)), dim3(256), 0, s, w_out, nevt, nsets,
+                     alphas_orig, scales, as0, as_cards, p, b0, mref2);
+  return hipGetLastError();
+}
+
 hipError_t launch_ingest(int npart, const double* aos, double* soa, int64_t nevt, hipStream_t s) {
   const int64_t blocks = (nevt + kIngestEvents - 1) / kIngestEvents;
   switch (npart) {

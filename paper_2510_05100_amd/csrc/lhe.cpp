@@ -355,6 +355,19 @@ int rwgt_lhe_event_info(const rwgt_lhe* l, int64_t i, int32_t* nup, int32_t* idp
   return RWGT_OK;
 }
 
+int rwgt_lhe_info(const rwgt_lhe* l, const int64_t* index, int64_t n, double* info) {
+  if (!l || n < 0 || (n > 0 && (!index || !info))) return RWGT_EINVAL;
+  for (int64_t r = 0; r < n; ++r) {
+    if (index[r] < 0 || index[r] >= int64_t(l->events.size())) return RWGT_EINVAL;
+    const Event& ev = l->events[size_t(index[r])];
+    info[4 * r] = ev.xwgt;
+    info[4 * r + 1] = ev.scale;
+    info[4 * r + 2] = ev.aqed;
+    info[4 * r + 3] = ev.aqcd;
+  }
+  return RWGT_OK;
+}
+
 int rwgt_lhe_select(rwgt_lhe* l, const char* process, int64_t* index_out, int64_t cap, int64_t* n_match) {
   if (!l || !n_match || cap < 0 || (cap > 0 && !index_out)) return RWGT_EINVAL;
   l->err.clear();

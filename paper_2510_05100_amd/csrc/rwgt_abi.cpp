@@ -174,6 +174,9 @@ struct rwgt_ctx {
   int64_t fac_probe_cap = 0;
   rwgt::FactorCard* fac_cards = nullptr;
   int fac_cards_cap = 0;
+  // per-event strong coupling: alpha_s of each card
+  double* as_cards = nullptr;
+  int as_cards_cap = 0;
   std::string err;
 
   int fail(int code, const std::string& msg) {
@@ -194,7 +197,7 @@ struct rwgt_ctx {
     if (hcards) hipHostFree(hcards);
     for (void* p : {sur_x, static_cast<void*>(sur_list), static_cast<void*>(sur_count), static_cast<void*>(sur_heads),
                     static_cast<void*>(sur_cards), static_cast<void*>(sur_cpar), static_cast<void*>(fac_probe),
-                    static_cast<void*>(fac_cards)})
+                    static_cast<void*>(fac_cards), static_cast<void*>(as_cards)})
       if (p) hipFree(p);
   }
 };
@@ -359,6 +362,44 @@ int rwgt_eval(rwgt_ctx* ctx, const double* momenta, int64_t nevt, const double* 
   } catch (const std::exception& ex) {
     return ctx->fail(RWGT_ENOMEM, ex.what());
   }
+}
+
+// Reweighting with the strong coupling per event (one-loop running from
+// alpha_s(91.1876 GeV) with five flavours for the new cards; the event's own
+// alpha_s, or the original card's run to the event scale, for the original).
+int rwgt_eval_alphas(rwgt_ctx* c, const double* momenta, int64_t nevt, const double* w_in, const double* alphas_orig,
+                     const double* scales, const double* param_sets, int32_t nsets, double* w_out) {
+  if (!c) return RWGT_EINVAL;
+  c->err.clear();
+  if (nevt > 0 && !scales) return c->fail(RWGT_EINVAL, "scales is NULL");
+  int rc = run(c, true, momenta, nevt, w_in, param_sets, nsets, w_out, nullptr);
+  if (rc != RWGT_OK || nevt == 0) return rc;
+  const int id = c->def->id;
+  const int p = id == rwgt::kProcEeMumu ? 0 : id == rwgt::kProcUuEeg ? 1 : 4;   // power of alpha_s in |M|^2
+  if (p == 0) return RWGT_OK;
+  const auto& layout = c->def->layout;
+  int ja = -1;
+  for (size_t j = 0; j < layout.size(); ++j)
+    if (layout[j] == "SMINPUTS 3") ja = int(j);
+  std::vector<double> as(static_cast<size_t>(nsets));
+  for (int k = 0; k < nsets; ++k) as[size_t(k)] = param_sets[size_t(k) * layout.size() + size_t(ja)];
+  hipError_t e = hipSuccess;
+  if (nsets > c->as_cards_cap) {
+    if (c->as_cards) { (void)hipStreamSynchronize(c->stream); (void)hipFree(c->as_cards); c->as_cards = nullptr; }
+    c->as_cards_cap = 0;
+    e = hipMalloc(&c->as_cards, size_t(nsets) * sizeof(double));
+    if (e != hipSuccess) return c->hip_fail(e, "hipMalloc(alpha_s per card)");
+    c->as_cards_cap = nsets;
+  }
+  // pageable source: wait for the copy
+  e = hipMemcpyAsync(c->as_cards, as.data(), as.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "alpha_s upload");
+  const double pi = 3.14159265358979323846;
+  const double b0 = (33.0 - 2.0 * 5.0) / (12.0 * pi), mref = 91.1876;
+  e = rwgt::launch_alphas(w_out, nevt, nsets, alphas_orig, scales, c->card.at("SMINPUTS 3"), c->as_cards, p, b0,
+                          mref * mref, c->stream);
+  return e == hipSuccess ? RWGT_OK : c->hip_fail(e, "per-event alpha_s");
 }
 
 // Coupling-factored reweighting (same result as rwgt_eval).  Electroweak

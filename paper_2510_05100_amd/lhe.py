@@ -19,13 +19,17 @@ PROCESSES = ("e+ e- > mu+ mu-", "u u~ > e+ e- g", "g g > t t~ g g")
 FPTYPE = {"d": _abi.RWGT_FP64, "f": _abi.RWGT_MIXED_FP16, "m": _abi.RWGT_MIXED_FP16}
 
 
-def reweight_lhe(in_path, out_path, param_card, rwgt_card, precision=None, factored=False, log=None):
+def reweight_lhe(in_path, out_path, param_card, rwgt_card, precision=None, factored=False, running_alphas=False,
+                 log=None):
     """Reweight every supported process in in_path; write out_path.
 
     param_card: SLHA text of the original card; rwgt_card: reweighting-card
     text ("launch rwgt_name=..." / "set BLOCK ID VALUE").  precision: an
     RWGT_* constant, else the card's "change fptype" (d: FP64; f or m: mixed),
-    else FP64.  factored: use the coupling-factored path.  Returns a summary
+    else FP64.  factored: use the coupling-factored path.  running_alphas:
+    the strong coupling per event (the event's AQCDUP for the original card,
+    each card's alpha_s run to the event's SCALUP; rwgt_eval_alphas).
+    Returns a summary
     (events per process, weight names, seconds per stage)."""
     import torch
     t0 = time.perf_counter()
@@ -52,7 +56,13 @@ def reweight_lhe(in_path, out_path, param_card, rwgt_card, precision=None, facto
                 p_dev = torch.as_tensor(mom).cuda()
                 w_dev = torch.as_tensor(w).cuda()
                 out = torch.empty((sets.shape[0], idx.size), dtype=torch.float64, device="cuda")
-                (_abi.rwgt_eval_factored if factored else _abi.rwgt_eval)(ctx, p_dev, w_dev, sets, out)
+                if running_alphas:
+                    info = _abi.rwgt_lhe_info(lhe, idx)
+                    aqcd = torch.as_tensor(np.ascontiguousarray(info[:, 3])).cuda()
+                    scale = torch.as_tensor(np.ascontiguousarray(info[:, 1])).cuda()
+                    _abi.rwgt_eval_alphas(ctx, p_dev, w_dev, aqcd, scale, sets, out)
+                else:
+                    (_abi.rwgt_eval_factored if factored else _abi.rwgt_eval)(ctx, p_dev, w_dev, sets, out)
                 wn = out.cpu().numpy()
             finally:
                 _abi.rwgt_destroy(ctx)

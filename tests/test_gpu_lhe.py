@@ -60,3 +60,25 @@ def test_reweight_lhe_against_oracle(tmp_path, factored):
         assert err.max() < tol
     others = [e for e in out if all(olhe.match(e, pr) is None for pr in KEYS)]
     assert len(others) == 15 and all(e["weights"]["mz"] == 0.0 == e["weights"]["sw"] for e in others)
+
+
+def test_reweight_lhe_running_alphas(tmp_path):
+    """Per-event strong coupling from the file: the event's AQCDUP for the
+    original card and each card's alpha_s run to the event's SCALUP."""
+    print("[case] lhe run running alpha_s", flush=True)
+    from gpu_util import torch_cuda
+    torch_cuda()
+    from oracle import running
+    from paper_2510_05100_amd import lhe
+    text, _ = slhe.lhe_text(n_per_process=(10, 20, 12, 3), seed=4300)
+    src, dst = tmp_path / "in.lhe", tmp_path / "out.lhe"
+    src.write_text(text)
+    lhe.reweight_lhe(src, dst, ORIG.slha(), CARD, running_alphas=True)
+    out = olhe.read(dst.read_text())
+    proc = "g g > t t~ g g"
+    rows = [e for e in out if olhe.match(e, proc) is not None]
+    for e in rows:
+        xw, scale, _, aqcd = e["info"]
+        want = xw * (running.alphas(0.130, scale) / aqcd) ** 4
+        assert abs(e["weights"]["as"] / want - 1) < 1e-12
+        assert abs(e["weights"]["mz"] / (xw * (running.alphas(0.118, scale) / aqcd) ** 4) - 1) < 1e-12

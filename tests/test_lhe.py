@@ -71,6 +71,8 @@ def test_library_reader_sort_and_momenta(sample):
         for i in (0, 1, len(ev) // 2, len(ev) - 1):
             nup, idp, info = rw.rwgt_lhe_event_info(lhe, i)
             assert (nup, idp, info) == (ev[i]["nup"], ev[i]["idprup"], ev[i]["info"])
+        allidx = np.arange(len(ev))
+        np.testing.assert_array_equal(rw.rwgt_lhe_info(lhe, allidx), np.array([e["info"] for e in ev]))
         for key, proc in PROC.items():
             idx = rw.rwgt_lhe_select(lhe, proc)
             want = [i for i, t in enumerate(truth) if t[0] == key]
