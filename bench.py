@@ -281,10 +281,15 @@ def main():
         line["factored"] = factored_leg(rw, torch, steps=5, warmup=2)
         log(f"factored: {line['factored']['factored_ms']:.2f} ms vs full {line['factored']['full_ms']:.2f} ms")
     if not a.no_surrogate:
+        # the workload's network (raw momenta + card, 4 x 256) and the
+        # physics-feature network (18 inputs, 3 x 128), same data and gate
         from paper_2510_05100_amd import surrogate
-        summary, sur = surrogate.run(torch, surrogate.Config(), log=log)
-        sur.close()
-        line["surrogate"] = summary
+        line["surrogate"] = {}
+        for name, cfg in (("raw_23_4x256", surrogate.Config(width=256, depth=4, features=rw.RWGT_FEAT_RAW)),
+                          ("physics_18_3x128", surrogate.Config())):
+            summary, sur = surrogate.run(torch, cfg, log=log)
+            sur.close()
+            line["surrogate"][name] = summary
     if a.copy_probe:
         src = torch.empty(64 << 20, dtype=torch.float64, device="cuda")
         dst = src.clone()
