@@ -22,7 +22,9 @@
 //              are listed for the exact path
 //   pack       weights in the per-lane order of the fused kernel's A operands
 //   infer      the fused inference pass: features, every layer, the heads and
-//              the gate for 32 rows per wave, activations kept in registers
+//              the gate for 32 rows per wave, activations kept in registers,
+//              weights read from L2 (staging them in LDS per compute unit
+//              measured slower: 0.45 against 0.39 ms per 1e6 rows)
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -47,8 +49,10 @@ __device__ __forceinline__ float silu_grad(float z) {
 //   [log s_hat, log(|s_ij| / s_hat) for i < j, M_Z, Gamma_Z, sin^2 theta_W,
 //    asinh Re chi, asinh Im chi, asinh Re chi0, asinh Im chi0]
 // where chi = s / (s - M^2 + i M Gamma) at s = s_ab of the resonant pair,
-// under the card (chi) and under the original card (chi0).  Computed in FP64
-// from the FP64 momenta, stored as FP32; unused slots are zero.
+// under the card (chi) and under the original card (chi0).  Invariants and
+// propagator ratios in FP64 from the FP64 momenta (they cancel near collinear
+// limits and the pole), their logarithms and asinh in FP32; unused slots are
+// zero.
 template <int NPART, int KIND>
 __device__ __forceinline__ void feature_row(const FeatureMap& fm, const double (&p)[NPART * 4], const float (&card)[3],
                                             float (&f)[kMlpMaxIn]) {
@@ -65,7 +69,7 @@ __device__ __forceinline__ void feature_row(const FeatureMap& fm, const double (
                     p[4 * i + 3] * p[4 * j + 3]);
     };
     const double shat = dot2(0, 1);
-    f[0] = float(log(shat));
+    f[0] = logf(float(shat));
     double s_res = 0.0;
     int k = 1;
 #pragma unroll
@@ -73,7 +77,7 @@ __device__ __forceinline__ void feature_row(const FeatureMap& fm, const double (
 #pragma unroll
       for (int j = i + 1; j < NPART; ++j) {
         const double sij = dot2(i, j);
-        f[k++] = float(log(fmax(fabs(sij) / shat, 1e-300)));
+        f[k++] = logf(fmaxf(float(fabs(sij) / shat), 1e-37f));
         if ((i == fm.res_a && j == fm.res_b) || (i == fm.res_b && j == fm.res_a)) s_res = sij;
       }
 #pragma unroll
@@ -81,8 +85,8 @@ __device__ __forceinline__ void feature_row(const FeatureMap& fm, const double (
     auto chi = [&](double m, double w, float& re, float& im) {
       const double x = s_res - m * m, y = m * w;
       const double d = x * x + y * y;
-      re = float(asinh(s_res * x / d));
-      im = float(asinh(-s_res * y / d));
+      re = asinhf(float(s_res * x / d));
+      im = asinhf(float(-s_res * y / d));
     };
     chi(double(card[0]), double(card[1]), f[k], f[k + 1]);
     chi(fm.mz0, fm.wz0, f[k + 2], f[k + 3]);
@@ -417,22 +421,28 @@ __device__ __forceinline__ f32x16_t mfma_bf16(bf16x8_t a, bf16x8_t b, f32x16_t c
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-// Fused inference: one wave per 32 rows (lanes l and l + 32 share row l % 32
-// and hold complementary halves of its features).  Transposed products
-// H'^T = W H^T: A = packed weights, B = this wave's activations, so the
-// accumulators of output block b are chunks 2b and 2b+1 of the next B operand.
-// The first layer runs on the high and low BF16 parts of its FP32 weights and
-// inputs (three products: hi.hi + hi.lo + lo.hi); the hidden layers on BF16
-// weights and activations as in training; the head in FP32 on the VALU.
+// Fused inference for the 32 rows e0 .. e0+31 of one wave.  Lanes l and
+// l + 32 share row l % 32 and hold complementary halves of its features.
+// Transposed products H'^T = W H^T: A = packed weights, B = this wave's
+// activations, so the accumulators of output block b are chunks 2b and 2b+1
+// of the next B operand.  The first layer runs on the high and low BF16 parts
+// of its FP32 weights and inputs (three products: hi.hi + hi.lo + lo.hi); the
+// hidden layers on BF16 weights and activations as in training; the head in
+// FP32 on the VALU.
+struct InferWeights {
+  const bf16x8_t *w0h, *w0l;
+  const float* b0;
+  const bf16x8_t* wh;
+  const float* bh;
+  const float* whead;   // rows 0 and 1, width floats each
+};
+
 template <int W, int NPART, int KIND>
-__global__ __launch_bounds__(256) void infer_k(const InferArgs a) {
+__device__ __forceinline__ void infer_rows(const InferArgs& a, const InferWeights& q, int64_t e0) {
   constexpr int NB = W / 32, NC = W / 16;
   const int lane = threadIdx.x & 63, h = lane >> 5;
-  const int64_t e0 = ((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6) * 32;
-  if (e0 >= a.n) return;                              // whole waves only
   const int64_t r = e0 + (lane & 31);
-  const bool valid = r < a.n;
-  const int64_t rr = valid ? r : a.n - 1;
+  const int64_t rr = r < a.n ? r : a.n - 1;
 
   float f[kMlpMaxIn];
   {
@@ -461,31 +471,26 @@ __global__ __launch_bounds__(256) void infer_k(const InferArgs a) {
     }
 
   bf16x8_t act[NC];
-  {
-    const bf16x8_t* w0h = static_cast<const bf16x8_t*>(a.w0hi);
-    const bf16x8_t* w0l = static_cast<const bf16x8_t*>(a.w0lo);
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      f32x16_t acc = {};
+  for (int b = 0; b < NB; ++b) {
+    f32x16_t acc = {};
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const bf16x8_t ah = w0h[(b * 2 + c) * 64 + lane];
-        const bf16x8_t al = w0l[(b * 2 + c) * 64 + lane];
-        acc = mfma_bf16(ah, xh[c], acc);
-        acc = mfma_bf16(ah, xl[c], acc);
-        acc = mfma_bf16(al, xh[c], acc);
-      }
+    for (int c = 0; c < 2; ++c) {
+      const bf16x8_t ah = q.w0h[(b * 2 + c) * 64 + lane];
+      const bf16x8_t al = q.w0l[(b * 2 + c) * 64 + lane];
+      acc = mfma_bf16(ah, xh[c], acc);
+      acc = mfma_bf16(ah, xl[c], acc);
+      acc = mfma_bf16(al, xh[c], acc);
+    }
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int fo = 32 * b + 8 * (i >> 2) + 4 * h + (i & 3);
-        act[2 * b + (i >> 3)][i & 7] = bf16(silu(acc[i] + a.b0[fo]));
-      }
+    for (int i = 0; i < 16; ++i) {
+      const int fo = 32 * b + 8 * (i >> 2) + 4 * h + (i & 3);
+      act[2 * b + (i >> 3)][i & 7] = bf16(silu(acc[i] + q.b0[fo]));
     }
   }
-  const bf16x8_t* wh = static_cast<const bf16x8_t*>(a.wh);
   for (int l = 0; l + 1 < a.nh; ++l) {
-    const bf16x8_t* wl = wh + size_t(l) * NB * NC * 64;
-    const float* bl = a.bh + size_t(l) * W;
+    const bf16x8_t* wl = q.wh + size_t(l) * NB * NC * 64;
+    const float* bl = q.bh + size_t(l) * W;
     bf16x8_t nxt[NC];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -504,8 +509,8 @@ __global__ __launch_bounds__(256) void infer_k(const InferArgs a) {
   // last hidden layer, straight into the two FP32 heads
   float mu = 0.0f, sg = 0.0f;
   {
-    const bf16x8_t* wl = wh + size_t(a.nh - 1) * NB * NC * 64;
-    const float* bl = a.bh + size_t(a.nh - 1) * W;
+    const bf16x8_t* wl = q.wh + size_t(a.nh - 1) * NB * NC * 64;
+    const float* bl = q.bh + size_t(a.nh - 1) * W;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       f32x16_t acc = {};
@@ -515,8 +520,8 @@ __global__ __launch_bounds__(256) void infer_k(const InferArgs a) {
       for (int i = 0; i < 16; ++i) {
         const int fo = 32 * b + 8 * (i >> 2) + 4 * h + (i & 3);
         const float v = silu(acc[i] + bl[fo]);
-        mu = fmaf(v, a.whead[fo], mu);
-        sg = fmaf(v, a.whead[W + fo], sg);
+        mu = fmaf(v, q.whead[fo], mu);
+        sg = fmaf(v, q.whead[W + fo], sg);
       }
     }
   }
@@ -525,7 +530,7 @@ __global__ __launch_bounds__(256) void infer_k(const InferArgs a) {
   mu = (mu + a.bhead[0]) * a.ys + a.ym;
   sg = sg + a.bhead[1] + logf(a.ys);
 
-  const bool mine = lane < 32 && valid;
+  const bool mine = lane < 32 && r < a.n;
   if (a.heads && mine) {
     a.heads[2 * r] = mu;
     a.heads[2 * r + 1] = sg;
@@ -546,6 +551,16 @@ __global__ __launch_bounds__(256) void infer_k(const InferArgs a) {
       if (fb) a.list[base + __popcll(m & ((uint64_t(1) << lane) - 1))] = int32_t(r);
     }
   }
+}
+
+// Weights from global memory (L2-resident): one wave per 32 rows.
+template <int W, int NPART, int KIND>
+__global__ __launch_bounds__(256) void infer_k(const InferArgs a) {
+  const int64_t e0 = ((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6) * 32;
+  if (e0 >= a.n) return;                              // whole waves only
+  const InferWeights q{static_cast<const bf16x8_t*>(a.w0hi), static_cast<const bf16x8_t*>(a.w0lo), a.b0,
+                       static_cast<const bf16x8_t*>(a.wh), a.bh, a.whead};
+  infer_rows<W, NPART, KIND>(a, q, e0);
 }
 
 // ----------------------------------------------------------------- launchers
@@ -697,7 +712,7 @@ hipError_t mlp_moments(const float* x, int64_t n, int ld, double* sums, bool cle
 
 template <int W>
 static hipError_t infer_launch(const InferArgs& a, hipStream_t s) {
-  const dim3 g(blocks_for(a.n, 128)), b(256);        // 4 waves x 32 rows per workgroup
+  const dim3 g(blocks_for(a.n, 4 * 32)), b(256);      // 4 waves x 32 rows per workgroup
   if (a.fm.npart == 4 && a.fm.kind == kFeatRaw)
     hipLaunchKernelGGL((infer_k<W, 4, kFeatRaw>), g, b, 0, s, a);
   else if (a.fm.npart == 4)

@@ -41,10 +41,10 @@ class Config:
     precision: int = _abi.RWGT_MLP_BF16
     features: int = _abi.RWGT_FEAT_PHYS
     batch: int = 4096
-    epochs: int = 20
+    epochs: int = 40
     lr: float = 2e-3
     lr_final: float = 2e-5
-    lam: float = 0.02
+    lam: float = 0.001
     seed: int = 1
     coverage: float = 0.999     # quantile of |r| / exp(s) taken as k
 
