@@ -169,6 +169,7 @@ struct rwgt_ctx {
   float* sur_cpar = nullptr;
   int64_t sur_cap = 0;
   int sur_card_cap = 0;
+  std::vector<double> sur_table;   // the param_table the device tables were built from
   // coupling-factored path: probe |M|^2 and per-card factors
   double* fac_probe = nullptr;
   int64_t fac_probe_cap = 0;
@@ -1024,6 +1025,12 @@ const char* rwgt_batch_last_error(const rwgt_batch* b) { return b ? b->err.c_str
 static int per_event_tables(rwgt_ctx* c, const rwgt_mlp* m, const double* param_table, int32_t ncards, int64_t rows,
                             bool need_x) {
   constexpr int kNparam = rwgt::kMlpCardParams;
+  // the same table as last time and room for the rows: nothing to rebuild
+  const size_t nval = size_t(ncards) * c->def->layout.size();
+  if (rows <= c->sur_cap && (!need_x || c->sur_x) && c->sur_cards && c->sur_table.size() == nval &&
+      std::memcmp(c->sur_table.data(), param_table, nval * sizeof(double)) == 0)
+    return RWGT_OK;
+  c->sur_table.clear();
   std::vector<CardPair> cards;
   int rc = build_cards(c, param_table, ncards, true, cards);
   if (rc != RWGT_OK) return rc;
@@ -1066,7 +1073,9 @@ static int per_event_tables(rwgt_ctx* c, const rwgt_mlp* m, const double* param_
   e = hipMemcpyAsync(c->sur_cards, cards.data(), cards.size() * sizeof(CardPair), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(c->sur_cpar, cpar.data(), cpar.size() * 4, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  return e == hipSuccess ? RWGT_OK : c->hip_fail(e, "per-event tables");
+  if (e != hipSuccess) return c->hip_fail(e, "per-event tables");
+  c->sur_table.assign(param_table, param_table + nval);
+  return RWGT_OK;
 }
 
 static int compute_units(int device) {
