@@ -119,6 +119,16 @@ int rwgt_eval_alphas(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const d
 int rwgt_me2(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const double *param_sets, int32_t nsets,
              double *me2_out);
 
+/* Number of non-finite entries (NaN or +-inf) in the output array of the
+ * last rwgt_eval, rwgt_me2, rwgt_eval_factored or rwgt_eval_alphas call on
+ * ctx (weights_out or me2_out, nsets * nevt entries); 0 when that call failed
+ * or had nevt = 0.  Non-finite momenta or weights give non-finite outputs
+ * (nothing is clamped), and a zero original |M|^2 gives w' = 0, which is
+ * finite (teaRex section, the normaliser's guard).  The count is taken on the
+ * device after the call's kernels, on the context's stream; this call waits
+ * for it.  Errors: RWGT_EINVAL (NULL), RWGT_EDEVICE. */
+int rwgt_nonfinite(rwgt_ctx *ctx, int64_t *count);
+
 /* Message of the last failed call on ctx (empty string if none). */
 const char *rwgt_last_error(const rwgt_ctx *ctx);
 

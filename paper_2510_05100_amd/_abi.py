@@ -35,6 +35,7 @@ SIGNATURES = {
                                            ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_void_p]),
     "rwgt_me2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                  ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_void_p]),
+    "rwgt_nonfinite": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "rwgt_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "rwgt_create_error": (ctypes.c_char_p, []),
     "rwgt_process_info": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int32)] * 4),
@@ -287,6 +288,15 @@ def rwgt_me2(ctx, momenta, param_sets, me2_out):
     rc = load().rwgt_me2(ctx, _ptr(momenta), nevt, pptr, params.shape[0], _ptr(me2_out))
     if rc != 0:
         _raise(rc, ctx)
+
+
+def rwgt_nonfinite(ctx):
+    """Non-finite outputs of the last evaluation on ctx (waits for it)."""
+    out = ctypes.c_int64()
+    rc = load().rwgt_nonfinite(ctx, ctypes.byref(out))
+    if rc != 0:
+        _raise(rc, ctx)
+    return out.value
 
 
 def rwgt_process_info(ctx):

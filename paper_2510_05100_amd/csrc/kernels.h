@@ -44,6 +44,13 @@ hipError_t launch_factored(bool ew, const double* soa, int64_t nevt, int ia, int
 hipError_t launch_alphas(double* w_out, int64_t nevt, int nsets, const double* alphas_orig, const double* scales,
                          double as0, const double* as_cards, int p, double b0, double mref2, hipStream_t s);
 
+// Non-finite entries (NaN, +-inf) of x[0..n): block b of the launch writes
+// its count to part[b]; the launch uses nonfinite_blocks(n) blocks (at most
+// kNonfiniteBlocks), so part needs that many entries.
+constexpr int kNonfiniteBlocks = 1024;
+int nonfinite_blocks(int64_t n);
+hipError_t launch_nonfinite(const double* x, int64_t n, unsigned long long* part, hipStream_t s);
+
 void process_constants(int proc, int* npart, int* ngood, int* ncol, int* ndiag);
 double process_flops(int proc);
 

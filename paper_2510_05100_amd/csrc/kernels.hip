@@ -202,6 +202,31 @@ hipError_t launch_alphas(double* w_out, int64_t nevt, int nsets, const double* a
   return hipGetLastError();
 }
 
+// Count of the non-finite outputs of a call: a grid-stride pass, each wave
+// sums its lanes' counts with shuffles, the block's four wave sums meet in
+// LDS and thread 0 writes the block total (no atomics, nothing to clear).
+__global__ __launch_bounds__(256) void nonfinite_kernel(const double* __restrict__ x, int64_t n,
+                                                        unsigned long long* __restrict__ part) {
+  __shared__ unsigned long long wsum[4];
+  unsigned long long c = 0;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) c += isfinite(x[i]) ? 0 : 1;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+int nonfinite_blocks(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return int(b < kNonfiniteBlocks ? (b < 1 ? 1 : b) : kNonfiniteBlocks);
+}
+
+hipError_t launch_nonfinite(const double* x, int64_t n, unsigned long long* part, hipStream_t s) {
+  hipLaunchKernelGGL(nonfinite_kernel, dim3(unsigned(nonfinite_blocks(n))), dim3(256), 0, s, x, n, part);
+  return hipGetLastError();
+}
+
 hipError_t launch_ingest(int npart, const double* aos, double* soa, int64_t nevt, hipStream_t s) {
   const int64_t blocks = (nevt + kIngestEvents - 1) / kIngestEvents;
   switch (npart) {

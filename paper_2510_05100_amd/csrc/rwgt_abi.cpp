@@ -178,6 +178,10 @@ struct rwgt_ctx {
   // per-event strong coupling: alpha_s of each card
   double* as_cards = nullptr;
   int as_cards_cap = 0;
+  // non-finite outputs of the last evaluation: per-block counts on the device
+  unsigned long long* nf_part = nullptr;
+  unsigned long long* nf_host = nullptr;   // pinned
+  int nf_blocks = 0;                       // blocks of the last count (0: nothing counted)
   std::string err;
 
   int fail(int code, const std::string& msg) {
@@ -198,8 +202,9 @@ struct rwgt_ctx {
     if (hcards) hipHostFree(hcards);
     for (void* p : {sur_x, static_cast<void*>(sur_list), static_cast<void*>(sur_count), static_cast<void*>(sur_heads),
                     static_cast<void*>(sur_cards), static_cast<void*>(sur_cpar), static_cast<void*>(fac_probe),
-                    static_cast<void*>(fac_cards), static_cast<void*>(as_cards)})
+                    static_cast<void*>(fac_cards), static_cast<void*>(as_cards), static_cast<void*>(nf_part)})
       if (p) hipFree(p);
+    if (nf_host) hipHostFree(nf_host);
   }
 };
 
@@ -295,6 +300,22 @@ int run(rwgt_ctx* c, bool reweight, const double* momenta, int64_t nevt, const d
   return RWGT_OK;
 }
 
+// Queue the count of non-finite entries of out[0..n) (the outputs of the call
+// that just enqueued its kernels); rwgt_nonfinite reads it back.
+int count_nonfinite(rwgt_ctx* c, const double* out, int64_t n) {
+  c->nf_blocks = 0;
+  if (n <= 0) return RWGT_OK;
+  hipError_t e = hipSuccess;
+  if (!c->nf_part) {
+    e = hipMalloc(&c->nf_part, rwgt::kNonfiniteBlocks * sizeof(unsigned long long));
+    if (e != hipSuccess) return c->hip_fail(e, "hipMalloc(non-finite counts)");
+  }
+  e = rwgt::launch_nonfinite(out, n, c->nf_part, c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "non-finite count kernel");
+  c->nf_blocks = rwgt::nonfinite_blocks(n);
+  return RWGT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -359,7 +380,9 @@ int rwgt_eval(rwgt_ctx* ctx, const double* momenta, int64_t nevt, const double* 
   if (!ctx) return RWGT_EINVAL;
   ctx->err.clear();
   try {
-    return run(ctx, true, momenta, nevt, weights_in, param_sets, nsets, weights_out, nullptr);
+    ctx->nf_blocks = 0;
+    const int rc = run(ctx, true, momenta, nevt, weights_in, param_sets, nsets, weights_out, nullptr);
+    return rc == RWGT_OK ? count_nonfinite(ctx, weights_out, int64_t(nsets) * nevt) : rc;
   } catch (const std::exception& ex) {
     return ctx->fail(RWGT_ENOMEM, ex.what());
   }
@@ -372,12 +395,13 @@ int rwgt_eval_alphas(rwgt_ctx* c, const double* momenta, int64_t nevt, const dou
                      const double* scales, const double* param_sets, int32_t nsets, double* w_out) {
   if (!c) return RWGT_EINVAL;
   c->err.clear();
+  c->nf_blocks = 0;
   if (nevt > 0 && !scales) return c->fail(RWGT_EINVAL, "scales is NULL");
   int rc = run(c, true, momenta, nevt, w_in, param_sets, nsets, w_out, nullptr);
   if (rc != RWGT_OK || nevt == 0) return rc;
   const int id = c->def->id;
   const int p = id == rwgt::kProcEeMumu ? 0 : id == rwgt::kProcUuEeg ? 1 : 4;   // power of alpha_s in |M|^2
-  if (p == 0) return RWGT_OK;
+  if (p == 0) return count_nonfinite(c, w_out, int64_t(nsets) * nevt);
   const auto& layout = c->def->layout;
   int ja = -1;
   for (size_t j = 0; j < layout.size(); ++j)
@@ -400,7 +424,8 @@ int rwgt_eval_alphas(rwgt_ctx* c, const double* momenta, int64_t nevt, const dou
   const double b0 = (33.0 - 2.0 * 5.0) / (12.0 * pi), mref = 91.1876;
   e = rwgt::launch_alphas(w_out, nevt, nsets, alphas_orig, scales, c->card.at("SMINPUTS 3"), c->as_cards, p, b0,
                           mref * mref, c->stream);
-  return e == hipSuccess ? RWGT_OK : c->hip_fail(e, "per-event alpha_s");
+  if (e != hipSuccess) return c->hip_fail(e, "per-event alpha_s");
+  return count_nonfinite(c, w_out, int64_t(nsets) * nevt);
 }
 
 // Coupling-factored reweighting (same result as rwgt_eval).  Electroweak
@@ -412,6 +437,7 @@ int rwgt_eval_factored(rwgt_ctx* c, const double* momenta, int64_t nevt, const d
                        const double* param_sets, int32_t nsets, double* w_out) {
   if (!c) return RWGT_EINVAL;
   c->err.clear();
+  c->nf_blocks = 0;
   if (nevt < 0) return c->fail(RWGT_EINVAL, "nevt < 0");
   if (nsets < 1) return c->fail(RWGT_EINVAL, "nsets < 1");
   if (!param_sets) return c->fail(RWGT_EINVAL, "param_sets is NULL");
@@ -501,7 +527,8 @@ int rwgt_eval_factored(rwgt_ctx* c, const double* momenta, int64_t nevt, const d
     if (e == hipSuccess)
       e = rwgt::launch_factored(ew, c->soa, nevt, ia, ib, c->fac_probe, o.mz, o.wz, c->fac_cards, int(fc.size()), w_in,
                                 w_out, c->stream);
-    return e == hipSuccess ? RWGT_OK : c->hip_fail(e, "factored evaluation");
+    if (e != hipSuccess) return c->hip_fail(e, "factored evaluation");
+    return count_nonfinite(c, w_out, int64_t(nsets) * nevt);
   } catch (const std::exception& ex) {
     return c->fail(RWGT_ENOMEM, ex.what());
   }
@@ -512,10 +539,31 @@ int rwgt_me2(rwgt_ctx* ctx, const double* momenta, int64_t nevt, const double* p
   if (!ctx) return RWGT_EINVAL;
   ctx->err.clear();
   try {
-    return run(ctx, false, momenta, nevt, nullptr, param_sets, nsets, nullptr, me2_out);
+    ctx->nf_blocks = 0;
+    const int rc = run(ctx, false, momenta, nevt, nullptr, param_sets, nsets, nullptr, me2_out);
+    return rc == RWGT_OK ? count_nonfinite(ctx, me2_out, int64_t(nsets) * nevt) : rc;
   } catch (const std::exception& ex) {
     return ctx->fail(RWGT_ENOMEM, ex.what());
   }
+}
+
+int rwgt_nonfinite(rwgt_ctx* c, int64_t* count) {
+  if (!c || !count) return RWGT_EINVAL;
+  *count = 0;
+  if (c->nf_blocks == 0) return RWGT_OK;
+  hipError_t e = hipSuccess;
+  if (!c->nf_host) {
+    e = hipHostMalloc(&c->nf_host, rwgt::kNonfiniteBlocks * sizeof(unsigned long long), hipHostMallocDefault);
+    if (e != hipSuccess) return c->hip_fail(e, "hipHostMalloc(non-finite counts)");
+  }
+  e = hipMemcpyAsync(c->nf_host, c->nf_part, size_t(c->nf_blocks) * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                     c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "non-finite count read-back");
+  unsigned long long s = 0;
+  for (int b = 0; b < c->nf_blocks; ++b) s += c->nf_host[b];
+  *count = int64_t(s);
+  return RWGT_OK;
 }
 
 const char* rwgt_last_error(const rwgt_ctx* ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }

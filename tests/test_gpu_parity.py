@@ -96,6 +96,51 @@ def test_eval_edge_cases():
             r.eval(dev(q), dev(np.ones(3)), [0.118, 172.5], out)
 
 
+def test_nonfinite_count():
+    """Non-finite inputs propagate to the outputs and are counted
+    (rwgt_nonfinite), for every evaluation entry point; a zero original |M|^2
+    gives w' = 0, which is finite.  The expected count follows from the inputs
+    alone: every output of an event with a NaN momentum or an infinite weight.
+    300,000 events x 1 card exceed 1024 x 256 entries, so the count kernel's
+    grid-stride loop is taken."""
+    _print_case("nonfinite")
+    torch = torch_cuda()
+    import paper_2510_05100_amd as rw
+    for key, proc, orig, new, n in (("ee_mumu", "e+ e- > mu+ mu-", synth.ORIG_EW, [synth.NEW_EE], 300000),
+                                    ("uu_eeg", "u u~ > e+ e- g", synth.ORIG_EW, [synth.NEW_UU, synth.NEW_EE], 70001)):
+        p = synth.events(key, n)
+        w = np.ones(n)
+        rng = np.random.default_rng(77)
+        bad_p = rng.choice(n, 13, replace=False)
+        bad_w = rng.choice(np.setdiff1d(np.arange(n), bad_p), 5, replace=False)
+        p[bad_p, 1, 2] = np.nan
+        w[bad_w] = np.inf
+        ok = np.setdiff1d(np.arange(n), np.concatenate([bad_p, bad_w]))
+        w[rng.choice(ok, 7, replace=False)] = 0.0   # finite: w' = 0
+        rows = np.stack([c.row(key) for c in new])
+        nsets = len(new)
+        want = (len(bad_p) + len(bad_w)) * nsets
+        with rw.Reweighter(proc, orig.slha()) as r:
+            pd, wd = dev(p), dev(w)
+            out = torch.empty((nsets, n), dtype=torch.float64, device="cuda")
+            r.eval(pd, wd, rows, out)
+            assert rw.rwgt_nonfinite(r.ctx) == want
+            assert int((~torch.isfinite(out)).sum()) == want
+            rw.rwgt_eval_factored(r.ctx, pd, wd, rows, out)
+            assert rw.rwgt_nonfinite(r.ctx) == want
+            scales = dev(np.full(n, 91.1876))
+            rw.rwgt_eval_alphas(r.ctx, pd, wd, None, scales, rows, out)
+            assert rw.rwgt_nonfinite(r.ctx) == want
+            me = torch.empty((nsets, n), dtype=torch.float64, device="cuda")
+            rw.rwgt_me2(r.ctx, pd, rows, me)
+            assert rw.rwgt_nonfinite(r.ctx) == len(bad_p) * nsets      # |M|^2 does not see the weights
+            with pytest.raises(rw.RwgtError, match="EINVAL"):
+                r.eval(pd, wd, np.zeros((0, rows.shape[1])), out[:0])
+            assert rw.rwgt_nonfinite(r.ctx) == 0
+            r.eval(pd[:0], wd[:0], rows, out[:, :0])
+            assert rw.rwgt_nonfinite(r.ctx) == 0
+
+
 def test_context_reuse_grow_shrink():
     _print_case("reuse")
     torch = torch_cuda()
