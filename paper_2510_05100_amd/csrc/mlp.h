@@ -56,8 +56,11 @@ struct InferArgs {
   float* heads = nullptr;              // [n][2] (nullable)
 };
 
+// C = A B^T with optional bias and SiLU (act) into FP32 Cf and / or Ct of
+// type tout.  work (work_elems floats, may be NULL): space for the partial
+// tiles of long-K products, which then run in K chunks on more waves.
 hipError_t mlp_gemm(int tin, int tout, const void* A, const void* B, int M, int N, int K, const float* bias,
-                    float* Cf, void* Ct, int act, hipStream_t s);
+                    float* Cf, void* Ct, int act, float* work, int64_t work_elems, hipStream_t s);
 hipError_t mlp_transpose(int tin, int tout, const void* in, void* out, int R, int C, hipStream_t s);
 hipError_t mlp_silu_bwd(int tout, const float* dh, const float* z, float* g, void* gt, int64_t n, hipStream_t s);
 hipError_t mlp_colsum(const float* g, float* db, int R, int C, hipStream_t s);

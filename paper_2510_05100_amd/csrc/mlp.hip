@@ -27,6 +27,7 @@
 //              measured slower: 0.45 against 0.39 ms per 1e6 rows)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "mlp.h"
@@ -106,22 +107,21 @@ __device__ __forceinline__ void load_event(const double* __restrict__ mom, int64
 }
 
 // ------------------------------------------------------------------ GEMMs
+// Epilogue of a 32 x 32 tile held in the standard accumulator layout (lane
+// l, element i: row 8 (i/4) + 4 (l/32) + i%4, column l%32): the raw sums to
+// this K chunk's slice of part, or bias, activation and the outputs.
 template <class TO>
-__global__ __launch_bounds__(64) void gemm_nt_bf16(const bf16* __restrict__ A, const bf16* __restrict__ B, int M,
-                                                   int N, int K, const float* __restrict__ bias,
-                                                   float* __restrict__ Cf, TO* __restrict__ Ct, int act) {
-  const int ntn = N / 32;
-  const int tm = blockIdx.x / ntn, tn = blockIdx.x % ntn;
+__device__ __forceinline__ void tile_out(const f32x16_t& acc, int tm, int tn, int M, int N,
+                                         const float* __restrict__ bias, float* __restrict__ Cf,
+                                         TO* __restrict__ Ct, int act, float* __restrict__ part) {
   const int l = threadIdx.x;
-  const bf16* a_row = A + size_t(tm * 32 + (l & 31)) * K + 8 * (l >> 5);
-  const bf16* b_row = B + size_t(tn * 32 + (l & 31)) * K + 8 * (l >> 5);
-  f32x16_t acc = {};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(a_row + k0);
-    const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(b_row + k0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-  }
   const int col = tn * 32 + (l & 31);
+  if (part) {
+    float* p = part + size_t(blockIdx.y) * M * N;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) p[size_t(tm * 32 + 8 * (i >> 2) + 4 * (l >> 5) + (i & 3)) * N + col] = acc[i];
+    return;
+  }
   const float bb = bias ? bias[col] : 0.0f;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
@@ -132,20 +132,47 @@ __global__ __launch_bounds__(64) void gemm_nt_bf16(const bf16* __restrict__ A, c
   }
 }
 
+// C = A B^T (A [M][K], B [N][K], K contiguous): one wave per 32 x 32 tile
+// (blockIdx.x) and K chunk [kchunk y, kchunk (y+1)) (blockIdx.y).  With more
+// than one chunk the partial tiles go to part [chunks][M][N] and ksum_k adds
+// them in chunk order (deterministic): long-K products (weight gradients,
+// K = batch rows) then fill the chip instead of a few waves.
+template <class TO>
+__global__ __launch_bounds__(64) void gemm_nt_bf16(const bf16* __restrict__ A, const bf16* __restrict__ B, int M,
+                                                   int N, int K, int kchunk, const float* __restrict__ bias,
+                                                   float* __restrict__ Cf, TO* __restrict__ Ct, int act,
+                                                   float* __restrict__ part) {
+  const int ntn = N / 32;
+  const int tm = blockIdx.x / ntn, tn = blockIdx.x % ntn;
+  const int l = threadIdx.x;
+  const bf16* a_row = A + size_t(tm * 32 + (l & 31)) * K + 8 * (l >> 5);
+  const bf16* b_row = B + size_t(tn * 32 + (l & 31)) * K + 8 * (l >> 5);
+  const int kb = int(blockIdx.y) * kchunk, ke = min(K, kb + kchunk);
+  f32x16_t acc = {};
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(a_row + k0);
+    const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(b_row + k0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+  }
+  tile_out<TO>(acc, tm, tn, M, N, bias, Cf, Ct, act, part);
+}
+
 // FP32 operands through the matrix cores as high and low BF16 parts: three
 // products hi.hi + hi.lo + lo.hi per step (relative error about 2^-16), the
 // same arithmetic as the fused kernel's first layer.
 template <class TO>
 __global__ __launch_bounds__(64) void gemm_nt_split(const float* __restrict__ A, const float* __restrict__ B, int M,
-                                                    int N, int K, const float* __restrict__ bias,
-                                                    float* __restrict__ Cf, TO* __restrict__ Ct, int act) {
+                                                    int N, int K, int kchunk, const float* __restrict__ bias,
+                                                    float* __restrict__ Cf, TO* __restrict__ Ct, int act,
+                                                    float* __restrict__ part) {
   const int ntn = N / 32;
   const int tm = blockIdx.x / ntn, tn = blockIdx.x % ntn;
   const int l = threadIdx.x;
   const float* a_row = A + size_t(tm * 32 + (l & 31)) * K + 8 * (l >> 5);
   const float* b_row = B + size_t(tn * 32 + (l & 31)) * K + 8 * (l >> 5);
+  const int kb = int(blockIdx.y) * kchunk, ke = min(K, kb + kchunk);
   f32x16_t acc = {};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  for (int k0 = kb; k0 < ke; k0 += 16) {
     bf16x8_t ah, al, bh, bl;
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
@@ -159,15 +186,51 @@ __global__ __launch_bounds__(64) void gemm_nt_split(const float* __restrict__ A,
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
   }
-  const int col = tn * 32 + (l & 31);
-  const float bb = bias ? bias[col] : 0.0f;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int row = tm * 32 + 8 * (i >> 2) + 4 * (l >> 5) + (i & 3);
-    const float v = acc[i] + bb;
-    if (Cf) Cf[size_t(row) * N + col] = v;
-    if (Ct) Ct[size_t(row) * N + col] = TO(act ? silu(v) : v);
+  tile_out<TO>(acc, tm, tn, M, N, bias, Cf, Ct, act, part);
+}
+
+// FP32 C = A B^T on the matrix cores (v_mfma_f32_32x32x2_f32: FP32 products,
+// FP32 accumulation), tiles and K chunks as gemm_nt_bf16.  Lane l reads 4
+// consecutive K values of row l%32 of each operand, half-wave h = l/32 the
+// four after half 0's; product step j pairs element j of both halves, so
+// step j covers K = {k0 + j, k0 + 4 + j}: the same indices on A and B, every
+// index of the 8-wide block once.
+template <class TO>
+__global__ __launch_bounds__(64) void gemm_nt_f32m(const float* __restrict__ A, const float* __restrict__ B, int M,
+                                                   int N, int K, int kchunk, const float* __restrict__ bias,
+                                                   float* __restrict__ Cf, TO* __restrict__ Ct, int act,
+                                                   float* __restrict__ part) {
+  const int ntn = N / 32;
+  const int tm = blockIdx.x / ntn, tn = blockIdx.x % ntn;
+  const int l = threadIdx.x;
+  const float* a_row = A + size_t(tm * 32 + (l & 31)) * K + 4 * (l >> 5);
+  const float* b_row = B + size_t(tn * 32 + (l & 31)) * K + 4 * (l >> 5);
+  const int kb = int(blockIdx.y) * kchunk, ke = min(K, kb + kchunk);
+  f32x16_t acc = {};
+  for (int k0 = kb; k0 < ke; k0 += 8) {
+    const float4 a = *reinterpret_cast<const float4*>(a_row + k0);
+    const float4 b = *reinterpret_cast<const float4*>(b_row + k0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, acc, 0, 0, 0);
   }
+  tile_out<TO>(acc, tm, tn, M, N, bias, Cf, Ct, act, part);
+}
+
+// C[i] = sum over chunks c (in order) of part[c][i], then bias / activation.
+template <class TO>
+__global__ __launch_bounds__(256) void ksum_k(const float* __restrict__ part, int chunks, int M, int N,
+                                              const float* __restrict__ bias, float* __restrict__ Cf,
+                                              TO* __restrict__ Ct, int act) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t mn = int64_t(M) * N;
+  if (i >= mn) return;
+  float v = 0.0f;
+  for (int c = 0; c < chunks; ++c) v += part[c * mn + i];
+  v += bias ? bias[i % N] : 0.0f;
+  if (Cf) Cf[i] = v;
+  if (Ct) Ct[i] = TO(act ? silu(v) : v);
 }
 
 template <class TO>
@@ -566,28 +629,58 @@ __global__ __launch_bounds__(256) void infer_k(const InferArgs a) {
 // ----------------------------------------------------------------- launchers
 static unsigned blocks_for(int64_t n, int b = 256) { return unsigned((n + b - 1) / b); }
 
+// K chunks of one product: one unless K is long (weight gradients, K = batch
+// rows) and a workspace of chunks x M x N floats is given; then enough
+// chunks of at least 128 K values each (a multiple of kstep) to bring the
+// waves near 1024, at most 32.
+static int k_chunk(int tiles, int M, int N, int K, int kstep, int64_t work_elems, int* chunks) {
+  int c = 1;
+  if (work_elems > 0 && K >= 1024) {
+    c = std::min(32, std::min(K / 128, std::max(1, 1024 / tiles)));
+    while (c > 1 && int64_t(c) * M * N > work_elems) c /= 2;
+  }
+  int kc = (K + c - 1) / c;
+  kc = (kc + kstep - 1) / kstep * kstep;
+  *chunks = (K + kc - 1) / kc;
+  return kc;
+}
+
 template <class TO>
 static void gemm_launch(int tin, const void* A, const void* B, int M, int N, int K, const float* bias, float* Cf,
-                        void* Ct, int act, hipStream_t s) {
-  if (tin == kMlpSplit)
-    hipLaunchKernelGGL(gemm_nt_split<TO>, dim3((M / 32) * (N / 32)), dim3(64), 0, s, static_cast<const float*>(A),
-                       static_cast<const float*>(B), M, N, K, bias, Cf, static_cast<TO*>(Ct), act);
-  else if (tin == kMlpBF16)
-    hipLaunchKernelGGL(gemm_nt_bf16<TO>, dim3((M / 32) * (N / 32)), dim3(64), 0, s, static_cast<const bf16*>(A),
-                       static_cast<const bf16*>(B), M, N, K, bias, Cf, static_cast<TO*>(Ct), act);
-  else
+                        void* Ct, int act, float* work, int64_t work_elems, hipStream_t s) {
+  const bool mfma = M % 32 == 0 && N % 32 == 0 && K % (tin == kMlpFP32 ? 8 : 16) == 0;
+  if (!mfma) {                      // FP32 of any shape (BF16 shapes are checked by the caller)
     hipLaunchKernelGGL(gemm_nt_f32<TO>, dim3(blocks_for(int64_t(M) * N)), dim3(256), 0, s,
                        static_cast<const float*>(A), static_cast<const float*>(B), M, N, K, bias, Cf,
+                       static_cast<TO*>(Ct), act);
+    return;
+  }
+  const int tiles = (M / 32) * (N / 32);
+  int chunks = 1;
+  const int kc = k_chunk(tiles, M, N, K, tin == kMlpFP32 ? 8 : 16, work_elems, &chunks);
+  float* part = chunks > 1 ? work : nullptr;
+  const dim3 grid{unsigned(tiles), unsigned(chunks), 1u};
+  if (tin == kMlpSplit)
+    hipLaunchKernelGGL(gemm_nt_split<TO>, grid, dim3(64), 0, s, static_cast<const float*>(A),
+                       static_cast<const float*>(B), M, N, K, kc, bias, Cf, static_cast<TO*>(Ct), act, part);
+  else if (tin == kMlpBF16)
+    hipLaunchKernelGGL(gemm_nt_bf16<TO>, grid, dim3(64), 0, s, static_cast<const bf16*>(A),
+                       static_cast<const bf16*>(B), M, N, K, kc, bias, Cf, static_cast<TO*>(Ct), act, part);
+  else
+    hipLaunchKernelGGL(gemm_nt_f32m<TO>, grid, dim3(64), 0, s, static_cast<const float*>(A),
+                       static_cast<const float*>(B), M, N, K, kc, bias, Cf, static_cast<TO*>(Ct), act, part);
+  if (part)
+    hipLaunchKernelGGL(ksum_k<TO>, dim3(blocks_for(int64_t(M) * N)), dim3(256), 0, s, part, chunks, M, N, bias, Cf,
                        static_cast<TO*>(Ct), act);
 }
 
 hipError_t mlp_gemm(int tin, int tout, const void* A, const void* B, int M, int N, int K, const float* bias,
-                    float* Cf, void* Ct, int act, hipStream_t s) {
+                    float* Cf, void* Ct, int act, float* work, int64_t work_elems, hipStream_t s) {
   if (tin != kMlpFP32 && (M % 32 || N % 32 || K % 16)) return hipErrorInvalidValue;
   if (tout == kMlpBF16)
-    gemm_launch<bf16>(tin, A, B, M, N, K, bias, Cf, Ct, act, s);
+    gemm_launch<bf16>(tin, A, B, M, N, K, bias, Cf, Ct, act, work, work_elems, s);
   else
-    gemm_launch<float>(tin, A, B, M, N, K, bias, Cf, Ct, act, s);
+    gemm_launch<float>(tin, A, B, M, N, K, bias, Cf, Ct, act, work, work_elems, s);
   return hipGetLastError();
 }
 

@@ -59,6 +59,14 @@ int rwgt_mlp::ensure_batch(int64_t rows) {
     if (e == hipSuccess) e = alloc(n * es, &gtt[l]);
     if (e == hipSuccess && l > 0) e = alloc(size_t(rows) * ly.in * 4, reinterpret_cast<void**>(&dh[l]));
   }
+  // partial tiles of the chunked weight-gradient products: 32 chunks of the
+  // largest layer
+  int64_t most = 0;
+  for (const Layer& ly : layers) most = std::max(most, int64_t(ly.out) * ly.in);
+  kpart = nullptr;
+  kpart_elems = 0;
+  if (e == hipSuccess) e = alloc(size_t(32 * most) * 4, reinterpret_cast<void**>(&kpart));
+  if (e == hipSuccess) kpart_elems = 32 * most;
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(mlp workspace)");
   bcap = rows;
   return RWGT_OK;
@@ -85,7 +93,8 @@ int rwgt_mlp::forward(const void* x, int64_t rows) {
     const bool last = l == L - 1;
     const Layer& ly = layers[l];
     e = rwgt::mlp_gemm(ly.split ? rwgt::kMlpSplit : ly.mode, last ? ly.mode : layers[l + 1].mode, input(l), ly.wc,
-                       int(rows), ly.out, ly.in, ly.b, z[l], last ? nullptr : h[l + 1], last ? 0 : 1, stream);
+                       int(rows), ly.out, ly.in, ly.b, z[l], last ? nullptr : h[l + 1], last ? 0 : 1, nullptr, 0,
+                       stream);
   }
   if (e != hipSuccess) return hip_fail(e, "mlp forward");
   return RWGT_OK;
@@ -103,12 +112,14 @@ int rwgt_mlp::backward(const float* y, int64_t n_valid, int64_t rows) {
     e = rwgt::mlp_transpose(kMlpFP32, ly.mode, g[l], gtt[l], int(rows), ly.out, stream);
     if (e == hipSuccess) e = rwgt::mlp_transpose(ly.mode, ly.mode, input(l), ht[l], int(rows), ly.in, stream);
     if (e == hipSuccess)
-      e = rwgt::mlp_gemm(ly.mode, ly.mode, gtt[l], ht[l], ly.out, ly.in, int(rows), nullptr, ly.gw, nullptr, 0, stream);
+      e = rwgt::mlp_gemm(ly.mode, ly.mode, gtt[l], ht[l], ly.out, ly.in, int(rows), nullptr, ly.gw, nullptr, 0, kpart,
+                         kpart_elems, stream);
     if (e == hipSuccess) e = rwgt::mlp_colsum(g[l], ly.gb, int(rows), ly.out, stream);
     if (l == 0 || e != hipSuccess) continue;
     // dH = G W: operands G [rows][out], W^T [in][out]; then through SiLU into
     // the previous layer's gradient (FP32 and its operand type)
-    e = rwgt::mlp_gemm(ly.mode, ly.mode, gt[l], ly.wct, int(rows), ly.in, ly.out, nullptr, dh[l], nullptr, 0, stream);
+    e = rwgt::mlp_gemm(ly.mode, ly.mode, gt[l], ly.wct, int(rows), ly.in, ly.out, nullptr, dh[l], nullptr, 0, nullptr, 0,
+                       stream);
     if (e == hipSuccess)
       e = rwgt::mlp_silu_bwd(layers[l - 1].mode, dh[l], z[l - 1], g[l - 1], gt[l - 1], rows * layers[l - 1].out,
                              stream);

@@ -38,6 +38,8 @@ struct rwgt_mlp {
   const void* x_in = nullptr;                             // the current batch's input rows (FP32)
   std::vector<void*> h, ht, gt, gtt;
   std::vector<float*> z, g, dh;
+  float* kpart = nullptr;                                 // K-chunk partial tiles of the weight gradients
+  int64_t kpart_elems = 0;
   std::vector<void*> work, params;
   std::string err;
 

@@ -41,7 +41,7 @@ class Config:
     precision: int = _abi.RWGT_MLP_BF16
     features: int = _abi.RWGT_FEAT_PHYS
     batch: int = 4096
-    epochs: int = 40
+    epochs: int = 250
     lr: float = 2e-3
     lr_final: float = 2e-5
     lam: float = 0.001
