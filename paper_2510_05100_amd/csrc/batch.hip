@@ -72,38 +72,81 @@ static hipError_t launch_batch_t(const BatchSeg* segs, int nseg, int64_t ntiles,
   return hipGetLastError();
 }
 
-// Exact reweighting of the events listed by the surrogate gate: lane i takes
-// list[i] < *count (grid-stride, the count stays on the device), card
-// cards[1 + card_index[e]] against the original cards[0].  Without a list
-// every event 0..n_all-1 is taken.
-template <class R, class... PROCS>
-__global__ __launch_bounds__(256) void exact_list_kernel(int proc, const double* __restrict__ mom,
-                                                         const int32_t* __restrict__ list,
-                                                         const unsigned int* __restrict__ count, int64_t n_all,
-                                                         const int32_t* __restrict__ card_index,
-                                                         const CardPair* __restrict__ cards,
-                                                         const double* __restrict__ w_in, double* __restrict__ w_out) {
-  const int64_t n = list ? int64_t(*count) : n_all;
-  BatchSeg sg{};
-  sg.mom = mom;
-  sg.w_in = w_in;
-  sg.w_out = w_out;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+// Exact reweighting with a card per event (the surrogate's fallback list, or
+// every event), one lane per (event, card, kept helicity): the 2 NGOOD lanes
+// of an event are consecutive lanes of one wave; lane j evaluates |M_h|^2 of
+// helicity good(j % NGOOD) under the original card cards[0] (j < NGOOD) or
+// the event's card cards[1 + card_index[e]], and the group's first lane
+// gathers them and adds each card's values in helicity order, the order of
+// the one-lane-per-event kernels, so w' is the same to the bit.  One
+// helicity and one card per lane keeps the registers to a few waves per
+// SIMD, and a short fallback list still fills the chip.  Events
+// list[0 .. *count) (the count stays on the device, at most n_all), or
+// 0 .. n_all-1 without a list; grid-stride over events.
+template <class R, class PROC>
+__global__ __launch_bounds__(256) void exact_hel_kernel(const double* __restrict__ mom,
+                                                        const int32_t* __restrict__ list,
+                                                        const unsigned int* __restrict__ count, int64_t n_all,
+                                                        const int32_t* __restrict__ card_index,
+                                                        const CardPair* __restrict__ cards,
+                                                        const double* __restrict__ w_in, double* __restrict__ w_out) {
+  constexpr int G = PROC::NGOOD, G2 = 2 * PROC::NGOOD;
+  static_assert(64 % G2 == 0, "event groups tile a wave");
+  const int64_t n = list ? (int64_t(*count) < n_all ? int64_t(*count) : n_all) : n_all;
+  const int j = int(threadIdx.x) % G2;
+  const int lane0 = int(threadIdx.x & 63) - j;             // the group's first lane in the wave
+  const int64_t per_block = blockDim.x / G2;
+  for (int64_t i = int64_t(blockIdx.x) * per_block + threadIdx.x / G2; i < n; i += int64_t(gridDim.x) * per_block) {
     const int64_t e = list ? int64_t(list[i]) : i;
-    batch_dispatch<R, PROCS...>(proc, sg, e, cards[0], cards[1 + card_index[e]]);
+    double P[PROC::NPART][4];
+    const double* src = mom + e * (PROC::NPART * 4);
+#pragma unroll
+    for (int a = 0; a < PROC::NPART; ++a)
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) P[a][mu] = src[a * 4 + mu];
+    const CardPair& cp = cards[j < G ? 0 : 1 + card_index[e]];
+    cx<R> jamp[PROC::NCOL];
+    PROC::template jamps<R>(P, PROC::good(j % G), pick<R>(cp), jamp);
+    const double hm = double(PROC::template colour_sum<R>(jamp));
+    double m0 = 0.0, m1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      m0 += __shfl(hm, lane0 + k);
+      m1 += __shfl(hm, lane0 + G + k);
+    }
+    if (j == 0) {
+      m0 *= PROC::AVERAGE;
+      m1 *= PROC::AVERAGE;
+      w_out[e] = ((m0 == 0.0 ? 0.0 : 1.0 / m0) * w_in[e]) * m1;
+    }
   }
+}
+
+template <class R>
+static void launch_exact_hel(int proc, const double* mom, const int32_t* list, const unsigned int* count,
+                             int64_t n_all, const int32_t* card_index, const CardPair* cards, const double* w_in,
+                             double* w_out, int max_blocks, hipStream_t s) {
+  const int g = 2 * (proc == 0 ? Proc_ee_mumu::NGOOD : Proc_uu_eeg::NGOOD);   // lanes per event
+  const int64_t need = (n_all * g + 255) / 256;
+  const unsigned blocks = unsigned(need < max_blocks ? (need < 1 ? 1 : need) : max_blocks);
+  if (proc == 0)
+    hipLaunchKernelGGL((exact_hel_kernel<R, Proc_ee_mumu>), dim3(blocks), dim3(256), 0, s, mom, list, count, n_all,
+                       card_index, cards, w_in, w_out);
+  else
+    hipLaunchKernelGGL((exact_hel_kernel<R, Proc_uu_eeg>), dim3(blocks), dim3(256), 0, s, mom, list, count, n_all,
+                       card_index, cards, w_in, w_out);
 }
 
 hipError_t launch_exact_list(int family, int precision, int proc, const double* mom, const int32_t* list,
                              const unsigned int* count, int64_t n_all, const int32_t* card_index,
-                             const CardPair* cards, const double* w_in, double* w_out, int grid, hipStream_t s) {
-  if (family != kFamilyElectroweak) return hipErrorInvalidValue;
+                             const CardPair* cards, const double* w_in, double* w_out, int max_blocks,
+                             hipStream_t s) {
+  if (family != kFamilyElectroweak || (proc != 0 && proc != 1)) return hipErrorInvalidValue;
+  if (n_all <= 0) return hipSuccess;
   if (precision == kPrecFP64)
-    hipLaunchKernelGGL((exact_list_kernel<double, Proc_ee_mumu, Proc_uu_eeg>), dim3(grid), dim3(256), 0, s, proc, mom,
-                       list, count, n_all, card_index, cards, w_in, w_out);
+    launch_exact_hel<double>(proc, mom, list, count, n_all, card_index, cards, w_in, w_out, max_blocks, s);
   else
-    hipLaunchKernelGGL((exact_list_kernel<float, Proc_ee_mumu, Proc_uu_eeg>), dim3(grid), dim3(256), 0, s, proc, mom,
-                       list, count, n_all, card_index, cards, w_in, w_out);
+    launch_exact_hel<float>(proc, mom, list, count, n_all, card_index, cards, w_in, w_out, max_blocks, s);
   return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ struct InferArgs {
   int64_t n = 0;                       // rows
   FeatureMap fm;
   const float* mean = nullptr;         // [32] standardisation (padded: 0 / 1)
-  const float* stdv = nullptr;
+  const float* istd = nullptr;       // 1 / standard deviation per input
   const void* w0hi = nullptr;          // first layer, packed BF16 high and low parts
   const void* w0lo = nullptr;
   const float* b0 = nullptr;
@@ -71,7 +71,7 @@ hipError_t mlp_adam(int tout, float* w, const float* grad, float* m, float* v, v
                     float c2, hipStream_t s);
 hipError_t mlp_convert(int tout, const float* in, void* out, void* outt, int rows, int cols, hipStream_t s);
 hipError_t mlp_features(const FeatureMap& fm, const double* mom, const int32_t* ev, const int32_t* cidx,
-                        const float* cpar, const float* mean, const float* stdv, float* x, int64_t n, int64_t rows,
+                        const float* cpar, const float* mean, const float* istd, float* x, int64_t n, int64_t rows,
                         int ld, hipStream_t s);
 hipError_t mlp_heads(const float* z, int ld, int64_t n, float ym, float ys, float* out, int ld_out, hipStream_t s);
 hipError_t mlp_log_ratio(const double* w_new, const double* w_old, float* y, int64_t n, hipStream_t s);

@@ -38,10 +38,19 @@ typedef __bf16 bf16;
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU and its derivative with the hardware reciprocal (1 ulp) instead of a
+// correctly rounded division: the same function in training and inference.
+__device__ __forceinline__ float sigmoid(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) { return z * sigmoid(z); }
 __device__ __forceinline__ float silu_grad(float z) {
-  const float s = 1.0f / (1.0f + __expf(-z));
+  const float s = sigmoid(z);
   return s * (1.0f + z * (1.0f - s));
+}
+
+// asinh x = sign(x) log(|x| + sqrt(x^2 + 1)) with the hardware logarithm:
+// absolute error about 1e-7 for the |x| < 1e3 of the propagator features.
+__device__ __forceinline__ float fast_asinh(float x) {
+  return copysignf(__logf(fabsf(x) + sqrtf(fmaf(x, x, 1.0f))), x);
 }
 
 // ------------------------------------------------------------ feature maps
@@ -52,8 +61,8 @@ __device__ __forceinline__ float silu_grad(float z) {
 // where chi = s / (s - M^2 + i M Gamma) at s = s_ab of the resonant pair,
 // under the card (chi) and under the original card (chi0).  Invariants and
 // propagator ratios in FP64 from the FP64 momenta (they cancel near collinear
-// limits and the pole), their logarithms and asinh in FP32; unused slots are
-// zero.
+// limits and the pole), their logarithms and asinh in FP32 with the hardware
+// logarithm; unused slots are zero.
 template <int NPART, int KIND>
 __device__ __forceinline__ void feature_row(const FeatureMap& fm, const double (&p)[NPART * 4], const float (&card)[3],
                                             float (&f)[kMlpMaxIn]) {
@@ -70,7 +79,8 @@ __device__ __forceinline__ void feature_row(const FeatureMap& fm, const double (
                     p[4 * i + 3] * p[4 * j + 3]);
     };
     const double shat = dot2(0, 1);
-    f[0] = logf(float(shat));
+    const double ishat = 1.0 / shat;
+    f[0] = __logf(float(shat));
     double s_res = 0.0;
     int k = 1;
 #pragma unroll
@@ -78,26 +88,28 @@ __device__ __forceinline__ void feature_row(const FeatureMap& fm, const double (
 #pragma unroll
       for (int j = i + 1; j < NPART; ++j) {
         const double sij = dot2(i, j);
-        f[k++] = logf(fmaxf(float(fabs(sij) / shat), 1e-37f));
+        f[k++] = __logf(fmaxf(float(fabs(sij) * ishat), 1e-37f));
         if ((i == fm.res_a && j == fm.res_b) || (i == fm.res_b && j == fm.res_a)) s_res = sij;
       }
 #pragma unroll
     for (int j = 0; j < kMlpCardParams; ++j) f[k++] = card[j];
     auto chi = [&](double m, double w, float& re, float& im) {
       const double x = s_res - m * m, y = m * w;
-      const double d = x * x + y * y;
-      re = asinhf(float(s_res * x / d));
-      im = asinhf(float(-s_res * y / d));
+      const double t = s_res / (x * x + y * y);
+      re = fast_asinh(float(t * x));
+      im = fast_asinh(float(-t * y));
     };
     chi(double(card[0]), double(card[1]), f[k], f[k + 1]);
     chi(fm.mz0, fm.wz0, f[k + 2], f[k + 3]);
   }
 }
 
+// (f - mean) / std as a product with the reciprocals istd (computed once on
+// the host per normalisation).
 __device__ __forceinline__ void standardise(float (&f)[kMlpMaxIn], const float* __restrict__ mean,
-                                            const float* __restrict__ stdv) {
+                                            const float* __restrict__ istd) {
 #pragma unroll
-  for (int k = 0; k < kMlpMaxIn; ++k) f[k] = (f[k] - mean[k]) / stdv[k];
+  for (int k = 0; k < kMlpMaxIn; ++k) f[k] = (f[k] - mean[k]) * istd[k];
 }
 
 template <int NPART>
@@ -367,7 +379,7 @@ template <int NPART, int KIND>
 __global__ __launch_bounds__(256) void features_k(const FeatureMap fm, const double* __restrict__ mom,
                                                   const int32_t* __restrict__ ev, const int32_t* __restrict__ cidx,
                                                   const float* __restrict__ cpar, const float* __restrict__ mean,
-                                                  const float* __restrict__ stdv, float* __restrict__ x, int64_t n,
+                                                  const float* __restrict__ istd, float* __restrict__ x, int64_t n,
                                                   int64_t rows, int ld) {
   const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= rows) return;
@@ -379,7 +391,7 @@ __global__ __launch_bounds__(256) void features_k(const FeatureMap fm, const dou
     load_event<NPART>(mom, e, p);
     const float card[3] = {cpar[3 * c], cpar[3 * c + 1], cpar[3 * c + 2]};
     feature_row<NPART, KIND>(fm, p, card, f);
-    standardise(f, mean, stdv);
+    standardise(f, mean, istd);
   } else {
 #pragma unroll
     for (int k = 0; k < kMlpMaxIn; ++k) f[k] = 0.0f;
@@ -515,7 +527,7 @@ __device__ __forceinline__ void infer_rows(const InferArgs& a, const InferWeight
     load_event<NPART>(a.mom, e, p);
     const float card[3] = {a.cpar[3 * c], a.cpar[3 * c + 1], a.cpar[3 * c + 2]};
     feature_row<NPART, KIND>(a.fm, p, card, f);
-    standardise(f, a.mean, a.stdv);
+    standardise(f, a.mean, a.istd);
   }
   // this lane's half of the inputs (a bitwise blend, so that the choice does
   // not become a lane-dependent index into f)
@@ -536,7 +548,9 @@ __device__ __forceinline__ void infer_rows(const InferArgs& a, const InferWeight
   bf16x8_t act[NC];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    f32x16_t acc = {};
+    f32x16_t acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = q.b0[32 * b + 8 * (i >> 2) + 4 * h + (i & 3)];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const bf16x8_t ah = q.w0h[(b * 2 + c) * 64 + lane];
@@ -546,10 +560,7 @@ __device__ __forceinline__ void infer_rows(const InferArgs& a, const InferWeight
       acc = mfma_bf16(al, xh[c], acc);
     }
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int fo = 32 * b + 8 * (i >> 2) + 4 * h + (i & 3);
-      act[2 * b + (i >> 3)][i & 7] = bf16(silu(acc[i] + q.b0[fo]));
-    }
+    for (int i = 0; i < 16; ++i) act[2 * b + (i >> 3)][i & 7] = bf16(silu(acc[i]));
   }
   for (int l = 0; l + 1 < a.nh; ++l) {
     const bf16x8_t* wl = q.wh + size_t(l) * NB * NC * 64;
@@ -557,14 +568,13 @@ __device__ __forceinline__ void infer_rows(const InferArgs& a, const InferWeight
     bf16x8_t nxt[NC];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      f32x16_t acc = {};
+      f32x16_t acc;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[i] = bl[32 * b + 8 * (i >> 2) + 4 * h + (i & 3)];
 #pragma unroll
       for (int c = 0; c < NC; ++c) acc = mfma_bf16(wl[(b * NC + c) * 64 + lane], act[c], acc);
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int fo = 32 * b + 8 * (i >> 2) + 4 * h + (i & 3);
-        nxt[2 * b + (i >> 3)][i & 7] = bf16(silu(acc[i] + bl[fo]));
-      }
+      for (int i = 0; i < 16; ++i) nxt[2 * b + (i >> 3)][i & 7] = bf16(silu(acc[i]));
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c) act[c] = nxt[c];
@@ -576,13 +586,15 @@ __device__ __forceinline__ void infer_rows(const InferArgs& a, const InferWeight
     const float* bl = q.bh + size_t(a.nh - 1) * W;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      f32x16_t acc = {};
+      f32x16_t acc;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[i] = bl[32 * b + 8 * (i >> 2) + 4 * h + (i & 3)];
 #pragma unroll
       for (int c = 0; c < NC; ++c) acc = mfma_bf16(wl[(b * NC + c) * 64 + lane], act[c], acc);
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         const int fo = 32 * b + 8 * (i >> 2) + 4 * h + (i & 3);
-        const float v = silu(acc[i] + bl[fo]);
+        const float v = silu(acc[i]);
         mu = fmaf(v, q.whead[fo], mu);
         sg = fmaf(v, q.whead[W + fo], sg);
       }
@@ -606,21 +618,55 @@ __device__ __forceinline__ void infer_rows(const InferArgs& a, const InferWeight
       else
         fb = true;
     }
-    const uint64_t m = __ballot(fb);
-    if (m) {                                          // wave-uniform
-      unsigned int base = 0;
-      if (lane == 0) base = atomicAdd(a.count, unsigned(__popcll(m)));
-      base = __shfl(base, 0);
-      if (fb) a.list[base + __popcll(m & ((uint64_t(1) << lane) - 1))] = int32_t(r);
+    if constexpr (W == 256) {
+      // width 256 (one wave per SIMD): one atomic per wave with a fallback
+      // row (the block-count form below measured 1.09 against 0.86 ms per 1e6
+      // rows for this kernel's code generation)
+      const uint64_t m = __ballot(fb);
+      if (m) {                                        // wave-uniform
+        unsigned int base = 0;
+        if (lane == 0) base = atomicAdd(a.count, unsigned(__popcll(m)));
+        base = __shfl(base, 0);
+        if (fb) a.list[base + __popcll(m & ((uint64_t(1) << lane) - 1))] = int32_t(r);
+      }
+    } else {
+      // fallback rows join the device list: the workgroup's waves count theirs
+      // in LDS and one lane reserves the block's slots with a single atomic
+      // (one atomic per wave contends on the counter when most waves have a
+      // fallback row: 0.49 against 0.32 ms for the gated path at 8.6%)
+      __shared__ unsigned int s_cnt[4];
+      __shared__ unsigned int s_base;
+      const uint64_t m = __ballot(fb);
+      const int wid = int(threadIdx.x >> 6), nw = int(blockDim.x >> 6);
+      if (lane == 0) s_cnt[wid] = unsigned(__popcll(m));
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        unsigned int tot = 0;
+        for (int w = 0; w < nw; ++w) tot += s_cnt[w];
+        s_base = tot ? atomicAdd(a.count, tot) : 0u;
+      }
+      __syncthreads();
+      if (fb) {
+        unsigned int off = s_base;
+        for (int w = 0; w < wid; ++w) off += s_cnt[w];
+        a.list[off + __popcll(m & ((uint64_t(1) << lane) - 1))] = int32_t(r);
+      }
     }
   }
 }
 
-// Weights from global memory (L2-resident): one wave per 32 rows.
+// Weights from global memory (L2-resident): one wave per 32 rows, 4 waves per
+// workgroup.  Width 128 is held to 128 registers (4 waves per SIMD, no
+// spills): the kernel is bound by its vector instructions, and the extra
+// waves hide the weight loads (0.207 against 0.242 ms per 1e6 rows at 3
+// waves).  Width 128: waves past the last row run on the clamped last row
+// and write nothing (every wave reaches the gate's barriers).
 template <int W, int NPART, int KIND>
-__global__ __launch_bounds__(256) void infer_k(const InferArgs a) {
+__global__ __launch_bounds__(256, W == 128 ? 4 : 1) void infer_k(const InferArgs a) {
   const int64_t e0 = ((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6) * 32;
-  if (e0 >= a.n) return;                              // whole waves only
+  if constexpr (W == 256) {
+    if (e0 >= a.n) return;                            // whole waves; this width's gate has no barrier
+  }
   const InferWeights q{static_cast<const bf16x8_t*>(a.w0hi), static_cast<const bf16x8_t*>(a.w0lo), a.b0,
                        static_cast<const bf16x8_t*>(a.wh), a.bh, a.whead};
   infer_rows<W, NPART, KIND>(a, q, e0);
@@ -751,17 +797,17 @@ hipError_t mlp_convert(int tout, const float* in, void* out, void* outt, int row
 }
 
 hipError_t mlp_features(const FeatureMap& fm, const double* mom, const int32_t* ev, const int32_t* cidx,
-                        const float* cpar, const float* mean, const float* stdv, float* x, int64_t n, int64_t rows,
+                        const float* cpar, const float* mean, const float* istd, float* x, int64_t n, int64_t rows,
                         int ld, hipStream_t s) {
   const dim3 g(blocks_for(rows)), b(256);
   if (fm.npart == 4 && fm.kind == kFeatRaw)
-    hipLaunchKernelGGL((features_k<4, kFeatRaw>), g, b, 0, s, fm, mom, ev, cidx, cpar, mean, stdv, x, n, rows, ld);
+    hipLaunchKernelGGL((features_k<4, kFeatRaw>), g, b, 0, s, fm, mom, ev, cidx, cpar, mean, istd, x, n, rows, ld);
   else if (fm.npart == 4)
-    hipLaunchKernelGGL((features_k<4, kFeatPhys>), g, b, 0, s, fm, mom, ev, cidx, cpar, mean, stdv, x, n, rows, ld);
+    hipLaunchKernelGGL((features_k<4, kFeatPhys>), g, b, 0, s, fm, mom, ev, cidx, cpar, mean, istd, x, n, rows, ld);
   else if (fm.npart == 5 && fm.kind == kFeatRaw)
-    hipLaunchKernelGGL((features_k<5, kFeatRaw>), g, b, 0, s, fm, mom, ev, cidx, cpar, mean, stdv, x, n, rows, ld);
+    hipLaunchKernelGGL((features_k<5, kFeatRaw>), g, b, 0, s, fm, mom, ev, cidx, cpar, mean, istd, x, n, rows, ld);
   else if (fm.npart == 5)
-    hipLaunchKernelGGL((features_k<5, kFeatPhys>), g, b, 0, s, fm, mom, ev, cidx, cpar, mean, stdv, x, n, rows, ld);
+    hipLaunchKernelGGL((features_k<5, kFeatPhys>), g, b, 0, s, fm, mom, ev, cidx, cpar, mean, istd, x, n, rows, ld);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -181,7 +181,7 @@ int rwgt_mlp::infer(const double* mom, const int32_t* ev, const int32_t* cidx, c
   a.n = n;
   a.fm = fm;
   a.mean = mean;
-  a.stdv = stdv;
+  a.istd = istd;
   a.w0hi = p0hi;
   a.w0lo = p0lo;
   a.b0 = layers[0].b;
@@ -271,9 +271,11 @@ int rwgt_mlp_create(int32_t n_in, int32_t width, int32_t depth, int32_t n_out, i
   std::vector<float> ones(rwgt::kMlpMaxIn, 1.0f), zeros(rwgt::kMlpMaxIn, 0.0f);
   dalloc(reinterpret_cast<void**>(&m->mean), ones.size() * 4);
   dalloc(reinterpret_cast<void**>(&m->stdv), ones.size() * 4);
+  dalloc(reinterpret_cast<void**>(&m->istd), ones.size() * 4);
   dalloc(reinterpret_cast<void**>(&m->loss), 4);
   if (e == hipSuccess) e = hipMemcpy(m->mean, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(m->stdv, ones.data(), ones.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->istd, ones.data(), ones.size() * 4, hipMemcpyHostToDevice);
   // packed weights of the fused inference kernel (BF16 networks of width 128
   // or 256 with 1..kMlpMaxHidden hidden width x width layers)
   const int nh = depth - 1;
@@ -346,8 +348,11 @@ int rwgt_mlp_set_normalisation(rwgt_mlp* m, const float* mean, const float* stdv
   for (int k = 0; k < m->n_in; ++k)
     if (!(stdv[k] > 0.0f) || !std::isfinite(stdv[k]) || !std::isfinite(mean[k]))
       return m->fail(RWGT_EINVAL, "standard deviations must be positive and finite");
+  std::vector<float> inv(size_t(m->n_in));
+  for (int k = 0; k < m->n_in; ++k) inv[size_t(k)] = 1.0f / stdv[k];
   hipError_t e = hipMemcpy(m->mean, mean, m->n_in * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(m->stdv, stdv, m->n_in * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->istd, inv.data(), m->n_in * 4, hipMemcpyHostToDevice);
   return e == hipSuccess ? RWGT_OK : m->hip_fail(e, "normalisation");
 }
 
@@ -423,7 +428,7 @@ int rwgt_mlp_features(rwgt_mlp* m, const double* momenta, int32_t npart, const i
   int rc = resolve_map(m, npart);
   if (rc != RWGT_OK) return rc;
   const int64_t rows = pad64(n);
-  hipError_t e = rwgt::mlp_features(m->fm, momenta, event_index, card_index, card_params, m->mean, m->stdv,
+  hipError_t e = rwgt::mlp_features(m->fm, momenta, event_index, card_index, card_params, m->mean, m->istd,
                                     static_cast<float*>(x_out), n, rows, m->layers[0].in, m->stream);
   return e == hipSuccess ? RWGT_OK : m->hip_fail(e, "features");
 }
@@ -474,12 +479,13 @@ int rwgt_mlp_fit_normalisation(rwgt_mlp* m, const double* momenta, int32_t npart
   const std::vector<float> zeros(rwgt::kMlpMaxIn, 0.0f), ones(rwgt::kMlpMaxIn, 1.0f);
   hipError_t e = hipMemcpy(m->mean, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(m->stdv, ones.data(), ones.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->istd, ones.data(), ones.size() * 4, hipMemcpyHostToDevice);
   if (e != hipSuccess) return m->hip_fail(e, "normalisation");
   const int ld = m->layers[0].in;
   auto fill = [&](int64_t a, int64_t b, float* x) {
     const double* mom = event_index ? momenta : momenta + a * npart * 4;
     return rwgt::mlp_features(m->fm, mom, event_index ? event_index + a : nullptr, card_index + a, card_params,
-                              m->mean, m->stdv, x, b - a, b - a, ld, m->stream);
+                              m->mean, m->istd, x, b - a, b - a, ld, m->stream);
   };
   std::vector<float> mean, stdv;
   rc = column_stats(m, n, ld, m->n_in, fill, mean, stdv);

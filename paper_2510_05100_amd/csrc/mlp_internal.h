@@ -24,7 +24,7 @@ struct rwgt_mlp {
   int n_in = 0, n_out = 0, width = 0;
   std::vector<Layer> layers;
   rwgt::FeatureMap fm;
-  float *mean = nullptr, *stdv = nullptr, *loss = nullptr;
+  float *mean = nullptr, *stdv = nullptr, *istd = nullptr, *loss = nullptr;   // istd = 1 / stdv
   float lambda = 0.1f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f, k_cal = 3.3f;
   float ym = 0.0f, ys = 1.0f;                             // target standardisation
   long long t = 0;

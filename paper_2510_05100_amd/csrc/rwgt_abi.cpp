@@ -1147,7 +1147,7 @@ int rwgt_eval_cards(rwgt_ctx* c, const double* momenta, int64_t nevt, const doub
     hipError_t e = rwgt::launch_exact_list(rwgt::kFamilyElectroweak,
                                            c->precision == RWGT_FP64 ? rwgt::kPrecFP64 : rwgt::kPrecMixedFP16, proc,
                                            momenta, nullptr, nullptr, nevt, card_index, c->sur_cards, w_in, w_out,
-                                           4 * compute_units(c->device), c->stream);
+                                           16 * compute_units(c->device), c->stream);
     return e == hipSuccess ? RWGT_OK : c->hip_fail(e, "card-per-event evaluation");
   } catch (const std::exception& ex) {
     return c->fail(RWGT_ENOMEM, ex.what());
@@ -1191,8 +1191,8 @@ int rwgt_sur_eval(rwgt_ctx* c, rwgt_mlp* m, const double* momenta, int64_t nevt,
     if (e == hipSuccess)
       e = rwgt::launch_exact_list(rwgt::kFamilyElectroweak,
                                   c->precision == RWGT_FP64 ? rwgt::kPrecFP64 : rwgt::kPrecMixedFP16, proc, momenta,
-                                  c->sur_list, c->sur_count, 0, card_index, c->sur_cards, w_in, w_out,
-                                  4 * compute_units(c->device), st);
+                                  c->sur_list, c->sur_count, nevt, card_index, c->sur_cards, w_in, w_out,
+                                  16 * compute_units(c->device), st);
     if (e != hipSuccess) return c->hip_fail(e, "surrogate gate / exact fallback");
     if (n_fallback) {
       unsigned int cnt = 0;
