@@ -53,12 +53,16 @@ def _inputs(rows, n, seed):
     return x, y
 
 
+@pytest.mark.parametrize("n", [200, 3000])
 @pytest.mark.parametrize("mode,tol", [(1, 1e-5), (0, 2e-2)])
-def test_gradients_and_heads_vs_reference(mode, tol):
-    print(f"[case] mlp gradients mode={mode}", flush=True)
+def test_gradients_and_heads_vs_reference(mode, tol, n):
+    """n = 3000 (3008 padded rows): the weight gradients, whose K is the row
+    count, run in K chunks (16 or 23, the last one shorter) summed by a
+    second kernel; n = 200 in one chunk."""
+    print(f"[case] mlp gradients mode={mode} n={n}", flush=True)
     torch = torch_cuda()
     import paper_2510_05100_amd as rw
-    n, lam, scale = 200, 0.3, (0.05, 0.4)
+    lam, scale = 0.3, (0.05, 0.4)
     flat = _params(11)
     m = rw.rwgt_mlp_create(N_IN, WIDTH, DEPTH, 2, mode, 1)
     try:
@@ -67,7 +71,7 @@ def test_gradients_and_heads_vs_reference(mode, tol):
         rw.rwgt_mlp_set_target_scale(m, *scale)
         rw.rwgt_mlp_set_params(m, flat)
         np.testing.assert_array_equal(rw.rwgt_mlp_get_params(m), flat)
-        x, y = _inputs(256, n, 5)
+        x, y = _inputs((n + 63) // 64 * 64, n, 5)
         xd, yd = torch.as_tensor(x).cuda(), torch.as_tensor(y).cuda()
         heads = torch.zeros((n, 32), dtype=torch.float32, device="cuda")
         rw.rwgt_mlp_forward(m, xd, n, heads)
