@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-factored", action="store_true")
+    ap.add_argument("--surrogate-epochs", type=int, default=None,
+                    help="training epochs of the surrogate networks (default: the Config default); fewer only "
+                         "to keep a kernel trace short")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 512 MiB device copy (scale reference for HBM byte counters)")
     return ap.parse_args()
@@ -287,6 +290,8 @@ def main():
         line["surrogate"] = {}
         for name, cfg in (("raw_23_4x256", surrogate.Config(width=256, depth=4, features=rw.RWGT_FEAT_RAW)),
                           ("physics_18_3x128", surrogate.Config())):
+            if a.surrogate_epochs:
+                cfg.epochs = a.surrogate_epochs
             summary, sur = surrogate.run(torch, cfg, log=log)
             sur.close()
             line["surrogate"][name] = summary
