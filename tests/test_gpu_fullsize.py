@@ -1,0 +1,180 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times: 1e6 g g -> t t~ g g events (FP64 and mixed), 1e6 u u~ -> e+ e- g
+events, and the 64-card batched mix at its full segment counts (128
+segments, 4.04e6 events).  Every output is checked against a property that
+holds at any size; sampled outputs against the oracle one by one.
+
+- g g -> t t~ g g with alpha_s 0.118 -> 0.130: every diagram carries g_s^4,
+  so w'/w = (0.130/0.118)^4 on every event: FP64 to 1e-12 (as at small
+  sizes), mixed to 2e-5 (the mixed path's bound; it measures 6.9e-6).
+  |M|^2 under the original card on 40 evenly spaced events against the
+  oracle's Berends-Giele recursion: 1e-10 (the small-size tolerance).
+- u u~ -> e+ e- g with the M_Z, Gamma_Z, sin^2 theta_W card: w' finite and
+  positive on every event; 500 evenly spaced events against the oracle's
+  reweighting: 1e-11.
+- Batched mix: every segment equals its plain rwgt_eval call bit for bit,
+  and 2 events of every segment (first and last) against the oracle: 1e-11.
+- Surrogate path on the 1e6 held-out events: the gate's decisions and both
+  kinds of output (exact fallback, network prediction) on every event.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import reweight
+
+from gpu_util import PROCESS_TEXT, dev, rel_err, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+RATIO = (0.130 / 0.118) ** 4
+N_FULL = 1_000_000
+
+
+def _case(name, **kw):
+    print(f"[case] fullsize {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+@pytest.fixture(scope="module")
+def gg_events():
+    return synth.events("gg_ttgg", N_FULL)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 2e-5)])
+def test_gg_ttgg_full_size(gg_events, precision, tol):
+    _case("gg_ttgg", precision=precision, n=N_FULL)
+    torch = torch_cuda()
+    import paper_2510_05100_amd as rw
+    p = gg_events
+    pd = dev(p)
+    w = torch.ones(N_FULL, dtype=torch.float64, device="cuda")
+    with rw.Reweighter(PROCESS_TEXT["gg_ttgg"], synth.ORIG_QCD.slha(), precision) as r:
+        out = torch.empty((1, N_FULL), dtype=torch.float64, device="cuda")
+        r.eval(pd, w, synth.NEW_QCD.row("gg_ttgg"), out)
+        assert rw.rwgt_nonfinite(r.ctx) == 0
+        ratio = out.cpu().numpy()[0]
+        err = np.abs(ratio / RATIO - 1.0)
+        print(f"gg_ttgg precision {precision}: max |w'/w / (0.130/0.118)^4 - 1| = {err.max():.3g}", flush=True)
+        assert err.max() < tol
+        if precision == 0:
+            me = torch.empty((1, N_FULL), dtype=torch.float64, device="cuda")
+            r.me2(pd, synth.ORIG_QCD.row("gg_ttgg"), me)
+            idx = np.linspace(0, N_FULL - 1, 40).astype(np.int64)
+            got = me.cpu().numpy()[0][idx]
+            want = reweight.me2("gg_ttgg", p[idx], synth.ORIG_QCD)
+            assert rel_err(got, want).max() < 1e-10
+
+
+def test_uu_eeg_full_size():
+    _case("uu_eeg", n=N_FULL)
+    torch = torch_cuda()
+    import paper_2510_05100_amd as rw
+    p = synth.events("uu_eeg", N_FULL)
+    w = np.ones(N_FULL)
+    with rw.Reweighter(PROCESS_TEXT["uu_eeg"], synth.ORIG_EW.slha()) as r:
+        out = torch.empty((1, N_FULL), dtype=torch.float64, device="cuda")
+        r.eval(dev(p), dev(w), synth.NEW_UU.row("uu_eeg"), out)
+        got = out.cpu().numpy()[0]
+    assert np.all(np.isfinite(got)) and np.all(got > 0)
+    idx = np.linspace(0, N_FULL - 1, 500).astype(np.int64)
+    want, _, _ = reweight.reweight("uu_eeg", p[idx], w[idx], synth.ORIG_EW, [synth.NEW_UU])
+    assert rel_err(got[idx], want[0]).max() < 1e-11
+
+
+def test_batched_mix_full_counts():
+    torch = torch_cuda()
+    import paper_2510_05100_amd as rw
+    grid = synth.batch_grid()
+    counts = synth.batch_counts()
+    _case("batched", segments=2 * len(grid), events=int(counts.sum()))
+    procs = ("ee_mumu", "uu_eeg")
+    host = {q: synth.events(q, int(counts.max())) for q in procs}
+    pools = {q: dev(host[q]) for q in procs}
+    ones = torch.ones(int(counts.max()), dtype=torch.float64, device="cuda")
+    ctxs = [rw.rwgt_create(PROCESS_TEXT[q], synth.ORIG_EW.slha(), 0) for q in procs]
+    b = None
+    try:
+        items, plain = [], []
+        for c, card in enumerate(grid):
+            for j, q in enumerate(procs):
+                n = int(counts[c, j])
+                items.append((j, pools[q][:n], ones[:n], card.row(q),
+                              torch.full((n,), -1.0, dtype=torch.float64, device="cuda")))
+                plain.append(torch.empty((1, n), dtype=torch.float64, device="cuda"))
+        b = rw.rwgt_batch_create(ctxs)
+        segs, keep = rw.make_segments(items)
+        rw.rwgt_batch_eval(b, segs)
+        for ctx in ctxs:
+            rw.rwgt_set_stream(ctx, None)
+        for (j, mom, w, row, _), out in zip(items, plain):
+            rw.rwgt_eval(ctxs[j], mom, w, row, out)
+        torch.cuda.synchronize()
+        for k, ((j, _, _, _, got), want) in enumerate(zip(items, plain)):
+            assert torch.equal(got, want[0]), f"segment {k}"
+        for c, card in enumerate(grid):
+            for j, q in enumerate(procs):
+                n = int(counts[c, j])
+                sel = np.array([0, n - 1])
+                ref, _, _ = reweight.reweight(q, host[q][sel], np.ones(2), synth.ORIG_EW, [card])
+                got = items[2 * c + j][4][torch.as_tensor(sel).cuda()].cpu().numpy()
+                assert rel_err(got, ref[0]).max() < 1e-11, (c, q)
+    finally:
+        if b is not None:
+            rw.rwgt_batch_destroy(b)
+        for ctx in ctxs:
+            rw.rwgt_destroy(ctx)
+
+
+def test_surrogate_gate_full_size():
+    """The surrogate path of the held-out workload (1e6 u u~ -> e+ e- g events,
+    a grid card per event, the fused width-128 physics network; untrained,
+    with the threshold at the median of its error bound so that half the
+    events fall back): every fallback event carries the exact card-per-event
+    w' bit for bit, every other event w exp(mu) of the fused kernel's own
+    prediction (to a few ulp: the same float mu, exp on the host), and the
+    fallback set is the set the bound k e^s > threshold selects (up to ties
+    within 1e-6 of the threshold, where host and device exp may differ)."""
+    _case("surrogate_gate", n=N_FULL)
+    torch = torch_cuda()
+    import paper_2510_05100_amd as rw
+    p = synth.events("uu_eeg", N_FULL, seed=synth.workloads.SEED_SUR_HELDOUT)
+    grid = synth.batch_grid()
+    table = np.stack([c.row("uu_eeg") for c in grid])
+    cards = np.stack([[c.MZ, c.WZ, c.sw2] for c in grid]).astype(np.float32)
+    cidx = synth.surrogate_cards(N_FULL).astype(np.int32)
+    w = np.linspace(0.5, 2.0, N_FULL)
+    kind, k_cal = rw.RWGT_FEAT_PHYS, 3.3
+    ctx = rw.rwgt_create(PROCESS_TEXT["uu_eeg"], synth.ORIG_EW.slha(), 0)
+    m = rw.rwgt_mlp_create(rw.n_features(kind, 5), 128, 3, 2, 0, 3)
+    try:
+        rw.rwgt_set_stream(ctx, None)
+        rw.rwgt_mlp_set_stream(m, None)
+        rw.rwgt_mlp_set_features(m, kind, 5, (2, 3), (synth.ORIG_EW.MZ, synth.ORIG_EW.WZ))
+        pd, wd, cd = dev(p), dev(w), torch.as_tensor(cidx).cuda()
+        card_d = torch.as_tensor(cards).cuda()
+        rw.rwgt_mlp_fit_normalisation(m, pd, None, cd, card_d, 100_000)
+        rw.rwgt_mlp_set_target_scale(m, 0.0, 0.02)
+        rw.rwgt_mlp_set_calibration(m, k_cal)
+        exact = torch.empty(N_FULL, dtype=torch.float64, device="cuda")
+        rw.rwgt_eval_cards(ctx, pd, wd, table, cd, exact)
+        heads = torch.empty((N_FULL, 2), dtype=torch.float32, device="cuda")
+        rw.rwgt_mlp_predict(m, pd, None, cd, card_d, N_FULL, heads)
+        torch.cuda.synchronize()
+        h = heads.cpu().numpy()
+        bound = np.float32(k_cal) * np.exp(h[:, 1])
+        thr = float(np.median(bound))
+        out = torch.full((N_FULL,), np.nan, dtype=torch.float64, device="cuda")
+        nfb = rw.rwgt_sur_eval(ctx, m, pd, wd, table, cd, thr, out)
+        torch.cuda.synchronize()
+        o, e = out.cpu().numpy(), exact.cpu().numpy()
+    finally:
+        rw.rwgt_mlp_destroy(m)
+        rw.rwgt_destroy(ctx)
+    assert np.all(np.isfinite(o))
+    clear = np.abs(bound / np.float32(thr) - 1) > 1e-6
+    want_fb = (bound > thr) | ~np.isfinite(h[:, 0])
+    fb = o == e
+    assert np.array_equal(fb[clear], want_fb[clear])
+    assert abs(int(nfb) - int(want_fb.sum())) <= int((~clear).sum())
+    net = clear & ~want_fb
+    np.testing.assert_allclose(o[net], w[net] * np.exp(h[net, 0].astype(np.float64)), rtol=1e-14, atol=0)
