@@ -71,6 +71,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-factored", action="store_true")
+    ap.add_argument("--no-pcie", action="store_true", help="skip the pinned-host-memory (PCIe-inclusive) step")
     ap.add_argument("--surrogate-epochs", type=int, default=None,
                     help="training epochs of the surrogate networks (default: the Config default); fewer only "
                          "to keep a kernel trace short")
@@ -128,6 +129,36 @@ def cpu_baseline(p, sample, gpu_w):
             "sample": f"{sample} of the {p.shape[0]} g g -> t t~ g g events (evenly spaced), original + 1 new "
                       f"card, FP64 numpy Berends-Giele oracle, single thread, {dt:.1f} s",
             "gpu_vs_oracle_max_rel_err": parity}
+
+
+def pcie_inclusive(rw, torch, p, rows, events, steps):
+    """The FP64 step with the momenta and weights starting in pinned host
+    memory: host-to-device copies, then the same rwgt_eval, all on one stream
+    and timed together (the boundary takes device pointers, so this rate is
+    reported beside `value`, never as it)."""
+    host_p = torch.as_tensor(p).pin_memory()
+    host_w = torch.ones(events, dtype=torch.float64).pin_memory()
+    dev_p = torch.empty_like(host_p, device="cuda")
+    dev_w = torch.empty_like(host_w, device="cuda")
+    out = torch.empty((rows.shape[0], events), dtype=torch.float64, device="cuda")
+    ms = []
+    with rw.Reweighter("g g > t t~ g g", __import__("synth").ORIG_QCD.slha(), rw.RWGT_FP64) as r:
+        for i in range(steps + 1):
+            s, e, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            s.record()
+            dev_p.copy_(host_p, non_blocking=True)
+            dev_w.copy_(host_w, non_blocking=True)
+            c.record()
+            r.eval(dev_p, dev_w, rows, out, stream=torch.cuda.current_stream())
+            e.record()
+            torch.cuda.synchronize()
+            if i:                                  # the first pass warms up
+                ms.append((s.elapsed_time(e), s.elapsed_time(c)))
+    step = float(np.mean([m[0] for m in ms]))
+    copy = float(np.mean([m[1] for m in ms]))
+    nbytes = host_p.numel() * 8 + host_w.numel() * 8
+    return {"ms_per_step": step, "copy_ms": copy, "h2d_bytes": nbytes, "h2d_GBps": nbytes / (copy * 1e-3) / 1e9,
+            "value": events * rows.shape[0] / (step * 1e-3), "unit": "reweighted events/s"}
 
 
 def batched_leg(rw, torch, precision, steps, warmup):
@@ -274,6 +305,9 @@ def main():
         line["mixed"] = {"value": a.events * nsets / (x["ms_per_step"] * 1e-3), "ms_per_step": x["ms_per_step"],
                          "max_rel_err": x["max_rel_err"], "dtype": "f32 amplitudes, f64 momenta/denominators/ratio",
                          "roofline": roofline(x, PEAK_FP32_VALU_UNPACKED, "mixed")}
+    if main_mode == "fp64" and not a.no_pcie:
+        line["pcie_inclusive"] = pcie_inclusive(rw, torch, p, rows, a.events, steps=3)
+        log(f"pcie-inclusive: {line['pcie_inclusive']['ms_per_step']:.2f} ms/step")
     if not a.no_batched:
         line["batched"] = {}
         for mode, prec in (("fp64", rw.RWGT_FP64), ("mixed", rw.RWGT_MIXED_FP16)):
