@@ -287,15 +287,16 @@ def test_surrogate_path_fallback_is_exact():
         rw.rwgt_destroy(ctx)
 
 
-@pytest.mark.parametrize("fused", [False, True])
-def test_fused_gate_fallback_is_exact(fused):
+@pytest.mark.parametrize("fused,n", [(False, 5000), (True, 5000), (True, 37)])
+def test_fused_gate_fallback_is_exact(fused, n):
     """Gate of a fused-eligible network (one kernel) and of a layered one:
     events it sends to the exact path carry the exact w' bit for bit, the
-    others w exp(mu) of that network's own prediction."""
-    print(f"[case] gate fused={fused}", flush=True)
+    others w exp(mu) of that network's own prediction.  n = 37: one partial
+    workgroup, whose waves past the last row still reach the gate's barriers.
+    Threshold 0: every event falls back; infinite: none does."""
+    print(f"[case] gate fused={fused} n={n}", flush=True)
     torch = torch_cuda()
     import paper_2510_05100_amd as rw
-    n = 5000
     p = synth.events("uu_eeg", n)
     grid = synth.batch_grid()
     table = np.stack([c.row("uu_eeg") for c in grid])
@@ -325,9 +326,12 @@ def test_fused_gate_fallback_is_exact(fused):
         h = heads.cpu().numpy()
         thr = float(np.median(3.3 * np.exp(h[:, 1])))
         out = torch.full((n,), np.nan, dtype=torch.float64, device="cuda")
+        none = torch.full((n,), np.nan, dtype=torch.float64, device="cuda")
+        assert rw.rwgt_sur_eval(ctx, m, pd, wd, table, cd, float("inf"), none) == 0
         nfb = rw.rwgt_sur_eval(ctx, m, pd, wd, table, cd, thr, out)
         torch.cuda.synchronize()
         o, e = out.cpu().numpy(), exact.cpu().numpy()
+        np.testing.assert_allclose(none.cpu().numpy(), w * np.exp(h[:n, 0].astype(np.float64)), rtol=2e-3)
     finally:
         rw.rwgt_mlp_destroy(m)
         rw.rwgt_destroy(ctx)
