@@ -45,11 +45,11 @@ template <> __device__ __forceinline__ const Card<float>& pick<float>(const Card
 
 // Colour-flow amplitudes of one lane kept in LDS, [NCOL][kMeBlock] so that
 // the lanes of a wave touch consecutive addresses.
-template <class R, int NCOL>
+template <class R, int NCOL, int STRIDE = kMeBlock>
 struct LdsJamp {
   cx<R>* base;
-  __device__ __forceinline__ cx<R>& operator[](int c) { return base[c * kMeBlock]; }
-  __device__ __forceinline__ const cx<R>& operator[](int c) const { return base[c * kMeBlock]; }
+  __device__ __forceinline__ cx<R>& operator[](int c) { return base[c * STRIDE]; }
+  __device__ __forceinline__ const cx<R>& operator[](int c) const { return base[c * STRIDE]; }
 };
 
 // Where a lane keeps its colour-flow amplitudes: registers, unless the
@@ -75,19 +75,47 @@ __device__ __forceinline__ double me2_event(const double (&P)[PROC::NPART][4], c
 template <class CT> struct ColourLdsOf { typedef ColourLds<CT> type; };
 template <> struct ColourLdsOf<void> { typedef char type; };
 
-// One lane per event.  R: amplitude precision.  CT: 16-bit type of the
-// matrix-core colour sum (_Float16 or __bf16), or void for the VALU form.
+// Waves per event group: the helicity sum of a many-flow process is split
+// between the HS waves of a 64 HS-lane workgroup (consecutive blocks of
+// helicities, each wave-uniform, added through LDS per card): HS times the
+// waves, each HS times shorter, so the last round of waves leaves fewer
+// SIMDs idle, and with wave-uniform loop bounds fewer registers spill.
+// Few-flow processes keep one lane per event in 256-lane workgroups and the
+// one-lane summation order, which their card-per-event and batched kernels
+// reproduce bit for bit.  g g -> t t~ g g, 1e6 events: 161.4 ms with one
+// wave, 152.9 ms with two (24 spilled registers instead of 54), 155.6 ms
+// with four (56 spilled).
+constexpr int kHelSplit = 2;
+template <class PROC>
+constexpr int hel_split() { return PROC::NCOL >= 8 ? kHelSplit : 1; }
+template <class PROC>
+constexpr int me_block() { return hel_split<PROC>() > 1 ? 64 * hel_split<PROC>() : kMeBlock; }
+
+// One event per lane (of each wave of the helicity split).  R: amplitude
+// precision.  CT: 16-bit type of the matrix-core colour sum (_Float16 or
+// __bf16), or void for the VALU form.
 template <class PROC, class R, class CT>
 __global__ __launch_bounds__(kMeBlock) void me_kernel(const double* __restrict__ soa, int64_t nevt,
                                                       const CardPair* __restrict__ cards, int ncards,
                                                       const double* __restrict__ w_in, double* __restrict__ w_out,
                                                       double* __restrict__ me_out) {
   constexpr bool kMfma = !std::is_void<CT>::value;
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  // whole waves past the end leave together; inside the last wave the lanes
-  // past the end recompute the last event (the matrix-core colour sum needs
-  // every lane) and write nothing
-  if (int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63) >= nevt) return;
+  constexpr int HS = hel_split<PROC>(), B = me_block<PROC>();
+  constexpr int EPB = HS > 1 ? 64 : B;                        // events per workgroup
+  constexpr int NH = PROC::NGOOD / HS;                        // helicities per wave
+  static_assert(PROC::NGOOD % HS == 0 && EPB % 64 == 0, "helicity split");
+  // which helicities: wave-uniform, kept in a scalar register so that the
+  // helicity of each loop trip stays uniform too
+  const int half = HS > 1 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)) : 0;
+  const int64_t i = int64_t(blockIdx.x) * EPB + (HS > 1 ? int(threadIdx.x & 63) : int(threadIdx.x));
+  // whole waves (split: whole workgroups) past the end leave together; inside
+  // the last wave the lanes past the end recompute the last event (the
+  // matrix-core colour sum needs every lane) and write nothing
+  if constexpr (HS > 1) {
+    if (int64_t(blockIdx.x) * EPB >= nevt) return;
+  } else {
+    if (int64_t(blockIdx.x) * B + (threadIdx.x & ~63) >= nevt) return;
+  }
   const bool valid = i < nevt;
   const int64_t ie = valid ? i : nevt - 1;
   double P[PROC::NPART][4];
@@ -96,8 +124,9 @@ __global__ __launch_bounds__(kMeBlock) void me_kernel(const double* __restrict__
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) P[a][mu] = soa[int64_t(a * 4 + mu) * nevt + ie];
 
-  [[maybe_unused]] __shared__ cx<R> lds_jamp[jamp_in_lds<PROC, R>() ? PROC::NCOL * kMeBlock : 1];
-  [[maybe_unused]] __shared__ typename ColourLdsOf<CT>::type lds_colour[kMfma ? kMeBlock / 64 : 1];
+  [[maybe_unused]] __shared__ cx<R> lds_jamp[jamp_in_lds<PROC, R>() ? PROC::NCOL * B : 1];
+  [[maybe_unused]] __shared__ typename ColourLdsOf<CT>::type lds_colour[kMfma ? B / 64 : 1];
+  [[maybe_unused]] __shared__ double lds_half[HS > 1 ? 64 * (HS - 1) : 1];   // the other waves' partial sums
   [[maybe_unused]] std::conditional_t<kMfma, ColourMfma<PROC::NCOL, std::conditional_t<kMfma, CT, _Float16>>, char> cm;
   if constexpr (kMfma) cm.init(PROC::cnum(), lds_colour[threadIdx.x >> 6]);
 
@@ -105,11 +134,11 @@ __global__ __launch_bounds__(kMeBlock) void me_kernel(const double* __restrict__
   for (int k = 0; k < ncards; ++k) {
     const Card<R>& cd = pick<R>(cards[k]);
     double me = 0.0;
-    for (int ih = 0; ih < PROC::NGOOD; ++ih) {
+    for (int ih = half * NH; ih < (half + 1) * NH; ++ih) {
       // The generated code reads the momenta through opq() at every use, so
       // none of the helicity-independent algebra is hoisted out of this loop.
       if constexpr (jamp_in_lds<PROC, R>()) {
-        LdsJamp<R, PROC::NCOL> jamp{lds_jamp + threadIdx.x};
+        LdsJamp<R, PROC::NCOL, B> jamp{lds_jamp + threadIdx.x};
         PROC::template jamps_grouped<R>(P, PROC::good(ih), cd, jamp);
         me += double(PROC::template colour_sum<R>(jamp));
       } else {
@@ -122,8 +151,15 @@ __global__ __launch_bounds__(kMeBlock) void me_kernel(const double* __restrict__
         }
       }
     }
+    if constexpr (HS > 1) {                      // the waves' partial sums in order, on the first wave
+      if (half > 0) lds_half[(half - 1) * 64 + (threadIdx.x & 63)] = me;
+      __syncthreads();
+      if (half == 0)
+        for (int w = 1; w < HS; ++w) me += lds_half[(w - 1) * 64 + threadIdx.x];
+      __syncthreads();                           // before the next card's partial sums
+    }
     me *= PROC::AVERAGE;
-    if (!valid) continue;
+    if (!valid || half != 0) continue;
     if (me_out) me_out[int64_t(k) * nevt + i] = me;
     if (w_out) {
       if (k == 0) {
@@ -138,9 +174,10 @@ __global__ __launch_bounds__(kMeBlock) void me_kernel(const double* __restrict__
 template <class PROC, class R, class CT>
 inline hipError_t launch_me_t(const double* soa, int64_t nevt, const CardPair* cards, int ncards,
                               const double* w_in, double* w_out, double* me_out, hipStream_t s) {
-  const int64_t blocks = (nevt + kMeBlock - 1) / kMeBlock;
-  hipLaunchKernelGGL((me_kernel<PROC, R, CT>), dim3(unsigned(blocks)), dim3(kMeBlock), 0, s, soa, nevt, cards,
-                     ncards, w_in, w_out, me_out);
+  constexpr int B = me_block<PROC>(), EPB = hel_split<PROC>() > 1 ? 64 : B;
+  const int64_t blocks = (nevt + EPB - 1) / EPB;
+  hipLaunchKernelGGL((me_kernel<PROC, R, CT>), dim3(unsigned(blocks)), dim3(B), 0, s, soa, nevt, cards, ncards,
+                     w_in, w_out, me_out);
   return hipGetLastError();
 }
 
