@@ -64,3 +64,16 @@ def test_mixed_ragged_last_wave():
         me = gpu_me2("gg_ttgg", p, synth.ORIG_QCD, [synth.ORIG_QCD], MIXED["fp16"])[0]
         ref = reweight.me2("gg_ttgg", p, synth.ORIG_QCD)
         assert rel_err(me, ref).max() < 1e-4
+
+
+def test_fp64_ragged_last_workgroup():
+    # the two waves of a workgroup split each event's helicity sum and add
+    # through LDS: a last workgroup with fewer than 64 events (lanes past the
+    # end recompute the last event and write nothing)
+    for n in (1, 65, 127):
+        print(f"[case] fp64 ragged n={n}", flush=True)
+        p = synth.events("gg_ttgg", n)
+        me = gpu_me2("gg_ttgg", p, synth.ORIG_QCD, [synth.ORIG_QCD, synth.NEW_QCD])
+        ref = reweight.me2("gg_ttgg", p, synth.ORIG_QCD)
+        assert rel_err(me[0], ref).max() < 1e-10
+        assert np.max(np.abs(me[1] / me[0] / ((0.130 / 0.118) ** 4) - 1)) < 1e-12
