@@ -7,7 +7,7 @@
  *
  *     w'_i = (w_i * (1 / |M|^2(p_i; theta))) * |M|^2(p_i; theta'),   1/0 -> 0
  *
- * (the normaliser / backlog order of procReweightor, the ratio of the teaRex
+ * (the normalise-then-multiply order of the teaRex section, the ratio of its
  * introduction), where |M|^2 is the tree-level squared matrix element summed
  * over helicities and colours and averaged over initial spins and colours
  * (MadtRex section: leading order, helicity-summed).  The per-event evaluation

@@ -8,7 +8,7 @@ path; the two meet only in the seeded inputs of ``synth``.
 What it computes is the plain definition of the reweighting result (the
 parameter-reweighting ratio w' = w |M'|^2 / |M|^2 of the paper's teaRex
 section, with the normaliser's 1/0 -> 0 guard and the normalise-then-multiply
-order of ``procReweightor::initialise``):
+order the same section gives for the reweighting step):
 
   |M|^2(p; card) = A_P * sum_hel sum_colours | sum_diagrams M_d |^2
 

@@ -2,8 +2,8 @@
 
 For event weights w and the original card theta, each new card theta_k gives
 
-  norm_i = w_i * (1/|M|^2(p_i; theta))   with 1/0 -> 0   (procReweightor::initialise)
-  w'_ki  = norm_i * |M|^2(p_i; theta_k)                  (append of the backlog)
+  norm_i = w_i * (1/|M|^2(p_i; theta))   with 1/0 -> 0   (teaRex section: normalisation)
+  w'_ki  = norm_i * |M|^2(p_i; theta_k)                  (teaRex section: new weights)
 
 i.e. w' = w |M'|^2/|M|^2 (the parameter-reweighting ratio of the teaRex
 introduction), evaluated in that order.  The cross section and its error
