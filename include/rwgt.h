@@ -175,8 +175,8 @@ int rwgt_kernel_times(rwgt_ctx *ctx, float *ingest_ms, float *me_ms);
  * one persistent kernel (workgroups take event tiles from a shared counter),
  * captured once into a HIP graph and replayed while the number of segments,
  * tiles and the schedule stay the same.  The schedule (tile size, workgroup
- * size, workgroups per CU) comes from rwgt_batch_set_schedule, the tuning
- * cache written by rwgt_batch_tune, or a default.  The paper runs
+ * size, workgroups per CU, helicity split) comes from rwgt_batch_set_schedule,
+ * the tuning cache written by rwgt_batch_tune, or a default.  The paper runs
  * subprocesses on a CPU thread pool and notes that sequential subprocesses
  * leave the GPU latency-bound; this is the single-launch alternative.
  * Family: e+ e- > mu+ mu- and u u~ > e+ e- g, all contexts of one precision.
@@ -205,9 +205,15 @@ int rwgt_batch_eval(rwgt_batch *batch, const rwgt_segment *segments, int32_t nse
 /* Milliseconds of the last graph launch (waits for it). */
 int rwgt_batch_time(rwgt_batch *batch, float *ms);
 /* Fix the schedule: events per tile, threads per workgroup (64..256, multiple
- * of 64), persistent workgroups per compute unit. */
-int rwgt_batch_set_schedule(rwgt_batch *batch, int32_t tile_events, int32_t block, int32_t blocks_per_cu);
-int rwgt_batch_get_schedule(const rwgt_batch *batch, int32_t *tile_events, int32_t *block, int32_t *grid);
+ * of 64), persistent workgroups per compute unit, and hel_split: 0 = one lane
+ * per event (both cards, every kept helicity), 1 = one lane per (event, card,
+ * kept helicity), the lanes of an event added in the one-lane order (the
+ * same result to the bit).  Errors: RWGT_EINVAL. */
+int rwgt_batch_set_schedule(rwgt_batch *batch, int32_t tile_events, int32_t block, int32_t blocks_per_cu,
+                            int32_t hel_split);
+/* hel_split may be NULL. */
+int rwgt_batch_get_schedule(const rwgt_batch *batch, int32_t *tile_events, int32_t *block, int32_t *grid,
+                            int32_t *hel_split);
 /* Autotune the schedule on these segments (each candidate timed reps times
  * after one capture run); keeps the fastest and records it in the cache. */
 int rwgt_batch_tune(rwgt_batch *batch, const rwgt_segment *segments, int32_t nsegments, int32_t reps);

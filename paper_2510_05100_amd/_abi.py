@@ -59,8 +59,9 @@ SIGNATURES.update({
     "rwgt_batch_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rwgt_batch_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Segment), ctypes.c_int32]),
     "rwgt_batch_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
-    "rwgt_batch_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
-    "rwgt_batch_get_schedule": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int32)] * 3),
+    "rwgt_batch_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.c_int32]),
+    "rwgt_batch_get_schedule": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int32)] * 4),
     "rwgt_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Segment), ctypes.c_int32, ctypes.c_int32]),
     "rwgt_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
 })
@@ -397,18 +398,18 @@ def rwgt_batch_time(batch):
     return ms.value
 
 
-def rwgt_batch_set_schedule(batch, tile_events, block, blocks_per_cu):
-    rc = load().rwgt_batch_set_schedule(batch, tile_events, block, blocks_per_cu)
+def rwgt_batch_set_schedule(batch, tile_events, block, blocks_per_cu, hel_split=0):
+    rc = load().rwgt_batch_set_schedule(batch, tile_events, block, blocks_per_cu, int(hel_split))
     if rc != 0:
         _braise(rc, batch)
 
 
 def rwgt_batch_get_schedule(batch):
-    v = [ctypes.c_int32() for _ in range(3)]
+    v = [ctypes.c_int32() for _ in range(4)]
     rc = load().rwgt_batch_get_schedule(batch, *[ctypes.byref(x) for x in v])
     if rc != 0:
         _braise(rc, batch)
-    return dict(zip(("tile_events", "block", "grid"), (x.value for x in v)))
+    return dict(zip(("tile_events", "block", "grid", "hel_split"), (x.value for x in v)))
 
 
 def rwgt_batch_tune(batch, segments, reps=2):

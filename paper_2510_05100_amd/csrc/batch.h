@@ -27,6 +27,7 @@ struct BatchSchedule {
   int tile_events;       // events per tile
   int block;             // threads per workgroup
   int grid;              // persistent workgroups
+  int hel_split;         // 0: one lane per event; 1: one lane per (event, card, helicity)
 };
 
 hipError_t launch_batch(int family, int precision, const BatchSeg* segs, int nseg, int64_t ntiles,

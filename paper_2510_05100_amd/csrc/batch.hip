@@ -37,6 +37,39 @@ __device__ __forceinline__ void batch_dispatch(int proc, const BatchSeg& sg, int
   ((proc == idx++ ? batch_event<R, PROCS>(sg, e, c0, c1) : void()), ...);
 }
 
+// One event on the 2 NGOOD consecutive lanes of a group (lane j of the
+// group, the group's first lane at lane0 of the wave): lane j evaluates
+// |M_h|^2 of helicity good(j % NGOOD) under c0 (j < NGOOD) or c1; the first
+// lane gathers the group's values with shuffles, adds each card's in
+// helicity order (the order of the one-lane-per-event kernels, so the result
+// is the same to the bit) and writes w' = (w (1/|M|^2_0)) |M|^2_1.  Every lane
+// of the group must call it.
+template <class R, class PROC>
+__device__ __forceinline__ void hel_group_event(const double* __restrict__ src, int j, int lane0, const CardPair& c0,
+                                                const CardPair& c1, const double* __restrict__ w_in,
+                                                double* __restrict__ w_out) {
+  constexpr int G = PROC::NGOOD;
+  double P[PROC::NPART][4];
+#pragma unroll
+  for (int a = 0; a < PROC::NPART; ++a)
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) P[a][mu] = src[a * 4 + mu];
+  cx<R> jamp[PROC::NCOL];
+  PROC::template jamps<R>(P, PROC::good(j % G), pick<R>(j < G ? c0 : c1), jamp);
+  const double hm = double(PROC::template colour_sum<R>(jamp));
+  double m0 = 0.0, m1 = 0.0;
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    m0 += __shfl(hm, lane0 + k);
+    m1 += __shfl(hm, lane0 + G + k);
+  }
+  if (j == 0) {
+    m0 *= PROC::AVERAGE;
+    m1 *= PROC::AVERAGE;
+    *w_out = ((m0 == 0.0 ? 0.0 : 1.0 / m0) * *w_in) * m1;
+  }
+}
+
 __global__ void batch_reset(unsigned long long* counter) { *counter = 0ull; }
 
 template <class R, class... PROCS>
@@ -63,12 +96,56 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchSeg* __restrict__
   }
 }
 
+// The events of one tile of a segment of process PROC, one (event, card,
+// helicity) per lane: 2 NGOOD lanes per event (the workgroup size is a
+// multiple of 64, which 2 NGOOD divides).
+template <class R, class PROC>
+__device__ __forceinline__ void hel_tile(const BatchSeg& sg, int64_t e0, int64_t e1, const CardPair& c0,
+                                         const CardPair& c1) {
+  constexpr int G2 = 2 * PROC::NGOOD;
+  static_assert(64 % G2 == 0, "event groups tile a wave");
+  const int j = int(threadIdx.x) % G2;
+  const int lane0 = int(threadIdx.x & 63) - j;
+  for (int64_t e = e0 + threadIdx.x / G2; e < e1; e += blockDim.x / G2)
+    hel_group_event<R, PROC>(sg.mom + e * (PROC::NPART * 4), j, lane0, c0, c1, sg.w_in + e, sg.w_out + e);
+}
+
+// The persistent batch kernel with the helicity split: tiles claimed as in
+// batch_kernel, each tile's events spread over (event, card, helicity) lanes.
+template <class R, class... PROCS>
+__global__ __launch_bounds__(256) void batch_hel_kernel(const BatchSeg* __restrict__ segs, int nseg, int64_t ntiles,
+                                                        int tile_events, const CardPair* __restrict__ cards,
+                                                        unsigned long long* counter) {
+  __shared__ long long s_tile;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    __syncthreads();
+    if (tile >= ntiles) return;
+    int lo = 0, hi = nseg - 1;                 // last segment with tile0 <= tile
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (segs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+    }
+    const BatchSeg sg = segs[lo];
+    const int64_t e0 = (tile - sg.tile0) * tile_events;
+    const int64_t e1 = e0 + tile_events < sg.nevt ? e0 + tile_events : sg.nevt;
+    int idx = 0;
+    ((sg.proc == idx++ ? hel_tile<R, PROCS>(sg, e0, e1, cards[2 * lo], cards[2 * lo + 1]) : void()), ...);
+  }
+}
+
 template <class R, class... PROCS>
 static hipError_t launch_batch_t(const BatchSeg* segs, int nseg, int64_t ntiles, const BatchSchedule& sc,
                                  const CardPair* cards, unsigned long long* counter, hipStream_t s) {
   hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, counter);
-  hipLaunchKernelGGL((batch_kernel<R, PROCS...>), dim3(sc.grid), dim3(sc.block), 0, s, segs, nseg, ntiles,
-                     sc.tile_events, cards, counter);
+  if (sc.hel_split)
+    hipLaunchKernelGGL((batch_hel_kernel<R, PROCS...>), dim3(sc.grid), dim3(sc.block), 0, s, segs, nseg, ntiles,
+                       sc.tile_events, cards, counter);
+  else
+    hipLaunchKernelGGL((batch_kernel<R, PROCS...>), dim3(sc.grid), dim3(sc.block), 0, s, segs, nseg, ntiles,
+                       sc.tile_events, cards, counter);
   return hipGetLastError();
 }
 
@@ -90,7 +167,7 @@ __global__ __launch_bounds__(256) void exact_hel_kernel(const double* __restrict
                                                         const int32_t* __restrict__ card_index,
                                                         const CardPair* __restrict__ cards,
                                                         const double* __restrict__ w_in, double* __restrict__ w_out) {
-  constexpr int G = PROC::NGOOD, G2 = 2 * PROC::NGOOD;
+  constexpr int G2 = 2 * PROC::NGOOD;
   static_assert(64 % G2 == 0, "event groups tile a wave");
   const int64_t n = list ? (int64_t(*count) < n_all ? int64_t(*count) : n_all) : n_all;
   const int j = int(threadIdx.x) % G2;
@@ -98,27 +175,8 @@ __global__ __launch_bounds__(256) void exact_hel_kernel(const double* __restrict
   const int64_t per_block = blockDim.x / G2;
   for (int64_t i = int64_t(blockIdx.x) * per_block + threadIdx.x / G2; i < n; i += int64_t(gridDim.x) * per_block) {
     const int64_t e = list ? int64_t(list[i]) : i;
-    double P[PROC::NPART][4];
-    const double* src = mom + e * (PROC::NPART * 4);
-#pragma unroll
-    for (int a = 0; a < PROC::NPART; ++a)
-#pragma unroll
-      for (int mu = 0; mu < 4; ++mu) P[a][mu] = src[a * 4 + mu];
-    const CardPair& cp = cards[j < G ? 0 : 1 + card_index[e]];
-    cx<R> jamp[PROC::NCOL];
-    PROC::template jamps<R>(P, PROC::good(j % G), pick<R>(cp), jamp);
-    const double hm = double(PROC::template colour_sum<R>(jamp));
-    double m0 = 0.0, m1 = 0.0;
-#pragma unroll
-    for (int k = 0; k < G; ++k) {
-      m0 += __shfl(hm, lane0 + k);
-      m1 += __shfl(hm, lane0 + G + k);
-    }
-    if (j == 0) {
-      m0 *= PROC::AVERAGE;
-      m1 *= PROC::AVERAGE;
-      w_out[e] = ((m0 == 0.0 ? 0.0 : 1.0 / m0) * w_in[e]) * m1;
-    }
+    hel_group_event<R, PROC>(mom + e * (PROC::NPART * 4), j, lane0, cards[0], cards[1 + card_index[e]], w_in + e,
+                             w_out + e);
   }
 }
 

@@ -768,11 +768,11 @@ struct rwgt_batch {
   unsigned long long* counter = nullptr;
   hipEvent_t staged = nullptr, t0 = nullptr, t1 = nullptr;
   bool staged_pending = false;
-  rwgt::BatchSchedule sched{256, 256, 0};
+  rwgt::BatchSchedule sched{256, 256, 0, 0};
   bool tuned = false;
   // captured graph and the launch shape it was captured for
   hipGraphExec_t exec = nullptr;
-  int g_nseg = -1, g_tile = 0, g_block = 0, g_grid = 0;
+  int g_nseg = -1, g_tile = 0, g_block = 0, g_grid = 0, g_hel = 0;
   int64_t g_ntiles = -1;
   std::string err;
 
@@ -826,14 +826,18 @@ bool tune_lookup(const std::string& key, rwgt::BatchSchedule& out) {
     if (bar == std::string::npos || line.substr(0, bar) != key) continue;
     std::istringstream v(line.substr(bar + 1));
     rwgt::BatchSchedule s{};
-    if (v >> s.tile_events >> s.block >> s.grid) { out = s; return true; }
+    if (v >> s.tile_events >> s.block >> s.grid) {
+      if (!(v >> s.hel_split)) s.hel_split = 0;               // entries written before the helicity split
+      out = s;
+      return true;
+    }
   }
   return false;
 }
 
 void tune_store(const std::string& key, const rwgt::BatchSchedule& s) {
   std::ofstream outf(tune_cache_path(), std::ios::app);
-  if (outf) outf << key << "|" << s.tile_events << " " << s.block << " " << s.grid << "\n";
+  if (outf) outf << key << "|" << s.tile_events << " " << s.block << " " << s.grid << " " << s.hel_split << "\n";
 }
 
 int batch_stage(rwgt_batch* b, const rwgt_segment* segs, int32_t nseg, int& nlive, int64_t& ntiles,
@@ -914,7 +918,7 @@ int batch_launch(rwgt_batch* b, int nlive, int64_t ntiles) {
   rwgt::BatchSchedule sc = b->sched;
   if (sc.grid <= 0) sc.grid = 2 * b->ncu;
   const bool same = b->exec && b->g_nseg == nlive && b->g_ntiles == ntiles && b->g_tile == sc.tile_events &&
-                    b->g_block == sc.block && b->g_grid == sc.grid;
+                    b->g_block == sc.block && b->g_grid == sc.grid && b->g_hel == sc.hel_split;
   if (!same) {
     if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
     hipGraph_t g = nullptr;
@@ -929,6 +933,7 @@ int batch_launch(rwgt_batch* b, int nlive, int64_t ntiles) {
     hipGraphDestroy(g);
     if (e != hipSuccess) { b->exec = nullptr; return b->hip_fail(e, "hipGraphInstantiate"); }
     b->g_nseg = nlive; b->g_ntiles = ntiles; b->g_tile = sc.tile_events; b->g_block = sc.block; b->g_grid = sc.grid;
+    b->g_hel = sc.hel_split;
   }
   hipEventRecord(b->t0, st);
   if ((e = hipGraphLaunch(b->exec, st)) != hipSuccess) return b->hip_fail(e, "hipGraphLaunch");
@@ -980,18 +985,23 @@ int rwgt_batch_set_stream(rwgt_batch* b, void* stream) {
   return RWGT_OK;
 }
 
-int rwgt_batch_set_schedule(rwgt_batch* b, int32_t tile_events, int32_t block, int32_t blocks_per_cu) {
-  if (!b || tile_events < 1 || block < 64 || block > 256 || block % 64 || blocks_per_cu < 1) return RWGT_EINVAL;
-  b->sched = rwgt::BatchSchedule{tile_events, block, blocks_per_cu * b->ncu};
+int rwgt_batch_set_schedule(rwgt_batch* b, int32_t tile_events, int32_t block, int32_t blocks_per_cu,
+                            int32_t hel_split) {
+  if (!b || tile_events < 1 || block < 64 || block > 256 || block % 64 || blocks_per_cu < 1 ||
+      (hel_split != 0 && hel_split != 1))
+    return RWGT_EINVAL;
+  b->sched = rwgt::BatchSchedule{tile_events, block, blocks_per_cu * b->ncu, hel_split};
   b->tuned = true;
   return RWGT_OK;
 }
 
-int rwgt_batch_get_schedule(const rwgt_batch* b, int32_t* tile_events, int32_t* block, int32_t* grid) {
+int rwgt_batch_get_schedule(const rwgt_batch* b, int32_t* tile_events, int32_t* block, int32_t* grid,
+                            int32_t* hel_split) {
   if (!b || !tile_events || !block || !grid) return RWGT_EINVAL;
   *tile_events = b->sched.tile_events;
   *block = b->sched.block;
   *grid = b->sched.grid > 0 ? b->sched.grid : 2 * b->ncu;
+  if (hel_split) *hel_split = b->sched.hel_split;
   return RWGT_OK;
 }
 
@@ -1028,9 +1038,10 @@ int rwgt_batch_time(rwgt_batch* b, float* ms) {
   return RWGT_OK;
 }
 
-// Grid search over (tile events, workgroup size, workgroups per CU) on the
-// given segments, timing each candidate with HIP events; the fastest is kept
-// and appended to the tuning cache (RWGT_TUNE_CACHE, default ~/.rwgt_autotune).
+// Grid search over (tile events, workgroup size, workgroups per CU, helicity
+// split) on the given segments, timing each candidate with HIP events; the
+// fastest is kept and appended to the tuning cache (RWGT_TUNE_CACHE, default
+// ~/.rwgt_autotune).
 int rwgt_batch_tune(rwgt_batch* b, const rwgt_segment* segs, int32_t nseg, int32_t reps) {
   if (!b || !segs || nseg < 1) return RWGT_EINVAL;
   if (reps < 1) reps = 2;
@@ -1041,23 +1052,24 @@ int rwgt_batch_tune(rwgt_batch* b, const rwgt_segment* segs, int32_t nseg, int32
   rwgt::BatchSchedule best_s = b->sched;
   int64_t total = 0;
   for (int32_t k = 0; k < nseg; ++k) total += segs[k].nevt > 0 ? segs[k].nevt : 0;
-  for (int t : tiles)
-    for (int bl : blocks)
-      for (int pc : per_cu) {
-        if (bl > t) continue;
-        b->sched = rwgt::BatchSchedule{t, bl, pc * b->ncu};
-        b->tuned = true;
-        float acc = 0.0f;
-        for (int r = 0; r <= reps; ++r) {
-          int rc = rwgt_batch_eval(b, segs, nseg);
-          if (rc != RWGT_OK) return rc;
-          float ms = 0.0f;
-          rc = rwgt_batch_time(b, &ms);
-          if (rc != RWGT_OK) return rc;
-          if (r > 0) acc += ms;   // the first run captures the graph
+  for (int hs = 0; hs <= 1; ++hs)
+    for (int t : tiles)
+      for (int bl : blocks)
+        for (int pc : per_cu) {
+          if (!hs && bl > t) continue;             // more lanes than the tile's events
+          b->sched = rwgt::BatchSchedule{t, bl, pc * b->ncu, hs};
+          b->tuned = true;
+          float acc = 0.0f;
+          for (int r = 0; r <= reps; ++r) {
+            int rc = rwgt_batch_eval(b, segs, nseg);
+            if (rc != RWGT_OK) return rc;
+            float ms = 0.0f;
+            rc = rwgt_batch_time(b, &ms);
+            if (rc != RWGT_OK) return rc;
+            if (r > 0) acc += ms;   // the first run captures the graph
+          }
+          if (acc / reps < best) { best = acc / reps; best_s = b->sched; }
         }
-        if (acc / reps < best) { best = acc / reps; best_s = b->sched; }
-      }
   b->sched = best_s;
   b->tuned = true;
   tune_store(tune_key(b, nseg, total), best_s);

@@ -54,13 +54,20 @@ def _plain(torch, rw, ctxs, job):
     return out
 
 
+@pytest.mark.parametrize("hel_split", [0, 1])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_batch_matches_plain_and_oracle(precision):
-    print(f"[case] batch precision={precision}", flush=True)
+def test_batch_matches_plain_and_oracle(precision, hel_split):
+    """Both batch kernels (one lane per event; one lane per (event, card,
+    helicity), tiles of 96 events so that groups end inside tiles and
+    segments) equal the plain path to the bit."""
+    print(f"[case] batch precision={precision} hel_split={hel_split}", flush=True)
     torch, rw, ctxs, jobs, pools = _setup(precision)
     b = rw.rwgt_batch_create(ctxs)
     try:
         segs, keep = _segments(rw, jobs)
+        if hel_split:
+            rw.rwgt_batch_set_schedule(b, 96, 256, 2, 1)
+            assert rw.rwgt_batch_get_schedule(b)["hel_split"] == 1
         rw.rwgt_batch_eval(b, segs)
         torch.cuda.synchronize()
         for job in jobs:
@@ -69,7 +76,7 @@ def test_batch_matches_plain_and_oracle(precision):
             ref = _plain(torch, rw, ctxs, job)
             torch.cuda.synchronize()
             got = job["out"].cpu().numpy()
-            assert np.max(rel_err(got, ref.cpu().numpy()[0])) < 1e-14
+            assert np.array_equal(got, ref.cpu().numpy()[0])
         if precision == 0:
             for job in jobs[:4]:
                 if job["n"] == 0:
@@ -129,6 +136,7 @@ def test_tune_picks_a_schedule(tmp_path):
         segs, keep = _segments(rw, jobs)
         sched = rw.rwgt_batch_tune(b, segs, reps=1)
         assert sched["tile_events"] >= 64 and sched["block"] in (64, 128, 256) and sched["grid"] >= 1
+        assert sched["hel_split"] in (0, 1)
         text = (tmp_path / "tune.txt").read_text()
         assert "gfx950" in text and "|" in text
         rw.rwgt_batch_eval(b, segs)
