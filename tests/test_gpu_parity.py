@@ -193,3 +193,26 @@ def test_xsec_against_oracle():
     assert rel_err(xs, rx).max() < 1e-11 and rel_err(xe, re_).max() < 1e-9
     assert not fb.any() and not rb.any()
     assert abs(xs[2] - 12.5) < 1e-10          # the original card gives back sigma
+
+
+def test_device_against_stored_oracle_values():
+    """|M|^2 and w' of the first events of each workload against the oracle
+    values stored in tests/golden/me2_oracle.json (no oracle run needed)."""
+    _print_case("golden")
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "me2_oracle.json")) as f:
+        cases = json.load(f)["cases"]
+    cards = {"ee_mumu": (synth.ORIG_EW, synth.NEW_EE), "uu_eeg": (synth.ORIG_EW, synth.NEW_UU),
+             "gg_ttgg": (synth.ORIG_QCD, synth.NEW_QCD)}
+    tol = {"ee_mumu": 1e-12, "uu_eeg": 1e-11, "gg_ttgg": 1e-10}
+    for c in cases:
+        proc, n = c["process"], c["events"]
+        orig, new = cards[proc]
+        assert list(orig.row(proc)) == c["orig"] and list(new.row(proc)) == c["new"]
+        p = synth.events(proc, n)
+        me = gpu_me2(proc, p, orig, [orig, new])
+        assert rel_err(me[0], c["me2_orig"]).max() < tol[proc]
+        assert rel_err(me[1], c["me2_new"]).max() < tol[proc]
+        wn = gpu_eval(proc, p, np.ones(n), orig, [new])[0]
+        assert rel_err(wn, c["w_new"]).max() < tol[proc]
