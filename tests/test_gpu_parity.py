@@ -216,3 +216,31 @@ def test_device_against_stored_oracle_values():
         assert rel_err(me[1], c["me2_new"]).max() < tol[proc]
         wn = gpu_eval(proc, p, np.ones(n), orig, [new])[0]
         assert rel_err(wn, c["w_new"]).max() < tol[proc]
+
+
+def test_gg_ttgg_several_cards_and_empty():
+    """Several cards in one call (the two waves of each workgroup add their
+    helicity halves through LDS once per card): every card's |M|^2 against
+    the oracle, and w'/w = (alpha_s'/0.118)^4 for each card, the card equal
+    to the original giving exactly |M|^2 / |M|^2 (1 to rounding); an empty
+    call is a no-op."""
+    _print_case("gg_several_cards")
+    torch = torch_cuda()
+    import paper_2510_05100_amd as rw
+    n = 200
+    p = synth.events("gg_ttgg", n)
+    alphas = (0.100, 0.118, 0.125, 0.130, 0.140)
+    cards = [dataclasses.replace(synth.ORIG_QCD, aS=a) for a in alphas]
+    me = gpu_me2("gg_ttgg", p, synth.ORIG_QCD, cards)
+    idx = np.array([0, 57, 199])
+    for k, c in enumerate(cards):
+        assert rel_err(me[k][idx], reweight.me2("gg_ttgg", p[idx], c)).max() < 1e-10
+    wn = gpu_eval("gg_ttgg", p, np.linspace(0.5, 2.0, n), synth.ORIG_QCD, cards)
+    w = np.linspace(0.5, 2.0, n)
+    for k, a in enumerate(alphas):
+        assert np.max(np.abs(wn[k] / w / ((a / 0.118) ** 4) - 1)) < 1e-12
+    with rw.Reweighter("g g > t t~ g g", synth.ORIG_QCD.slha()) as r:
+        out = torch.full((2, 0), -1.0, dtype=torch.float64, device="cuda")
+        r.eval(torch.empty((0, 6, 4), dtype=torch.float64, device="cuda"),
+               torch.empty(0, dtype=torch.float64, device="cuda"), np.stack([c.row("gg_ttgg") for c in cards[:2]]), out)
+        assert rw.rwgt_nonfinite(r.ctx) == 0
