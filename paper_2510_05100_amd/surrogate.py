@@ -119,8 +119,9 @@ class Surrogate:
                 sl = slice(b * cfg.batch, (b + 1) * cfg.batch)
                 lr = cfg.lr * (cfg.lr_final / cfg.lr) ** (step / max(1, nsteps - 1))
                 _abi.rwgt_mlp_features(self.mlp, mom_dev, ev[sl], cd[sl], net_cards_dev, cfg.batch, xbuf)
-                _abi.rwgt_mlp_train_step(self.mlp, xbuf, yp[sl], cfg.batch, lr, loss)
-                if b % 64 == 0:
+                probe = b % 64 == 0                 # the loss is copied out only on the steps that read it
+                _abi.rwgt_mlp_train_step(self.mlp, xbuf, yp[sl], cfg.batch, lr, loss if probe else None)
+                if probe:
                     acc += float(loss.item()) / cfg.batch
                 step += 1
             self.history.append(acc / ((steps_per_epoch + 63) // 64))
