@@ -313,13 +313,17 @@ __global__ __launch_bounds__(256) void loss_grad(const float* __restrict__ z, co
                                                  int rows, int ld, float lambda, float ym, float ys,
                                                  float* __restrict__ g, T* __restrict__ gt,
                                                  float* __restrict__ loss) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= rows) return;
-  float l = 0.0f;
-  for (int c = 0; c < ld; ++c) {
-    g[size_t(r) * ld + c] = 0.0f;
-    gt[size_t(r) * ld + c] = T(0.0f);
+  // the block's rows [r0, r0 + nr) are zeroed first with consecutive lanes on
+  // consecutive addresses, then the two head columns of the valid rows are set
+  const int r0 = blockIdx.x * blockDim.x;
+  const int nr = min(int(blockDim.x), rows - r0);
+  for (int k = threadIdx.x; k < nr * ld; k += blockDim.x) {
+    g[size_t(r0) * ld + k] = 0.0f;
+    gt[size_t(r0) * ld + k] = T(0.0f);
   }
+  __syncthreads();
+  const int r = r0 + threadIdx.x;
+  float l = 0.0f;
   if (r < n_valid) {
     // log-error head clamped at -15 (its gradient is zero below)
     const float mu = z[size_t(r) * ld], s_raw = z[size_t(r) * ld + 1], s = fmaxf(s_raw, -15.0f);
