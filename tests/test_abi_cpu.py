@@ -94,3 +94,14 @@ def test_procgen_colour_matrix_matches_bruteforce():
     for name, text, want in [("ee_mumu", "e+ e- > mu+ mu-", [[1]]), ("uu_eeg", "u u~ > e+ e- g", [[4]])]:
         num, den = emit.colour_matrix_ints(diagrams.build(diagrams.parse(name, text)))
         assert np.allclose(np.array(num) / den, want)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: any other --gpus exits with status 2 and a
+    message, before generating events or touching a device."""
+    import subprocess
+    import sys
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120, cwd=ROOT)
+    assert res.returncode == 2
+    assert "one GPU only" in res.stderr and res.stdout == ""
