@@ -108,6 +108,24 @@ def test_graph_replay_sees_new_inputs_and_recaptures():
         for j, f in zip(jobs, first):
             if j["n"]:
                 np.testing.assert_allclose(j["out"].cpu().numpy(), 3.0 * f.cpu().numpy(), rtol=1e-15)
+        # several replays in a row, with eager work and synchronisations between
+        # them (outputs cleared, weights rescaled): every replay resets its tile
+        # counter inside the graph and writes every output again
+        scale = 3.0
+        for rep in range(5):
+            for j in jobs:
+                j["out"].fill_(-1.0)
+                j["w_dev"].mul_(0.5)
+            scale *= 0.5
+            torch.cuda.synchronize()
+            rw.rwgt_batch_eval(b, segs)
+            torch.cuda.synchronize()
+            for j, f in zip(jobs, first):
+                if j["n"]:
+                    np.testing.assert_allclose(j["out"].cpu().numpy(), scale * f.cpu().numpy(), rtol=1e-15,
+                                               err_msg=f"replay {rep}")
+        for j in jobs:
+            j["w_dev"].mul_(3.0 / scale)
         # a different schedule changes the launch shape: captured again, same results
         rw.rwgt_batch_set_schedule(b, 64, 64, 1)
         for j in jobs:
