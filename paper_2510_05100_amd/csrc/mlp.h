@@ -63,7 +63,10 @@ hipError_t mlp_gemm(int tin, int tout, const void* A, const void* B, int M, int 
                     float* Cf, void* Ct, int act, float* work, int64_t work_elems, hipStream_t s);
 hipError_t mlp_transpose(int tin, int tout, const void* in, void* out, int R, int C, hipStream_t s);
 hipError_t mlp_silu_bwd(int tout, const float* dh, const float* z, float* g, void* gt, int64_t n, hipStream_t s);
-hipError_t mlp_colsum(const float* g, float* db, int R, int C, hipStream_t s);
+// db[c] = sum over the R rows of g[r][c], deterministic.  work (may be NULL):
+// ceil(R/64) C floats for row-slab partials; without enough of it the sum
+// runs in one pass (one workgroup per column).
+hipError_t mlp_colsum(const float* g, float* db, int R, int C, float* work, int64_t work_elems, hipStream_t s);
 hipError_t mlp_loss_grad(int tout, const float* z, const float* y, int n_valid, int rows, int ld, float lambda,
                          float ym, float ys, float* g, void* gt, float* loss, hipStream_t s);
 hipError_t mlp_adam(int tout, float* w, const float* grad, float* m, float* v, void* wt, void* wtt, int rows,

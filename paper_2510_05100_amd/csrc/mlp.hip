@@ -14,7 +14,8 @@
 //              the FP32 result and/or the SiLU (or identity) in the next
 //              layer's operand type.
 //   silu_bwd   G = dH * silu'(Z)
-//   colsum     db = sum over rows of G
+//   colsum     db = sum over rows of G (two coalesced passes over a
+//              workspace, else one workgroup per column)
 //   loss_grad  Gaussian-error loss of the two heads and its gradient
 //   adam       FP32 master weights, moments, and the operand-type copies W, W^T
 //   features   standardised input rows (raw or physics feature map)
@@ -301,6 +302,43 @@ __global__ __launch_bounds__(256) void colsum(const float* __restrict__ g, float
     __syncthreads();
   }
   if (threadIdx.x == 0) db[c] = part[0];
+}
+
+// The same sum in two passes over a workspace of ceil(R/64) x C partials,
+// coalesced and deterministic.  colsum_part: workgroup (x, y) takes the 64
+// columns from 64x and the 64 rows from 64y; lane = column, so each row's
+// columns are one contiguous load; each wave loads its 16 rows (every fourth)
+// before adding them, and the four waves add in wave order.  colsum_fin: one
+// wave per column adds the slab partials (lane k takes slabs k, k+64, ...)
+// and reduces the lanes with a fixed shuffle tree.
+constexpr int kColsumSlabRows = 64;
+
+__global__ __launch_bounds__(256) void colsum_part(const float* __restrict__ g, float* __restrict__ part, int R, int C) {
+  __shared__ float ws[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
+  const int r0 = blockIdx.y * kColsumSlabRows + w;
+  float v[kColsumSlabRows / 4];
+#pragma unroll
+  for (int k = 0; k < kColsumSlabRows / 4; ++k) {
+    const int r = r0 + 4 * k;
+    v[k] = (c < C && r < R) ? g[size_t(r) * C + c] : 0.0f;
+  }
+  float s = 0.0f;
+#pragma unroll
+  for (int k = 0; k < kColsumSlabRows / 4; ++k) s += v[k];
+  ws[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && c < C) part[size_t(blockIdx.y) * C + c] = ((ws[0][lane] + ws[1][lane]) + ws[2][lane]) + ws[3][lane];
+}
+
+__global__ __launch_bounds__(64) void colsum_fin(const float* __restrict__ part, float* __restrict__ db, int C,
+                                                 int slabs) {
+  const int c = blockIdx.x;
+  float s = 0.0f;
+  for (int k = threadIdx.x; k < slabs; k += 64) s += part[size_t(k) * C + c];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
+  if (threadIdx.x == 0) db[c] = s;
 }
 
 // Heads: mu = z[r][0], s = z[r][1] in standardised target units
@@ -759,8 +797,14 @@ hipError_t mlp_silu_bwd(int tout, const float* dh, const float* z, float* g, voi
   return hipGetLastError();
 }
 
-hipError_t mlp_colsum(const float* g, float* db, int R, int C, hipStream_t s) {
-  hipLaunchKernelGGL(colsum, dim3(C), dim3(256), 0, s, g, db, R, C);
+hipError_t mlp_colsum(const float* g, float* db, int R, int C, float* work, int64_t work_elems, hipStream_t s) {
+  const int64_t slabs = (int64_t(R) + kColsumSlabRows - 1) / kColsumSlabRows;
+  if (work && slabs >= 1 && slabs <= 65535 && slabs * C <= work_elems) {
+    hipLaunchKernelGGL(colsum_part, dim3((C + 63) / 64, unsigned(slabs)), dim3(256), 0, s, g, work, R, C);
+    hipLaunchKernelGGL(colsum_fin, dim3(C), dim3(64), 0, s, work, db, C, int(slabs));
+  } else {
+    hipLaunchKernelGGL(colsum, dim3(C), dim3(256), 0, s, g, db, R, C);
+  }
   return hipGetLastError();
 }
 

@@ -114,7 +114,9 @@ int rwgt_mlp::backward(const float* y, int64_t n_valid, int64_t rows) {
     if (e == hipSuccess)
       e = rwgt::mlp_gemm(ly.mode, ly.mode, gtt[l], ht[l], ly.out, ly.in, int(rows), nullptr, ly.gw, nullptr, 0, kpart,
                          kpart_elems, stream);
-    if (e == hipSuccess) e = rwgt::mlp_colsum(g[l], ly.gb, int(rows), ly.out, stream);
+    // the bias gradient's slab partials reuse kpart, free again once the
+    // weight-gradient product above has summed its chunks (stream order)
+    if (e == hipSuccess) e = rwgt::mlp_colsum(g[l], ly.gb, int(rows), ly.out, kpart, kpart_elems, stream);
     if (l == 0 || e != hipSuccess) continue;
     // dH = G W: operands G [rows][out], W^T [in][out]; then through SiLU into
     // the previous layer's gradient (FP32 and its operand type)
