@@ -239,8 +239,18 @@ __global__ __launch_bounds__(256) void ksum_k(const float* __restrict__ part, in
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t mn = int64_t(M) * N;
   if (i >= mn) return;
+  // loads in groups of eight ahead of their additions (independent loads in
+  // flight instead of one per trip); the additions keep chunk order
   float v = 0.0f;
-  for (int c = 0; c < chunks; ++c) v += part[c * mn + i];
+  int c = 0;
+  for (; c + 8 <= chunks; c += 8) {
+    float p[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) p[k] = part[(c + k) * mn + i];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v += p[k];
+  }
+  for (; c < chunks; ++c) v += part[c * mn + i];
   v += bias ? bias[i % N] : 0.0f;
   if (Cf) Cf[i] = v;
   if (Ct) Ct[i] = TO(act ? silu(v) : v);
