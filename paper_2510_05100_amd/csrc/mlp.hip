@@ -162,7 +162,20 @@ __global__ __launch_bounds__(64) void gemm_nt_bf16(const bf16* __restrict__ A, c
   const bf16* b_row = B + size_t(tn * 32 + (l & 31)) * K + 8 * (l >> 5);
   const int kb = int(blockIdx.y) * kchunk, ke = min(K, kb + kchunk);
   f32x16_t acc = {};
-  for (int k0 = kb; k0 < ke; k0 += 16) {
+  int k0 = kb;
+  // four K steps at a time: their loads in flight together, then the products
+  // in K order
+  for (; k0 + 64 <= ke; k0 += 64) {
+    bf16x8_t a[4], b[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      a[j] = *reinterpret_cast<const bf16x8_t*>(a_row + k0 + 16 * j);
+      b[j] = *reinterpret_cast<const bf16x8_t*>(b_row + k0 + 16 * j);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[j], b[j], acc, 0, 0, 0);
+  }
+  for (; k0 < ke; k0 += 16) {
     const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(a_row + k0);
     const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(b_row + k0);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
@@ -220,7 +233,24 @@ __global__ __launch_bounds__(64) void gemm_nt_f32m(const float* __restrict__ A, 
   const float* b_row = B + size_t(tn * 32 + (l & 31)) * K + 4 * (l >> 5);
   const int kb = int(blockIdx.y) * kchunk, ke = min(K, kb + kchunk);
   f32x16_t acc = {};
-  for (int k0 = kb; k0 < ke; k0 += 8) {
+  int k0 = kb;
+  // four 8-wide K blocks at a time: loads first, products in K order
+  for (; k0 + 32 <= ke; k0 += 32) {
+    float4 a[4], b[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      a[j] = *reinterpret_cast<const float4*>(a_row + k0 + 8 * j);
+      b[j] = *reinterpret_cast<const float4*>(b_row + k0 + 8 * j);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j].x, b[j].x, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j].y, b[j].y, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j].z, b[j].z, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j].w, b[j].w, acc, 0, 0, 0);
+    }
+  }
+  for (; k0 < ke; k0 += 8) {
     const float4 a = *reinterpret_cast<const float4*>(a_row + k0);
     const float4 b = *reinterpret_cast<const float4*>(b_row + k0);
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
