@@ -72,6 +72,22 @@ hipError_t mlp_loss_grad(int tout, const float* z, const float* y, int n_valid, 
 hipError_t mlp_adam(int tout, float* w, const float* grad, float* m, float* v, void* wt, void* wtt, int rows,
                     int cols, int mask_rows, int mask_cols, float lr, float b1, float b2, float eps, float c1,
                     float c2, hipStream_t s);
+// One Adam step over every parameter tensor of a network in one launch: a
+// device table of segments (each a tensor as mlp_adam takes it, at element
+// offset begin of the concatenation, begins ascending from 0) and the total
+// element count.  Per element the same arithmetic as mlp_adam.
+struct AdamSeg {
+  float* w;
+  const float* grad;
+  float* m;
+  float* v;
+  void* wt;
+  void* wtt;
+  int64_t begin;
+  int rows, cols, mask_rows, mask_cols, bf16_out;
+};
+hipError_t mlp_adam_all(const AdamSeg* segs, int nseg, int64_t total, float lr, float b1, float b2, float eps, float c1,
+                        float c2, hipStream_t s);
 hipError_t mlp_convert(int tout, const float* in, void* out, void* outt, int rows, int cols, hipStream_t s);
 hipError_t mlp_features(const FeatureMap& fm, const double* mom, const int32_t* ev, const int32_t* cidx,
                         const float* cpar, const float* mean, const float* istd, float* x, int64_t n, int64_t rows,

@@ -446,6 +446,36 @@ __global__ __launch_bounds__(256) void adam(float* __restrict__ w, const float* 
   if (wtt) wtt[size_t(c) * rows + r] = T(wi);
 }
 
+// Adam over a table of parameter tensors: element gi belongs to the last
+// segment whose begin is at most gi (a few segments: a linear scan).
+__global__ __launch_bounds__(256) void adam_all(const AdamSeg* __restrict__ segs, int nseg, int64_t total, float lr,
+                                                float b1, float b2, float eps, float c1, float c2) {
+  const int64_t gi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gi >= total) return;
+  int k = 0;
+  while (k + 1 < nseg && gi >= segs[k + 1].begin) ++k;
+  const AdamSeg sg = segs[k];
+  const int64_t i = gi - sg.begin;
+  const int r = int(i / sg.cols), c = int(i % sg.cols);
+  float wi = 0.0f;
+  if (r < sg.mask_rows && c < sg.mask_cols) {
+    const float gv = sg.grad[i];
+    const float mi = b1 * sg.m[i] + (1.0f - b1) * gv;
+    const float vi = b2 * sg.v[i] + (1.0f - b2) * gv * gv;
+    sg.m[i] = mi;
+    sg.v[i] = vi;
+    wi = sg.w[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    sg.w[i] = wi;
+  }
+  if (sg.bf16_out) {
+    if (sg.wt) static_cast<bf16*>(sg.wt)[i] = bf16(wi);
+    if (sg.wtt) static_cast<bf16*>(sg.wtt)[size_t(c) * sg.rows + r] = bf16(wi);
+  } else {
+    if (sg.wt) static_cast<float*>(sg.wt)[i] = wi;
+    if (sg.wtt) static_cast<float*>(sg.wtt)[size_t(c) * sg.rows + r] = wi;
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void convert_k(const float* __restrict__ in, T* __restrict__ out,
                                                  T* __restrict__ outt, int rows, int cols) {
@@ -870,6 +900,13 @@ hipError_t mlp_adam(int tout, float* w, const float* grad, float* m, float* v, v
   else
     hipLaunchKernelGGL(adam<float>, dim3(blocks_for(n)), dim3(256), 0, s, w, grad, m, v, static_cast<float*>(wt),
                        static_cast<float*>(wtt), rows, cols, mask_rows, mask_cols, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t mlp_adam_all(const AdamSeg* segs, int nseg, int64_t total, float lr, float b1, float b2, float eps, float c1,
+                        float c2, hipStream_t s) {
+  if (!segs || nseg < 1 || total < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(adam_all, dim3(blocks_for(total)), dim3(256), 0, s, segs, nseg, total, lr, b1, b2, eps, c1, c2);
   return hipGetLastError();
 }
 

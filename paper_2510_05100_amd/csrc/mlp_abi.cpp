@@ -134,6 +134,12 @@ int rwgt_mlp::update(float lr) {
   ++t;
   const float c1 = 1.0f / (1.0f - std::pow(b1, float(t)));
   const float c2 = 1.0f / (1.0f - std::pow(b2, float(t)));
+  if (adam_segs) {
+    hipError_t e = rwgt::mlp_adam_all(adam_segs, adam_nseg, adam_total, lr, b1, b2, eps, c1, c2, stream);
+    if (e != hipSuccess) return hip_fail(e, "adam");
+    pack_dirty = true;
+    return RWGT_OK;
+  }
   for (auto& ly : layers) {
     hipError_t e = rwgt::mlp_adam(ly.mode, ly.w, ly.gw, ly.mw, ly.vw, ly.wc, ly.wct, ly.out, ly.in, ly.out_used,
                                   ly.in_used, lr, b1, b2, eps, c1, c2, stream);
@@ -287,6 +293,27 @@ int rwgt_mlp_create(int32_t n_in, int32_t width, int32_t depth, int32_t n_out, i
     dalloc(&m->p0lo, nb * 2 * kPackBytes);
     dalloc(&m->phid, size_t(nh) * nb * nc * kPackBytes);
     dalloc(reinterpret_cast<void**>(&m->pbias), size_t(nh) * width * 4);
+  }
+  // the Adam segment table: each layer's W (operand-type copies W, W^T) and
+  // bias, in layer order, as the per-tensor calls take them
+  if (e == hipSuccess) {
+    std::vector<rwgt::AdamSeg> segs;
+    int64_t begin = 0;
+    for (const auto& ly : m->layers) {
+      segs.push_back({ly.w, ly.gw, ly.mw, ly.vw, ly.wc, ly.wct, begin, ly.out, ly.in, ly.out_used, ly.in_used,
+                      ly.mode == kMlpBF16 ? 1 : 0});
+      begin += int64_t(ly.out) * ly.in;
+      segs.push_back({ly.b, ly.gb, ly.mb, ly.vb, nullptr, nullptr, begin, 1, ly.out, 1, ly.out_used, 0});
+      begin += ly.out;
+    }
+    void* tab = nullptr;
+    dalloc(&tab, segs.size() * sizeof(rwgt::AdamSeg));
+    if (e == hipSuccess) e = hipMemcpy(tab, segs.data(), segs.size() * sizeof(rwgt::AdamSeg), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+      m->adam_segs = static_cast<rwgt::AdamSeg*>(tab);
+      m->adam_nseg = int(segs.size());
+      m->adam_total = begin;
+    }
   }
   if (e == hipSuccess && m->refresh_copies() != RWGT_OK) e = hipErrorUnknown;
   if (e == hipSuccess) e = hipDeviceSynchronize();

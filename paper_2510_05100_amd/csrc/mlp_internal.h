@@ -39,6 +39,9 @@ struct rwgt_mlp {
   std::vector<void*> h, ht, gt, gtt;
   std::vector<float*> z, g, dh;
   float* kpart = nullptr;                                 // K-chunk partial tiles of the weight gradients
+  rwgt::AdamSeg* adam_segs = nullptr;                     // device table of every parameter tensor (one Adam launch)
+  int adam_nseg = 0;
+  int64_t adam_total = 0;
   int64_t kpart_elems = 0;
   std::vector<void*> work, params;
   std::string err;
