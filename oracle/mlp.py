@@ -21,9 +21,21 @@ the photon's at the invariant mass s = s_ab of the resonant pair (a, b),
 under the card (chi) and under the original card (chi_0).  ``raw_features``
 is the plain [momenta (n*4), M_Z, Gamma_Z, sin^2 theta_W] row.
 
-Pinned by central finite differences of L, and the features by momentum
-conservation, a direct (p_i + p_j)^2 and the propagator's pole and
-high-energy limits (tests/test_oracle_mlp.py).
+Training updates every parameter by Adam (Kingma and Ba, ICLR 2015, their
+Algorithm 1): with gradient g at step t = 1, 2, ...
+  m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,
+  theta <- theta - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+(``adam_step``).  The calibration factor k of the error head is the
+``coverage`` quantile of |y - mu| / exp(s) over held-out pairs, the quantile
+taken with linear interpolation between order statistics (Hyndman and Fan's
+definition 7: position (n - 1) q of the sorted values) (``calibration_k``).
+
+Pinned (tests/test_oracle_mlp.py) by central finite differences of L,
+hand-computed two-layer networks (forward values and loss at activations
+where SiLU has closed forms), closed forms of Adam under constant and
+alternating gradients, order statistics of small samples, and the features
+by momentum conservation, a direct (p_i + p_j)^2 and the propagator's pole
+and high-energy limits.
 """
 from __future__ import annotations
 
@@ -114,6 +126,32 @@ def gradients(params, x, y, lam, scale=(0.0, 1.0)):
         if i > 0:
             g = (g @ w) * silu_grad(cache[i - 1][1])
     return grads
+
+
+def adam_step(theta, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """Adam step number t (t >= 1) on flat arrays; returns (theta, m, v)."""
+    theta, g = np.asarray(theta, np.float64), np.asarray(g, np.float64)
+    m = b1 * np.asarray(m, np.float64) + (1.0 - b1) * g
+    v = b2 * np.asarray(v, np.float64) + (1.0 - b2) * g * g
+    m_hat = m / (1.0 - b1 ** t)
+    v_hat = v / (1.0 - b2 ** t)
+    return theta - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
+def quantile_linear(values, q):
+    """Order-statistic quantile: sort, then interpolate linearly at position
+    (n - 1) q between the two neighbouring order statistics."""
+    x = np.sort(np.asarray(values, np.float64).ravel())
+    h = (x.size - 1) * q
+    lo = int(np.floor(h))
+    hi = min(lo + 1, x.size - 1)
+    return float(x[lo] + (h - lo) * (x[hi] - x[lo]))
+
+
+def calibration_k(y, mu, s, coverage):
+    """Calibration factor k: the coverage quantile of |y - mu| / exp(s)."""
+    z = np.abs(np.asarray(y, np.float64) - np.asarray(mu, np.float64)) / np.exp(np.asarray(s, np.float64))
+    return quantile_linear(z, coverage)
 
 
 def pack(params):

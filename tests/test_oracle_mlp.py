@@ -1,6 +1,10 @@
-"""Pin of the FP64 reference network: analytic gradients of the loss against
-central finite differences (including the error-head term with its held-fixed
-residual, which the finite difference reproduces by holding r fixed)."""
+"""Pins of the FP64 reference network and its training arithmetic: analytic
+gradients of the loss against central finite differences (including the
+error-head term with its held-fixed residual, which the finite difference
+reproduces by holding r fixed); forward values and losses of hand-computed
+two-layer networks; Adam against its closed forms under constant and
+alternating gradients and its scale invariance; the calibration quantile
+against order statistics."""
 import numpy as np
 
 from oracle import mlp
@@ -124,3 +128,105 @@ def test_target_scale_is_a_change_of_units():
     for (wa, ba), (wb, bb) in zip(a, b):
         np.testing.assert_allclose(wa, wb, rtol=1e-13, atol=1e-15)
         np.testing.assert_allclose(ba, bb, rtol=1e-13, atol=1e-15)
+
+
+def _hand_net():
+    """A 3 -> 2 -> 2 network with integer weights: W1 [2][3], W2 [2][2]
+    (not symmetric, so a transposed operand changes the result)."""
+    w1 = np.array([[1.0, 0.0, 2.0], [0.0, 1.0, -1.0]])
+    w2 = np.array([[2.0, 4.0], [1.0, 0.0]])
+    return [(w1, np.zeros(2)), (w2, np.array([0.5, -1.0]))]
+
+
+def test_forward_hand_computed_two_layers():
+    """Rows chosen so that every hidden pre-activation is +-ln 3, ln 2 or
+    -ln 2 / 2, where SiLU has closed forms: silu(ln 3) = (3/4) ln 3,
+    silu(-ln 3) = -(1/4) ln 3, silu(ln 2) = (2/3) ln 2,
+    silu(-ln 2 / 2) = -(ln 2 / 2)(sqrt 2 - 1)."""
+    l2, l3, r2 = np.log(2.0), np.log(3.0), np.sqrt(2.0)
+    x = np.array([[l3, -l3, 0.0], [0.0, 0.0, l2 / 2]])
+    heads, cache = mlp.forward(_hand_net(), x)
+    # row 0: h = (3/4 ln 3, -1/4 ln 3); row 1: h = (2/3 ln 2, -(ln 2/2)(sqrt 2 - 1))
+    want = np.array([[0.5 * l3 + 0.5, 0.75 * l3 - 1.0],
+                     [l2 * (10.0 / 3.0 - 2.0 * r2) + 0.5, (2.0 / 3.0) * l2 - 1.0]])
+    np.testing.assert_allclose(heads, want, rtol=1e-15, atol=1e-15)
+    np.testing.assert_allclose(cache[1][0], [[0.75 * l3, -0.25 * l3], [2 * l2 / 3, -(l2 / 2) * (r2 - 1)]],
+                               rtol=1e-15, atol=1e-15)
+
+
+def test_loss_hand_computed():
+    """Constant heads (zero last-layer weights, biases (mu, s)): with
+    y = (1, 0), mu = 0.5, s = ln 2 every row has r^2 = 1/4 and
+    exp(-2 s) = 1/4, so L = 1/8 + lambda (1/32 + ln 2); s = -20 is clamped
+    to -15; standardised targets (y - 0.5) / 2 = (1/4, -1/4) with mu = s = 0
+    give L = 1/32 (1 + lambda)."""
+    net = _hand_net()
+    x = np.array([[0.3, -0.2, 0.1], [1.0, 2.0, -3.0]])
+    const = lambda mu, s: [net[0], (np.zeros((2, 2)), np.array([mu, s]))]   # noqa: E731
+    lam = 0.1
+    assert abs(mlp.loss(const(0.5, np.log(2.0)), x, [1.0, 0.0], lam) - (0.125 + lam * (1 / 32 + np.log(2.0)))) < 1e-15
+    want = 0.125 + lam * (0.125 * np.exp(30.0) - 15.0)
+    assert abs(mlp.loss(const(0.5, -20.0), x, [1.0, 0.0], lam) / want - 1.0) < 1e-15
+    # y' = (0.25, -0.25) with mu = 0, s = 0: 1/2 * 1/16 + lam (1/2 * 1/16)
+    assert abs(mlp.loss(const(0.0, 0.0), x, [1.0, 0.0], lam, scale=(0.5, 2.0)) - (1 / 32) * (1 + lam)) < 1e-15
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient the bias-corrected moments are exactly g and
+    g^2 at every step, so each step moves theta by -lr g / (|g| + eps):
+    after T steps theta_0 - T lr g / (|g| + eps).  A missing bias correction
+    or swapped beta1 / beta2 breaks this."""
+    g = np.array([3.0, -0.02, 0.0, 1e-5, -7.5e3])
+    theta = np.array([0.1, -0.2, 0.3, 0.0, 1.0])
+    m = v = np.zeros(5)
+    lr, eps = 1e-3, 1e-8
+    th = theta
+    for t in range(1, 6):
+        th, m, v = mlp.adam_step(th, g, m, v, t, lr, eps=eps)
+    np.testing.assert_allclose(th, theta - 5 * lr * g / (np.abs(g) + eps), rtol=1e-13, atol=1e-16)
+    np.testing.assert_allclose(m, (1 - 0.9 ** 5) * g, rtol=1e-14)
+    np.testing.assert_allclose(v, (1 - 0.999 ** 5) * g * g, rtol=1e-12)
+
+
+def test_adam_alternating_gradient_closed_form():
+    """Gradients g then -g: m_2 = -(1 - b1)^2 g, so the bias-corrected
+    m_2 / (1 - b1^2) = -(1 - b1)/(1 + b1) g, while v_2 / (1 - b2^2) = g^2:
+    the second step moves theta by +lr (1 - b1)/(1 + b1) g/(|g| + eps)."""
+    g = np.array([0.5, -2.0, 1e-3])
+    b1, b2, lr, eps = 0.8, 0.95, 0.01, 1e-7
+    th1, m, v = mlp.adam_step(np.zeros(3), g, 0.0, 0.0, 1, lr, b1, b2, eps)
+    th2, m, v = mlp.adam_step(th1, -g, m, v, 2, lr, b1, b2, eps)
+    np.testing.assert_allclose(th1, -lr * g / (np.abs(g) + eps), rtol=1e-14)
+    np.testing.assert_allclose(th2 - th1, lr * (1 - b1) / (1 + b1) * g / (np.abs(g) + eps), rtol=1e-12)
+    np.testing.assert_allclose(m, -(1 - b1) ** 2 * g, rtol=1e-14)
+
+
+def test_adam_scale_invariance_without_eps():
+    """eps = 0: the update does not change when every gradient is scaled by c > 0."""
+    rng = np.random.default_rng(5)
+    gs = rng.normal(size=(4, 6))
+    a = b = np.zeros(6)
+    ma = va = mb = vb = np.zeros(6)
+    for t, g in enumerate(gs, 1):
+        a, ma, va = mlp.adam_step(a, g, ma, va, t, 0.05, eps=0.0)
+        b, mb, vb = mlp.adam_step(b, 1234.5 * g, mb, vb, t, 0.05, eps=0.0)
+    np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-15)
+
+
+def test_quantile_and_calibration_order_statistics():
+    """Position (n - 1) q between the sorted values: the median of 1..5 is
+    3, q = 0.9 gives 4 + 0.6 = 4.6, q = 0 and 1 the extremes; it equals
+    numpy's default ('linear') quantile.  calibration_k of |y - mu| = (1, 4,
+    9, 16) with s = (0, ln 2, ln 3, ln 4) takes z = (1, 2, 3, 4)."""
+    v = np.array([3.0, 1.0, 2.0, 5.0, 4.0])
+    assert mlp.quantile_linear(v, 0.5) == 3.0
+    assert abs(mlp.quantile_linear(v, 0.9) - 4.6) < 1e-15
+    assert mlp.quantile_linear(v, 0.0) == 1.0 and mlp.quantile_linear(v, 1.0) == 5.0
+    rng = np.random.default_rng(2)
+    big = rng.exponential(size=1001)
+    for q in (0.1, 0.5, 0.999):
+        assert mlp.quantile_linear(big, q) == np.quantile(big, q)
+    s = np.log([1.0, 2.0, 3.0, 4.0])
+    y = np.array([1.0, -4.0, 9.0, 16.0])
+    assert abs(mlp.calibration_k(y, 0.0, s, 1.0) - 4.0) < 1e-14
+    assert abs(mlp.calibration_k(y, 0.0, s, 0.5) - 2.5) < 1e-14
