@@ -119,6 +119,28 @@ int rwgt_eval_alphas(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const d
 int rwgt_me2(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const double *param_sets, int32_t nsets,
              double *me2_out);
 
+/* Cancellation guard of the mixed precisions (RWGT_MIXED_*).  Single-precision
+ * rounding of the amplitude terms is amplified where the terms of a colour
+ * flow cancel (the MadtRex section's usage notes warn that single precision
+ * can lose accuracy through such cancellations).  For each event the mixed
+ * kernel measures
+ *     kappa = max over cards of  sum_hel sum_t m_t |A_t|^2 / sum_hel sum_c |J_c|^2,
+ * A_t the amplitude terms (m_t: the colour flows term t enters), J_c the
+ * colour-flow amplitudes; kappa = 1 without cancellation.  Events with kappa
+ * above kappa_max are evaluated again, in double precision, within the same
+ * rwgt_eval / rwgt_me2 call, and their outputs replaced.  kappa_max <= 0
+ * turns the guard off; the default is the library's calibrated value.
+ * Applies to rwgt_eval and rwgt_me2 on mixed contexts. */
+int rwgt_set_mixed_guard(rwgt_ctx *ctx, double kappa_max);
+/* Events re-evaluated in double precision by the last rwgt_eval / rwgt_me2
+ * call on ctx (0 if the guard did not run); waits for the stream. */
+int rwgt_mixed_guard_count(rwgt_ctx *ctx, int64_t *n_reevaluated);
+/* Mixed |M|^2 (me2_out [nsets][nevt], DEVICE, optional) and kappa per event
+ * (kappa_out [nevt], DEVICE) without re-evaluation.  Errors: RWGT_EINVAL on a
+ * double-precision context or a NULL kappa_out, else as rwgt_me2. */
+int rwgt_cancellation(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const double *param_sets, int32_t nsets,
+                      double *me2_out, double *kappa_out);
+
 /* Number of non-finite entries (NaN or +-inf) in the output array of the
  * last rwgt_eval, rwgt_me2, rwgt_eval_factored or rwgt_eval_alphas call on
  * ctx (weights_out or me2_out, nsets * nevt entries); 0 when that call failed
@@ -315,6 +337,76 @@ int rwgt_mlp_train_step(rwgt_mlp *mlp, const void *x, const float *y, int64_t n,
 /* Training targets y[i] = log(w_new[i] / w_old[i]) (w_old NULL: 1; w_old = 0: y = 0). */
 int rwgt_mlp_targets(rwgt_mlp *mlp, const double *w_new, const double *w_old, int64_t n, float *y);
 const char *rwgt_mlp_last_error(const rwgt_mlp *mlp);
+/* Adam state (HOST outputs): first and second moments packed as
+ * rwgt_mlp_get_params, and the number of Adam steps taken (the t of the bias
+ * corrections 1 - beta^t).  Waits for the stream. */
+int rwgt_mlp_get_adam(rwgt_mlp *mlp, float *first, float *second, int64_t *steps);
+
+/* Training on a grid of (event, card) pairs.  Pair j of an nevt x ncards grid
+ * is event j % nevt of momenta [nevt][npart][4] (DEVICE) with card j / nevt of
+ * card_params [ncards][3] (DEVICE, M_Z, Gamma_Z, sin^2 theta_W), target
+ * y[j] (DEVICE float [ncards][nevt], e.g. from rwgt_mlp_targets on
+ * rwgt_eval's weights_out).
+ *
+ * Fits the input normalisation (mean and population standard deviation of
+ * every feature over all pairs) and the target scale (of y); waits. */
+int rwgt_mlp_fit_grid(rwgt_mlp *mlp, const double *momenta, int32_t npart, int64_t nevt, const float *card_params,
+                      int32_t ncards, const float *y);
+
+/* Schedule of rwgt_mlp_train: steps of batch pairs, floor(pairs / batch) per
+ * epoch, each pair at most once per epoch; learning rate
+ * lr (lr_final / lr)^(step / (steps - 1)) over the steps of all epochs. */
+typedef struct rwgt_train_cfg {
+  int64_t batch;      /* pairs per Adam step, 1..pairs */
+  int32_t epochs;     /* epochs of the whole schedule */
+  float lr, lr_final; /* learning rate at the first and at the last step */
+  uint64_t seed;      /* order of the pairs in each epoch (rwgt_train_order) */
+} rwgt_train_cfg;
+
+/* Trains epochs [epochs done, epoch_end) of the schedule: per step, the next
+ * batch of the epoch's pair order (rwgt_train_order of seed, epoch, pairs),
+ * their standardised features, forward, loss, backward and one Adam step.  The
+ * first call fixes the schedule; later calls (also after rwgt_mlp_load) must
+ * pass the same one, so training in pieces gives the parameters of one
+ * uninterrupted run.  epoch_loss (HOST, optional, epoch_end - epochs done
+ * floats): mean loss per pair of each epoch, read on every 64th step (then
+ * the call waits).  Errors: RWGT_EINVAL (bad sizes, schedule or epoch_end,
+ * a changed schedule), RWGT_EDEVICE, RWGT_ENOMEM. */
+int rwgt_mlp_train(rwgt_mlp *mlp, const double *momenta, int32_t npart, int64_t nevt, const float *card_params,
+                   int32_t ncards, const float *y, const rwgt_train_cfg *cfg, int32_t epoch_end, float *epoch_loss);
+/* Epochs and steps of the schedule done, and Adam steps taken (HOST outputs). */
+int rwgt_mlp_get_progress(const rwgt_mlp *mlp, int64_t *epoch, int64_t *steps, int64_t *adam_steps);
+/* Pair order of training: out[i] (HOST) = the pair at position pos0 + i of
+ * epoch `epoch` of a grid of n pairs, a bijection of [0, n) for each (seed,
+ * epoch): a four-round Feistel network keyed by SplitMix64's mixer, cycle
+ * walked into [0, n).  Host only. */
+int rwgt_train_order(uint64_t seed, int64_t epoch, int64_t n, int64_t pos0, int64_t count, int64_t *out);
+
+/* Calibration of the error head: over every pair of the grid, the residual
+ * r = |y - mu_y| and its size in predicted errors z = r / exp(s_y) (FP64 on
+ * the host, from the network's FP32 heads); k = the coverage quantile of z
+ * (linear interpolation at position (pairs - 1) coverage between order
+ * statistics) becomes the network's calibration factor.  stats (HOST, 4
+ * doubles) = (k, median r, 0.9 quantile of r, 0.999 quantile of r).  Waits.
+ * Errors: RWGT_EINVAL (coverage outside (0, 1), a non-finite residual). */
+int rwgt_mlp_calibrate(rwgt_mlp *mlp, const double *momenta, int32_t npart, int64_t nevt, const float *card_params,
+                       int32_t ncards, const float *y, double coverage, double *stats);
+
+/* Checkpoints: one file with the network shape, feature map, normalisation,
+ * target scale, calibration factor, loss weight and Adam constants, FP32
+ * master parameters, both Adam moments and their step count, the training
+ * schedule and the epochs and steps done, closed by a 64-bit FNV-1a hash.
+ * rwgt_mlp_save writes (via a temporary file renamed over path; waits);
+ * rwgt_mlp_load creates a network on the current device from a file;
+ * rwgt_mlp_checkpoint_info reads and checks a file on the host only: shape
+ * (5 ints: n_in, width, depth, n_out, precision), epochs done, Adam steps.
+ * Errors: RWGT_EINVAL (unreadable or unwritable path), RWGT_ECARD (not a
+ * checkpoint, wrong version, hash or size mismatch: message from
+ * rwgt_mlp_checkpoint_error), RWGT_EDEVICE, RWGT_ENOMEM. */
+int rwgt_mlp_save(rwgt_mlp *mlp, const char *path);
+int rwgt_mlp_load(const char *path, rwgt_mlp **out);
+int rwgt_mlp_checkpoint_info(const char *path, int32_t *shape, int64_t *epoch, int64_t *adam_steps);
+const char *rwgt_mlp_checkpoint_error(void);
 
 /* Exact reweighting with a card per event (the path rwgt_sur_eval falls back
  * to, on every event): event i gets card card_index[i] (DEVICE int32, in

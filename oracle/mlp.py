@@ -30,11 +30,17 @@ Algorithm 1): with gradient g at step t = 1, 2, ...
 taken with linear interpolation between order statistics (Hyndman and Fan's
 definition 7: position (n - 1) q of the sorted values) (``calibration_k``).
 
+A BF16 network (the surrogate's precision: BF16 weights, FP32 sums) is
+evaluated by ``forward_bf16``: its width x width layers take BF16-rounded
+weights and BF16-rounded input activations (the operands of a BF16 product);
+the first layer, the head and every sum stay in full precision.
+
 Pinned (tests/test_oracle_mlp.py) by central finite differences of L,
 hand-computed two-layer networks (forward values and loss at activations
 where SiLU has closed forms), closed forms of Adam under constant and
-alternating gradients, order statistics of small samples, and the features
-by momentum conservation, a direct (p_i + p_j)^2 and the propagator's pole
+alternating gradients, order statistics of small samples, BF16
+rounding by hand-rounded values, the BF16 network by a hand-computed
+three-layer case, and the features by momentum conservation, a direct (p_i + p_j)^2 and the propagator's pole
 and high-energy limits.
 """
 from __future__ import annotations
@@ -62,6 +68,30 @@ def forward(params, x):
         cache.append((h, z))
         h = silu(z) if i + 1 < len(params) else z
     return h, cache
+
+
+def bf16(x):
+    """Nearest bfloat16 value (8 significant bits, ties to even) of each
+    element, returned as float64: x = m 2^e with 1/2 <= |m| < 1, the
+    significand m 2^8 rounded to the nearest integer (half to even)."""
+    m, e = np.frexp(np.asarray(x, dtype=np.float64))
+    return np.ldexp(np.rint(m * 256.0), e - 8)
+
+
+def forward_bf16(params, x):
+    """Heads of the network with BF16 hidden layers: every width x width layer
+    (all but the first and the head) multiplies BF16-rounded weights by
+    BF16-rounded input activations; the first layer and the head keep their
+    weights and inputs as given; every sum, bias and activation is exact
+    (FP64 here)."""
+    h = np.asarray(x, dtype=np.float64)
+    last = len(params) - 1
+    for i, (w, b) in enumerate(params):
+        if 0 < i < last:
+            w, h = bf16(w), bf16(h)
+        z = h @ np.asarray(w, np.float64).T + b
+        h = silu(z) if i < last else z
+    return h
 
 
 def raw_features(p, cards):

@@ -10,7 +10,9 @@ from ._abi import (  # noqa: F401
     rwgt_mlp_set_normalisation, rwgt_mlp_set_params, rwgt_mlp_set_stream, rwgt_mlp_set_training, rwgt_mlp_targets,
     rwgt_mlp_train_step, rwgt_sur_eval, RWGT_FEAT_RAW, RWGT_FEAT_PHYS, n_features, rwgt_mlp_set_features,
     rwgt_mlp_set_target_scale, rwgt_mlp_predict, rwgt_mlp_fit_normalisation,
-    rwgt_mlp_fit_target_scale, rwgt_mlp_get_normalisation, rwgt_eval_cards,
+    rwgt_mlp_fit_target_scale, rwgt_mlp_get_normalisation, rwgt_eval_cards, rwgt_mlp_get_adam, rwgt_mlp_fit_grid,
+    rwgt_mlp_train, rwgt_mlp_get_progress, rwgt_train_order, rwgt_mlp_calibrate, rwgt_mlp_save, rwgt_mlp_load,
+    rwgt_mlp_checkpoint_info, rwgt_set_mixed_guard, rwgt_mixed_guard_count, rwgt_cancellation,
 )
 from ._abi import (  # noqa: F401
     Segment, make_segments, rwgt_batch_create, rwgt_batch_destroy, rwgt_batch_eval, rwgt_batch_get_schedule,

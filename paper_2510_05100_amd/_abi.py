@@ -132,6 +132,41 @@ SIGNATURES.update({
                                            ctypes.c_char_p, ctypes.c_int32, ctypes.c_char_p]),
 })
 
+class TrainCfg(ctypes.Structure):
+    """rwgt_train_cfg of include/rwgt.h."""
+    _fields_ = [("batch", ctypes.c_int64), ("epochs", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("lr_final", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+SIGNATURES.update({
+    "rwgt_mlp_get_adam": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
+                                          ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int64)]),
+    "rwgt_mlp_fit_grid": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "rwgt_mlp_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(TrainCfg),
+                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]),
+    "rwgt_mlp_get_progress": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 3),
+    "rwgt_train_order": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                         ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    "rwgt_mlp_calibrate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                           ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_double,
+                                           ctypes.POINTER(ctypes.c_double)]),
+    "rwgt_mlp_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
+    "rwgt_mlp_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "rwgt_mlp_checkpoint_info": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
+                                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "rwgt_mlp_checkpoint_error": (ctypes.c_char_p, []),
+})
+
+SIGNATURES.update({
+    "rwgt_set_mixed_guard": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    "rwgt_mixed_guard_count": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "rwgt_cancellation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.c_void_p]),
+})
+
 SIGNATURES["rwgt_xsec"] = (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                           ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -770,3 +805,119 @@ def rwgt_reweight_card(process, param_card, rwgt_card, cap=4096, name_len=64):
         return rwgt_reweight_card(process, param_card, rwgt_card, cap=n.value, name_len=name_len)
     out_names = [names.raw[i * name_len:(i + 1) * name_len].split(b"\0")[0].decode() for i in range(n.value)]
     return buf[:n.value], out_names, (fp.value.decode() or None)
+
+
+# ------------------------------------------------------- training on a grid
+def rwgt_mlp_get_adam(mlp):
+    """(first moments, second moments, Adam steps) packed as rwgt_mlp_get_params."""
+    n = rwgt_mlp_num_params(mlp)
+    first, second = np.zeros(n, dtype=np.float32), np.zeros(n, dtype=np.float32)
+    steps = ctypes.c_int64()
+    rc = load().rwgt_mlp_get_adam(mlp, _fptr(first), _fptr(second), ctypes.byref(steps))
+    if rc != 0:
+        _mraise(rc, mlp)
+    return first, second, steps.value
+
+
+def rwgt_mlp_fit_grid(mlp, momenta, card_params, y):
+    """momenta [nevt, npart, 4] f64, card_params [ncards, 3] f32, y [ncards, nevt] f32 (device)."""
+    rc = load().rwgt_mlp_fit_grid(mlp, _dp(momenta), momenta.shape[1], momenta.shape[0], _dp(card_params),
+                                  card_params.shape[0], _dp(y))
+    if rc != 0:
+        _mraise(rc, mlp)
+
+
+def rwgt_mlp_train(mlp, momenta, card_params, y, batch, epochs, lr, lr_final, seed, epoch_end):
+    """Train epochs [done, epoch_end) of the schedule; returns the mean loss per pair of each."""
+    cfg = TrainCfg(int(batch), int(epochs), float(lr), float(lr_final), int(seed))
+    done, _, _ = rwgt_mlp_get_progress(mlp)
+    losses = np.zeros(max(int(epoch_end) - done, 0), dtype=np.float32)
+    rc = load().rwgt_mlp_train(mlp, _dp(momenta), momenta.shape[1], momenta.shape[0], _dp(card_params),
+                               card_params.shape[0], _dp(y), ctypes.byref(cfg), int(epoch_end), _fptr(losses))
+    if rc != 0:
+        _mraise(rc, mlp)
+    return losses
+
+
+def rwgt_mlp_get_progress(mlp):
+    """(epochs done, schedule steps done, Adam steps taken)."""
+    vals = [ctypes.c_int64() for _ in range(3)]
+    rc = load().rwgt_mlp_get_progress(mlp, *[ctypes.byref(v) for v in vals])
+    if rc != 0:
+        _mraise(rc, mlp)
+    return tuple(v.value for v in vals)
+
+
+def rwgt_train_order(seed, epoch, n, pos0=0, count=None):
+    count = n - pos0 if count is None else count
+    out = np.zeros(count, dtype=np.int64)
+    rc = load().rwgt_train_order(int(seed), int(epoch), int(n), int(pos0), int(count),
+                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if rc != 0:
+        raise RwgtError(rc, "rwgt_train_order: bad arguments")
+    return out
+
+
+def rwgt_mlp_calibrate(mlp, momenta, card_params, y, coverage):
+    """(k, median |r|, 0.9 quantile of |r|, 0.999 quantile of |r|); sets the network's k."""
+    stats = np.zeros(4)
+    rc = load().rwgt_mlp_calibrate(mlp, _dp(momenta), momenta.shape[1], momenta.shape[0], _dp(card_params),
+                                   card_params.shape[0], _dp(y), float(coverage),
+                                   stats.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != 0:
+        _mraise(rc, mlp)
+    return tuple(float(v) for v in stats)
+
+
+def _ckraise(code):
+    raise RwgtError(code, (load().rwgt_mlp_checkpoint_error() or b"").decode())
+
+
+def rwgt_mlp_save(mlp, path):
+    rc = load().rwgt_mlp_save(mlp, os.fsencode(path))
+    if rc != 0:
+        _mraise(rc, mlp)
+
+
+def rwgt_mlp_load(path):
+    out = ctypes.c_void_p()
+    rc = load().rwgt_mlp_load(os.fsencode(path), ctypes.byref(out))
+    if rc != 0:
+        _ckraise(rc)
+    return out
+
+
+def rwgt_mlp_checkpoint_info(path):
+    """((n_in, width, depth, n_out, precision), epochs done, Adam steps); host only."""
+    shape = (ctypes.c_int32 * 5)()
+    epoch, steps = ctypes.c_int64(), ctypes.c_int64()
+    rc = load().rwgt_mlp_checkpoint_info(os.fsencode(path), shape, ctypes.byref(epoch), ctypes.byref(steps))
+    if rc != 0:
+        _ckraise(rc)
+    return tuple(shape), epoch.value, steps.value
+
+
+# ------------------------------------------------------ mixed-path guard
+def rwgt_set_mixed_guard(ctx, kappa_max):
+    rc = load().rwgt_set_mixed_guard(ctx, float(kappa_max))
+    if rc != 0:
+        _raise(rc, ctx)
+
+
+def rwgt_mixed_guard_count(ctx):
+    n = ctypes.c_int64()
+    rc = load().rwgt_mixed_guard_count(ctx, ctypes.byref(n))
+    if rc != 0:
+        _raise(rc, ctx)
+    return n.value
+
+
+def rwgt_cancellation(ctx, momenta, param_sets, kappa_out, me2_out=None):
+    """Mixed |M|^2 (optional, [nsets, nevt]) and kappa [nevt] per event, without re-evaluation."""
+    _check_device(momenta, "momenta")
+    _check_device(kappa_out, "kappa_out")
+    a, ptr = _host_params(param_sets)
+    rc = load().rwgt_cancellation(ctx, _ptr(momenta), momenta.shape[0], ptr, a.shape[0], _ptr(me2_out),
+                                  _ptr(kappa_out))
+    if rc != 0:
+        _raise(rc, ctx)

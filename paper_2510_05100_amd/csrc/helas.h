@@ -93,6 +93,13 @@ __host__ __device__ __forceinline__ void term_fence() {
   __builtin_amdgcn_sched_barrier(0);
 #endif
 }
+// Hooks of the mixed path's cancellation guard (me_kernel.h), called by the
+// generated amplitude code at the start of a helicity and after each
+// amplitude term (with the number of colour flows the term enters).  No-ops
+// for plain amplitude storage; the guard's storage overloads them.
+template <class J> __host__ __device__ __forceinline__ void note_reset(J&) {}
+template <class J, class R> __host__ __device__ __forceinline__ void note_amp(J&, const cx<R>&, int) {}
+
 template <class D> __host__ __device__ __forceinline__ D msq(const D* k) {
   return k[0] * k[0] - k[1] * k[1] - k[2] * k[2] - k[3] * k[3];
 }

@@ -21,8 +21,27 @@ hipError_t launch_ingest(int npart, const double* aos, double* soa, int64_t nevt
 hipError_t launch_me(int proc, int precision, const double* soa, int64_t nevt, const CardPair* cards, int ncards,
                      const double* w_in, double* w_out, double* me_out, hipStream_t s);
 
+// Default threshold of the mixed path's cancellation guard (0: off).
+constexpr double kGuardKappaDefault = 0.0;
+
+// Cancellation guard of the mixed path (me_kernel.h, launch_me_guarded).
+struct GuardArgs {
+  const int32_t* rows = nullptr;          // re-evaluation: the event of each row
+  const unsigned int* nrows = nullptr;    // re-evaluation: number of rows (device)
+  int32_t* flagged = nullptr;             // guard: events to re-evaluate (capacity nevt)
+  unsigned int* nflagged = nullptr;       // guard: their count (device)
+  double kmax = 0.0;                      // guard: kappa above this is flagged (< 0: flag nothing)
+  double* kappa = nullptr;                // guard (optional): kappa of each event
+};
+
+// Mixed-precision |M|^2 / w' (precision RWGT_MIXED_*) with the events whose
+// cancellation measure exceeds g.kmax re-evaluated in double precision.
+hipError_t launch_me_guarded(int proc, int precision, const double* soa, int64_t nevt, const CardPair* cards,
+                             int ncards, const double* w_in, double* w_out, double* me_out, const GuardArgs& g,
+                             hipStream_t s);
+
 // Reweighted cross sections and errors per card: out[k] = {sigma', dsigma', fallback flag};
-// part must hold nsets * nblocks * 3 doubles.
+// part must hold nsets * (3 * nblocks + 3) doubles (two-pass scratch).
 hipError_t launch_xsec(const double* w_in, const double* w_out, int64_t nevt, int nsets, double sigma, double dsigma,
                        double norm, double* part, int nblocks, double* out, hipStream_t s);
 
@@ -57,6 +76,9 @@ double process_flops(int proc);
 #define RWGT_DECLARE_PROCESS(NAME)                                                                        \
   hipError_t launch_me_##NAME(int precision, const double* soa, int64_t nevt, const CardPair* cards,     \
                               int ncards, const double* w_in, double* w_out, double* me_out, hipStream_t s); \
+  hipError_t launch_me_guarded_##NAME(int precision, const double* soa, int64_t nevt, const CardPair* cards, \
+                                      int ncards, const double* w_in, double* w_out, double* me_out,          \
+                                      const GuardArgs& g, hipStream_t s);                                     \
   void constants_##NAME(int* npart, int* ngood, int* ncol, int* ndiag);                                 \
   double flops_##NAME();
 RWGT_DECLARE_PROCESS(ee_mumu)

@@ -33,49 +33,86 @@ __global__ __launch_bounds__(256) void ingest_kernel(const double* __restrict__ 
 }
 
 // Reweighted cross sections (teaRex section): per card the sums
-// S1 = sum w', S2 = sum w'^2 and R = sum w'/w (terms with w = 0 count 0),
-// reduced in two deterministic passes, then
-//   sigma' = C S1,  dsigma' = dsigma R/N + sigma std(w'),  std = sqrt(S2/N - (S1/N)^2),
+// S1 = sum w' and R = sum w'/w (terms with w = 0 count 0), then, around the
+// mean m = S1/N, S2 = sum (w' - m)^2, each reduced in a fixed order (block
+// partials, then one lane per card), so results are deterministic:
+//   sigma' = C S1,  dsigma' = dsigma R/N + sigma std(w'),  std = sqrt(S2/N),
 // and, when dsigma' is infinite, NaN or not positive, dsigma' = dsigma max(sigma'/sigma, sigma/sigma').
+// The variance is taken about the mean (two passes) because for near-constant
+// w' (a pure alpha_s change) S2/N - m^2 cancels to noise of order 1e-16 m^2.
 constexpr int kXsecBlock = 256;
 
-__global__ __launch_bounds__(kXsecBlock) void xsec_partial(const double* __restrict__ w_in,
-                                                           const double* __restrict__ w_out, int64_t nevt,
-                                                           double* __restrict__ part) {
-  __shared__ double sh[3][kXsecBlock];
-  const int k = blockIdx.y;
-  const double* wo = w_out + int64_t(k) * nevt;
-  double s1 = 0.0, s2 = 0.0, r = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nevt; i += int64_t(gridDim.x) * blockDim.x) {
-    const double x = wo[i];
-    s1 += x;
-    s2 += x * x;
-    r += w_in[i] != 0.0 ? x / w_in[i] : 0.0;
-  }
-  sh[0][threadIdx.x] = s1;
-  sh[1][threadIdx.x] = s2;
-  sh[2][threadIdx.x] = r;
+template <int Q>
+__device__ void block_sum(double (&sh)[Q][kXsecBlock], const double (&v)[Q], double* __restrict__ dst) {
+#pragma unroll
+  for (int q = 0; q < Q; ++q) sh[q][threadIdx.x] = v[q];
   __syncthreads();
   for (int w = kXsecBlock / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w)
-      for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x < 3) part[(int64_t(k) * gridDim.x + blockIdx.x) * 3 + threadIdx.x] = sh[threadIdx.x][0];
+  if (threadIdx.x < Q) dst[threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ __launch_bounds__(64) void xsec_final(const double* __restrict__ part, int nblocks, int64_t nevt,
-                                                 double sigma, double dsigma, double norm, double* __restrict__ out) {
-  const int k = blockIdx.x;
-  if (threadIdx.x != 0) return;
-  double s[3] = {0.0, 0.0, 0.0};
-  for (int b = 0; b < nblocks; ++b)
-    for (int q = 0; q < 3; ++q) s[q] += part[(int64_t(k) * nblocks + b) * 3 + q];
+// Pass 1: block partials of S1 and R -> part[k][block][2].
+__global__ __launch_bounds__(kXsecBlock) void xsec_pass1(const double* __restrict__ w_in,
+                                                         const double* __restrict__ w_out, int64_t nevt,
+                                                         double* __restrict__ part) {
+  __shared__ double sh[2][kXsecBlock];
+  const int k = blockIdx.y;
+  const double* wo = w_out + int64_t(k) * nevt;
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nevt; i += int64_t(gridDim.x) * blockDim.x) {
+    const double x = wo[i];
+    v[0] += x;
+    v[1] += w_in[i] != 0.0 ? x / w_in[i] : 0.0;
+  }
+  block_sum<2>(sh, v, part + (int64_t(k) * gridDim.x + blockIdx.x) * 2);
+}
+
+// One lane per card: S1, R from pass 1 -> sums[k] = {S1, R, S1/N}.
+__global__ __launch_bounds__(64) void xsec_mean(const double* __restrict__ part, int nblocks, int64_t nevt,
+                                                int nsets, double* __restrict__ sums) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nsets) return;
+  double s1 = 0.0, r = 0.0;
+  for (int b = 0; b < nblocks; ++b) {
+    s1 += part[(int64_t(k) * nblocks + b) * 2];
+    r += part[(int64_t(k) * nblocks + b) * 2 + 1];
+  }
+  sums[k * 3 + 0] = s1;
+  sums[k * 3 + 1] = r;
+  sums[k * 3 + 2] = s1 / double(nevt);
+}
+
+// Pass 2: block partials of sum (w' - m)^2 -> part2[k][block].
+__global__ __launch_bounds__(kXsecBlock) void xsec_pass2(const double* __restrict__ w_out, int64_t nevt,
+                                                         const double* __restrict__ sums,
+                                                         double* __restrict__ part2) {
+  __shared__ double sh[1][kXsecBlock];
+  const int k = blockIdx.y;
+  const double* wo = w_out + int64_t(k) * nevt;
+  const double m = sums[k * 3 + 2];
+  double v[1] = {0.0};
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nevt; i += int64_t(gridDim.x) * blockDim.x) {
+    const double d = wo[i] - m;
+    v[0] += d * d;
+  }
+  block_sum<1>(sh, v, part2 + int64_t(k) * gridDim.x + blockIdx.x);
+}
+
+__global__ __launch_bounds__(64) void xsec_final(const double* __restrict__ sums, const double* __restrict__ part2,
+                                                 int nblocks, int64_t nevt, int nsets, double sigma, double dsigma,
+                                                 double norm, double* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nsets) return;
+  double s2 = 0.0;
+  for (int b = 0; b < nblocks; ++b) s2 += part2[int64_t(k) * nblocks + b];
   const double n = double(nevt);
-  const double xs = norm * s[0];
-  const double mean = s[0] / n;
-  const double var = s[1] / n - mean * mean;
-  double err = dsigma * (s[2] / n) + sigma * sqrt(var > 0.0 ? var : 0.0);
+  const double xs = norm * sums[k * 3 + 0];
+  double err = dsigma * (sums[k * 3 + 1] / n) + sigma * sqrt(s2 / n);
   double fallback = 0.0;
   if (!(err > 0.0) || isinf(err)) {
     const double a = xs / sigma, b = sigma / xs;
@@ -89,8 +126,15 @@ __global__ __launch_bounds__(64) void xsec_final(const double* __restrict__ part
 
 hipError_t launch_xsec(const double* w_in, const double* w_out, int64_t nevt, int nsets, double sigma, double dsigma,
                        double norm, double* part, int nblocks, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(xsec_partial, dim3(nblocks, nsets), dim3(kXsecBlock), 0, s, w_in, w_out, nevt, part);
-  hipLaunchKernelGGL(xsec_final, dim3(nsets), dim3(64), 0, s, part, nblocks, nevt, sigma, dsigma, norm, out);
+  // part: [nsets][nblocks][2] pass-1 partials, then [nsets][3] sums, then [nsets][nblocks] pass-2 partials.
+  double* sums = part + size_t(nsets) * nblocks * 2;
+  double* part2 = sums + size_t(nsets) * 3;
+  const int lanes = (nsets + 63) / 64;
+  hipLaunchKernelGGL(xsec_pass1, dim3(nblocks, nsets), dim3(kXsecBlock), 0, s, w_in, w_out, nevt, part);
+  hipLaunchKernelGGL(xsec_mean, dim3(lanes), dim3(64), 0, s, part, nblocks, nevt, nsets, sums);
+  hipLaunchKernelGGL(xsec_pass2, dim3(nblocks, nsets), dim3(kXsecBlock), 0, s, w_out, nevt, sums, part2);
+  hipLaunchKernelGGL(xsec_final, dim3(lanes), dim3(64), 0, s, sums, part2, nblocks, nevt, nsets, sigma, dsigma, norm,
+                     out);
   return hipGetLastError();
 }
 
@@ -244,6 +288,18 @@ hipError_t launch_me(int proc, int precision, const double* soa, int64_t nevt, c
     case kProcEeMumu: return launch_me_ee_mumu(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, s);
     case kProcUuEeg: return launch_me_uu_eeg(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, s);
     case kProcGgTtgg: return launch_me_gg_ttgg(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_me_guarded(int proc, int precision, const double* soa, int64_t nevt, const CardPair* cards,
+                             int ncards, const double* w_in, double* w_out, double* me_out, const GuardArgs& g,
+                             hipStream_t s) {
+  switch (proc) {
+    case kProcEeMumu: return launch_me_guarded_ee_mumu(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, g, s);
+    case kProcUuEeg: return launch_me_guarded_uu_eeg(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, g, s);
+    case kProcGgTtgg:
+      return launch_me_guarded_gg_ttgg(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, g, s);
   }
   return hipErrorInvalidValue;
 }

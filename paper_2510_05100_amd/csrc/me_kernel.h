@@ -58,6 +58,29 @@ struct LdsJamp {
 template <class PROC, class R>
 constexpr bool jamp_in_lds() { return PROC::NCOL >= 8 && sizeof(R) == 8; }
 
+// Colour-flow amplitudes of the guarded mixed path: the flows and the
+// incoherent sum of the amplitude terms, sum_t m_t |amp_t|^2 (m_t: the number
+// of flows term t enters).  Its ratio to the coherent sum_c |J_c|^2 measures
+// how much the terms cancel in the flows, which is what amplifies their
+// single-precision rounding.
+template <class R, int NCOL>
+struct GuardJamp {
+  cx<R> j[NCOL];
+  R inco;
+  __device__ __forceinline__ cx<R>& operator[](int c) { return j[c]; }
+  __device__ __forceinline__ const cx<R>& operator[](int c) const { return j[c]; }
+};
+template <class R, int NCOL>
+__device__ __forceinline__ void note_reset(GuardJamp<R, NCOL>& g) { g.inco = R(0); }
+template <class R, int NCOL>
+__device__ __forceinline__ void note_amp(GuardJamp<R, NCOL>& g, const cx<R>& a, int m) {
+  g.inco += R(m) * (a.re * a.re + a.im * a.im);
+}
+template <class R, int NCOL>
+__device__ __forceinline__ cx<R> (&flows(GuardJamp<R, NCOL>& g))[NCOL] { return g.j; }
+template <class R, int NCOL>
+__device__ __forceinline__ cx<R> (&flows(cx<R> (&j)[NCOL]))[NCOL] { return j; }
+
 // |M|^2 of one event under one card with the colour flows in registers and
 // the colour sum on the VALU (the form of few-flow processes).
 template <class PROC, class R>
@@ -93,31 +116,40 @@ constexpr int me_block() { return hel_split<PROC>() > 1 ? 64 * hel_split<PROC>()
 
 // One event per lane (of each wave of the helicity split).  R: amplitude
 // precision.  CT: 16-bit type of the matrix-core colour sum (_Float16 or
-// __bf16), or void for the VALU form.
-template <class PROC, class R, class CT>
+// __bf16), or void for the VALU form.  GUARD (float amplitudes): also the
+// cancellation measure kappa of each event, the largest over its cards of
+// sum_hel sum_t m_t |amp_t|^2 / sum_hel sum_c |J_c|^2; events with kappa above
+// g.kmax are appended to g.flagged.  INDEXED: row r of the launch is event
+// g.rows[r] of the nevt-event arrays, for r < *g.nrows (the re-evaluation of
+// flagged events in double precision).
+template <class PROC, class R, class CT, bool GUARD = false, bool INDEXED = false>
 __global__ __launch_bounds__(kMeBlock) void me_kernel(const double* __restrict__ soa, int64_t nevt,
                                                       const CardPair* __restrict__ cards, int ncards,
                                                       const double* __restrict__ w_in, double* __restrict__ w_out,
-                                                      double* __restrict__ me_out) {
+                                                      double* __restrict__ me_out, const GuardArgs g) {
   constexpr bool kMfma = !std::is_void<CT>::value;
   constexpr int HS = hel_split<PROC>(), B = me_block<PROC>();
   constexpr int EPB = HS > 1 ? 64 : B;                        // events per workgroup
   constexpr int NH = PROC::NGOOD / HS;                        // helicities per wave
   static_assert(PROC::NGOOD % HS == 0 && EPB % 64 == 0, "helicity split");
+  static_assert(!GUARD || sizeof(R) == 4, "the guard watches single-precision amplitudes");
   // which helicities: wave-uniform, kept in a scalar register so that the
   // helicity of each loop trip stays uniform too
   const int half = HS > 1 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)) : 0;
-  const int64_t i = int64_t(blockIdx.x) * EPB + (HS > 1 ? int(threadIdx.x & 63) : int(threadIdx.x));
+  const int64_t r = int64_t(blockIdx.x) * EPB + (HS > 1 ? int(threadIdx.x & 63) : int(threadIdx.x));
+  const int64_t nrows = INDEXED ? int64_t(*g.nrows) : nevt;
   // whole waves (split: whole workgroups) past the end leave together; inside
   // the last wave the lanes past the end recompute the last event (the
   // matrix-core colour sum needs every lane) and write nothing
   if constexpr (HS > 1) {
-    if (int64_t(blockIdx.x) * EPB >= nevt) return;
+    if (int64_t(blockIdx.x) * EPB >= nrows) return;
   } else {
-    if (int64_t(blockIdx.x) * B + (threadIdx.x & ~63) >= nevt) return;
+    if (int64_t(blockIdx.x) * B + (threadIdx.x & ~63) >= nrows) return;
   }
-  const bool valid = i < nevt;
-  const int64_t ie = valid ? i : nevt - 1;
+  const bool valid = r < nrows;
+  const int64_t rr = valid ? r : nrows - 1;
+  const int64_t i = INDEXED ? int64_t(g.rows[rr]) : rr;      // the event of this lane
+  const int64_t ie = i;
   double P[PROC::NPART][4];
 #pragma unroll
   for (int a = 0; a < PROC::NPART; ++a)
@@ -127,13 +159,16 @@ __global__ __launch_bounds__(kMeBlock) void me_kernel(const double* __restrict__
   [[maybe_unused]] __shared__ cx<R> lds_jamp[jamp_in_lds<PROC, R>() ? PROC::NCOL * B : 1];
   [[maybe_unused]] __shared__ typename ColourLdsOf<CT>::type lds_colour[kMfma ? B / 64 : 1];
   [[maybe_unused]] __shared__ double lds_half[HS > 1 ? 64 * (HS - 1) : 1];   // the other waves' partial sums
+  [[maybe_unused]] __shared__ double lds_guard[GUARD && HS > 1 ? 2 * 64 * (HS - 1) : 1];
   [[maybe_unused]] std::conditional_t<kMfma, ColourMfma<PROC::NCOL, std::conditional_t<kMfma, CT, _Float16>>, char> cm;
   if constexpr (kMfma) cm.init(PROC::cnum(), lds_colour[threadIdx.x >> 6]);
 
   double norm = 0.0;
+  [[maybe_unused]] double kappa = 0.0;
   for (int k = 0; k < ncards; ++k) {
     const Card<R>& cd = pick<R>(cards[k]);
     double me = 0.0;
+    [[maybe_unused]] double inco = 0.0, coh = 0.0;
     for (int ih = half * NH; ih < (half + 1) * NH; ++ih) {
       // The generated code reads the momenta through opq() at every use, so
       // none of the helicity-independent algebra is hoisted out of this loop.
@@ -142,21 +177,45 @@ __global__ __launch_bounds__(kMeBlock) void me_kernel(const double* __restrict__
         PROC::template jamps_grouped<R>(P, PROC::good(ih), cd, jamp);
         me += double(PROC::template colour_sum<R>(jamp));
       } else {
-        cx<R> jamp[PROC::NCOL];
+        std::conditional_t<GUARD, GuardJamp<R, PROC::NCOL>, cx<R>[PROC::NCOL]> jamp;
         PROC::template jamps<R>(P, PROC::good(ih), cd, jamp);
         if constexpr (kMfma) {
-          me += cm.sum(jamp, lds_colour[threadIdx.x >> 6]) * (1.0 / PROC::CDEN);
+          me += cm.sum(flows(jamp), lds_colour[threadIdx.x >> 6]) * (1.0 / PROC::CDEN);
         } else {
           me += double(PROC::template colour_sum<R>(jamp));
+        }
+        if constexpr (GUARD) {
+          R c2 = R(0);
+#pragma unroll
+          for (int c = 0; c < PROC::NCOL; ++c) c2 += jamp[c].re * jamp[c].re + jamp[c].im * jamp[c].im;
+          coh += double(c2);
+          inco += double(jamp.inco);
         }
       }
     }
     if constexpr (HS > 1) {                      // the waves' partial sums in order, on the first wave
       if (half > 0) lds_half[(half - 1) * 64 + (threadIdx.x & 63)] = me;
+      if constexpr (GUARD) {
+        if (half > 0) {
+          lds_guard[(half - 1) * 128 + (threadIdx.x & 63)] = inco;
+          lds_guard[(half - 1) * 128 + 64 + (threadIdx.x & 63)] = coh;
+        }
+      }
       __syncthreads();
       if (half == 0)
         for (int w = 1; w < HS; ++w) me += lds_half[(w - 1) * 64 + threadIdx.x];
+      if constexpr (GUARD) {
+        if (half == 0)
+          for (int w = 1; w < HS; ++w) {
+            inco += lds_guard[(w - 1) * 128 + threadIdx.x];
+            coh += lds_guard[(w - 1) * 128 + 64 + threadIdx.x];
+          }
+      }
       __syncthreads();                           // before the next card's partial sums
+    }
+    if constexpr (GUARD) {
+      const double kk = coh > 0.0 ? inco / coh : (inco > 0.0 ? __builtin_inf() : 0.0);
+      kappa = kk > kappa || !(kk == kk) ? kk : kappa;
     }
     me *= PROC::AVERAGE;
     if (!valid || half != 0) continue;
@@ -169,16 +228,48 @@ __global__ __launch_bounds__(kMeBlock) void me_kernel(const double* __restrict__
       }
     }
   }
+  if constexpr (GUARD) {
+    if (valid && half == 0) {
+      if (g.kappa) g.kappa[i] = kappa;
+      if (g.flagged && !(kappa <= g.kmax)) g.flagged[atomicAdd(g.nflagged, 1u)] = int32_t(i);
+    }
+  }
 }
 
-template <class PROC, class R, class CT>
+static __global__ void zero_count_kernel(unsigned int* c) { *c = 0u; }
+
+template <class PROC, class R, class CT, bool GUARD = false, bool INDEXED = false>
 inline hipError_t launch_me_t(const double* soa, int64_t nevt, const CardPair* cards, int ncards,
-                              const double* w_in, double* w_out, double* me_out, hipStream_t s) {
+                              const double* w_in, double* w_out, double* me_out, hipStream_t s,
+                              const GuardArgs& g = GuardArgs{}) {
   constexpr int B = me_block<PROC>(), EPB = hel_split<PROC>() > 1 ? 64 : B;
   const int64_t blocks = (nevt + EPB - 1) / EPB;
-  hipLaunchKernelGGL((me_kernel<PROC, R, CT>), dim3(unsigned(blocks)), dim3(B), 0, s, soa, nevt, cards, ncards,
-                     w_in, w_out, me_out);
+  hipLaunchKernelGGL((me_kernel<PROC, R, CT, GUARD, INDEXED>), dim3(unsigned(blocks)), dim3(B), 0, s, soa, nevt,
+                     cards, ncards, w_in, w_out, me_out, g);
   return hipGetLastError();
+}
+
+// Mixed precision with the cancellation guard: the float-amplitude kernel
+// flags the events whose kappa exceeds g.kmax (g.kmax < 0: none, kappa only),
+// then the double-precision kernel re-evaluates the flagged events in place
+// (one workgroup per event group of the whole range; groups past the flagged
+// count leave at once).
+template <class PROC>
+inline hipError_t launch_me_guarded_t(int precision, const double* soa, int64_t nevt, const CardPair* cards,
+                                      int ncards, const double* w_in, double* w_out, double* me_out, GuardArgs g,
+                                      hipStream_t s) {
+  constexpr bool many = PROC::NCOL >= 8;
+  if (g.nflagged) hipLaunchKernelGGL(zero_count_kernel, dim3(1), dim3(1), 0, s, g.nflagged);
+  hipError_t e = precision == kPrecMixedBF16
+      ? launch_me_t<PROC, float, std::conditional_t<many, __bf16, void>, true>(soa, nevt, cards, ncards, w_in, w_out,
+                                                                               me_out, s, g)
+      : launch_me_t<PROC, float, std::conditional_t<many, _Float16, void>, true>(soa, nevt, cards, ncards, w_in,
+                                                                                 w_out, me_out, s, g);
+  if (e != hipSuccess || g.kmax < 0.0 || !g.flagged || !g.nflagged) return e;
+  GuardArgs gi;
+  gi.rows = g.flagged;
+  gi.nrows = g.nflagged;
+  return launch_me_t<PROC, double, void, false, true>(soa, nevt, cards, ncards, w_in, w_out, me_out, s, gi);
 }
 
 // Precision dispatch: FP64; or float amplitudes with the colour sum on the

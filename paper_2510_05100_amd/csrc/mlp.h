@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "shuffle.h"
+
 namespace rwgt {
 
 // Operand type of one layer: BF16 on the matrix cores, or FP32 on the VALU.
@@ -93,6 +95,11 @@ hipError_t mlp_features(const FeatureMap& fm, const double* mom, const int32_t* 
                         const float* cpar, const float* mean, const float* istd, float* x, int64_t n, int64_t rows,
                         int ld, hipStream_t s);
 hipError_t mlp_heads(const float* z, int ld, int64_t n, float ym, float ys, float* out, int ld_out, hipStream_t s);
+// Rows [pos0, pos0 + n) of the order sh over a card-major (event, card) grid
+// of nevt events: event and card index per row, and y[pair] into yb when y
+// is non-NULL (shuffle.h).
+hipError_t mlp_gather_pairs(const Shuffle& sh, int64_t pos0, int64_t n, int64_t nevt, const float* y, int32_t* ev,
+                            int32_t* cd, float* yb, hipStream_t s);
 hipError_t mlp_log_ratio(const double* w_new, const double* w_old, float* y, int64_t n, hipStream_t s);
 hipError_t mlp_gate(const float* z, int ld, int64_t n, float ym, float ys, float k_cal, float threshold,
                     const double* w_in, double* w_out, int32_t* list, unsigned int* count, hipStream_t s);

@@ -32,6 +32,7 @@
 #include <cstdint>
 
 #include "mlp.h"
+#include "shuffle.h"
 
 namespace rwgt {
 
@@ -540,6 +541,20 @@ __global__ __launch_bounds__(256) void gate_k(const float* __restrict__ z, int l
   }
 }
 
+// Rows [pos0, pos0 + n) of an epoch's order over the pairs of a card-major
+// grid (pair j: event j % nevt, card j / nevt): each row's event and card
+// index and, when y is given, its target y[j].  s.n = 0: pairs in order.
+__global__ __launch_bounds__(256) void gather_pairs_k(const Shuffle s, int64_t pos0, int64_t n, int64_t nevt,
+                                                      const float* __restrict__ y, int32_t* __restrict__ ev,
+                                                      int32_t* __restrict__ cd, float* __restrict__ yb) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int64_t j = shuffled(s, pos0 + r);
+  ev[r] = int32_t(j % nevt);
+  cd[r] = int32_t(j / nevt);
+  if (y) yb[r] = y[j];
+}
+
 // Training targets y = log(w_new / w_old) (w_old = 0: y = 0).
 __global__ __launch_bounds__(256) void log_ratio_k(const double* __restrict__ w_new, const double* __restrict__ w_old,
                                                    float* __restrict__ y, int64_t n) {
@@ -940,6 +955,13 @@ hipError_t mlp_features(const FeatureMap& fm, const double* mom, const int32_t* 
 
 hipError_t mlp_heads(const float* z, int ld, int64_t n, float ym, float ys, float* out, int ld_out, hipStream_t s) {
   hipLaunchKernelGGL(heads_k, dim3(blocks_for(n)), dim3(256), 0, s, z, ld, n, ym, ys, out, ld_out);
+  return hipGetLastError();
+}
+
+hipError_t mlp_gather_pairs(const Shuffle& sh, int64_t pos0, int64_t n, int64_t nevt, const float* y, int32_t* ev,
+                            int32_t* cd, float* yb, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_pairs_k, dim3(blocks_for(n)), dim3(256), 0, s, sh, pos0, n, nevt, y, ev, cd, yb);
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -214,6 +215,7 @@ int rwgt_mlp::infer(const double* mom, const int32_t* ev, const int32_t* cidx, c
 rwgt_mlp::~rwgt_mlp() {
   if (stream) hipStreamSynchronize(stream); else hipDeviceSynchronize();
   for (void* p : work) hipFree(p);
+  for (void* p : twork) hipFree(p);
   for (void* p : params) hipFree(p);
 }
 
@@ -338,13 +340,18 @@ int rwgt_mlp_num_params(const rwgt_mlp* m, int64_t* n) {
   return RWGT_OK;
 }
 
-// Parameters packed layer by layer as W[out_used][in_used] then b[out_used].
-static int pack_params(rwgt_mlp* m, bool to_host, float* host, bool grads) {
+}  // extern "C"
+
+// Parameters (or gradients, or Adam moments: rwgt_mlp::kCopy*) packed layer
+// by layer as W[out_used][in_used] then b[out_used]; padding stays as it is.
+int pack_params(rwgt_mlp* m, bool to_host, float* host, int which) {
   hipError_t e = hipStreamSynchronize(m->stream);
   size_t off = 0;
   for (auto& ly : m->layers) {
-    float* w = grads ? ly.gw : ly.w;
-    float* b = grads ? ly.gb : ly.b;
+    float* const ws[4] = {ly.w, ly.gw, ly.mw, ly.vw};
+    float* const bs[4] = {ly.b, ly.gb, ly.mb, ly.vb};
+    float* w = ws[which];
+    float* b = bs[which];
     std::vector<float> full(size_t(ly.in) * ly.out);
     if (e == hipSuccess) e = hipMemcpy(full.data(), w, full.size() * 4, hipMemcpyDeviceToHost);
     if (to_host) {
@@ -362,15 +369,28 @@ static int pack_params(rwgt_mlp* m, bool to_host, float* host, bool grads) {
     off += ly.out_used;
   }
   if (e != hipSuccess) return m->hip_fail(e, "parameter copy");
-  if (!to_host && !grads) return m->refresh_copies();
+  if (!to_host && which == rwgt_mlp::kCopyParams) return m->refresh_copies();
   return RWGT_OK;
 }
 
-int rwgt_mlp_get_params(rwgt_mlp* m, float* host) { return (m && host) ? pack_params(m, true, host, false) : RWGT_EINVAL; }
-int rwgt_mlp_set_params(rwgt_mlp* m, const float* host) {
-  return (m && host) ? pack_params(m, false, const_cast<float*>(host), false) : RWGT_EINVAL;
+extern "C" {
+
+int rwgt_mlp_get_params(rwgt_mlp* m, float* host) {
+  return (m && host) ? pack_params(m, true, host, rwgt_mlp::kCopyParams) : RWGT_EINVAL;
 }
-int rwgt_mlp_get_grads(rwgt_mlp* m, float* host) { return (m && host) ? pack_params(m, true, host, true) : RWGT_EINVAL; }
+int rwgt_mlp_set_params(rwgt_mlp* m, const float* host) {
+  return (m && host) ? pack_params(m, false, const_cast<float*>(host), rwgt_mlp::kCopyParams) : RWGT_EINVAL;
+}
+int rwgt_mlp_get_grads(rwgt_mlp* m, float* host) {
+  return (m && host) ? pack_params(m, true, host, rwgt_mlp::kCopyGrads) : RWGT_EINVAL;
+}
+int rwgt_mlp_get_adam(rwgt_mlp* m, float* first, float* second, int64_t* steps) {
+  if (!m || !first || !second || !steps) return RWGT_EINVAL;
+  int rc = pack_params(m, true, first, rwgt_mlp::kCopyFirst);
+  if (rc == RWGT_OK) rc = pack_params(m, true, second, rwgt_mlp::kCopySecond);
+  *steps = m->t;
+  return rc;
+}
 
 int rwgt_mlp_set_normalisation(rwgt_mlp* m, const float* mean, const float* stdv) {
   if (!m || !mean || !stdv) return RWGT_EINVAL;
@@ -437,9 +457,11 @@ int rwgt_mlp_set_calibration(rwgt_mlp* m, float k) {
   return RWGT_OK;
 }
 
+}  // extern "C"
+
 // The feature map of a network that has none yet: the raw map of npart
 // particles.  Errors when the map and the network's width disagree.
-static int resolve_map(rwgt_mlp* m, int32_t npart) {
+int resolve_map(rwgt_mlp* m, int32_t npart) {
   if (m->fm.npart == 0) {
     if (m->n_in != rwgt::feature_count(RWGT_FEAT_RAW, npart))
       return m->fail(RWGT_EINVAL, "feature count differs from the input width");
@@ -449,6 +471,8 @@ static int resolve_map(rwgt_mlp* m, int32_t npart) {
   if (npart != m->fm.npart) return m->fail(RWGT_EINVAL, "particle count differs from the feature map");
   return RWGT_OK;
 }
+
+extern "C" {
 
 int rwgt_mlp_features(rwgt_mlp* m, const double* momenta, int32_t npart, const int32_t* event_index,
                       const int32_t* card_index, const float* card_params, int32_t nparam, int64_t n, void* x_out) {
@@ -531,6 +555,41 @@ int rwgt_mlp_fit_target_scale(rwgt_mlp* m, const float* y, int64_t n) {
   int rc = column_stats(m, n, 1, 1, fill, mean, stdv);
   if (rc != RWGT_OK) return rc;
   return rwgt_mlp_set_target_scale(m, mean[0], stdv[0]);
+}
+
+int rwgt_mlp_fit_grid(rwgt_mlp* m, const double* momenta, int32_t npart, int64_t nevt, const float* card_params,
+                      int32_t ncards, const float* y) {
+  if (!m || !momenta || !card_params || !y || nevt < 1 || ncards < 1) return RWGT_EINVAL;
+  const int64_t total = nevt * ncards;
+  if (nevt > INT32_MAX || total > (int64_t(1) << 40)) return m->fail(RWGT_EINVAL, "grid too large");
+  int rc = resolve_map(m, npart);
+  if (rc != RWGT_OK) return rc;
+  const std::vector<float> zeros(rwgt::kMlpMaxIn, 0.0f), ones(rwgt::kMlpMaxIn, 1.0f);
+  hipError_t e = hipMemcpy(m->mean, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->stdv, ones.data(), ones.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->istd, ones.data(), ones.size() * 4, hipMemcpyHostToDevice);
+  int32_t* idx = nullptr;
+  const int64_t chunk = int64_t(1) << 18;
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&idx), size_t(2 * chunk) * 4);
+  if (e != hipSuccess) {
+    if (idx) (void)hipFree(idx);
+    return m->hip_fail(e, "normalisation");
+  }
+  const int ld = m->layers[0].in;
+  const rwgt::Shuffle in_order;                          // n = 0: pairs in order
+  auto fill = [&](int64_t a, int64_t b, float* x) {
+    hipError_t r = rwgt::mlp_gather_pairs(in_order, a, b - a, nevt, nullptr, idx, idx + chunk, nullptr, m->stream);
+    if (r == hipSuccess)
+      r = rwgt::mlp_features(m->fm, momenta, idx, idx + chunk, card_params, m->mean, m->istd, x, b - a, b - a, ld,
+                             m->stream);
+    return r;
+  };
+  std::vector<float> mean, stdv;
+  rc = column_stats(m, total, ld, m->n_in, fill, mean, stdv);
+  (void)hipFree(idx);
+  if (rc == RWGT_OK) rc = rwgt_mlp_set_normalisation(m, mean.data(), stdv.data());
+  if (rc == RWGT_OK) rc = rwgt_mlp_fit_target_scale(m, y, total);
+  return rc;
 }
 
 int rwgt_mlp_forward(rwgt_mlp* m, const void* x, int64_t n, float* heads_out) {

@@ -10,6 +10,7 @@
 #include "mlp.h"
 
 struct rwgt_mlp {
+  enum { kCopyParams = 0, kCopyGrads = 1, kCopyFirst = 2, kCopySecond = 3 };   // pack_params selections
   struct Layer {
     int mode = 0;                                         // operand type (rwgt::kMlpBF16 / kMlpFP32)
     bool split = false;                                   // FP32 forward product as split BF16 (kMlpSplit)
@@ -44,6 +45,22 @@ struct rwgt_mlp {
   int64_t adam_total = 0;
   int64_t kpart_elems = 0;
   std::vector<void*> work, params;
+  // training schedule and progress (rwgt_mlp_train; saved in checkpoints)
+  struct Schedule {
+    int64_t batch = 0;
+    int32_t epochs = 0;
+    float lr = 0.0f, lr_final = 0.0f;
+    uint64_t seed = 0;
+  } sched;
+  bool has_sched = false;
+  int64_t epoch = 0;                                      // epochs completed
+  int64_t step = 0;                                       // steps of the schedule taken
+  // training-batch workspace (rwgt_mlp_train)
+  int64_t tcap = 0;
+  int32_t *tr_ev = nullptr, *tr_cd = nullptr;
+  float *tr_y = nullptr, *tr_x = nullptr, *tr_loss = nullptr;
+  int64_t tr_loss_cap = 0;
+  std::vector<void*> twork;
   std::string err;
 
   int fail(int code, const std::string& msg) { err = msg; return code; }
@@ -62,5 +79,19 @@ struct rwgt_mlp {
   int forward(const void* x, int64_t rows);
   int backward(const float* y, int64_t n_valid, int64_t rows);
   int update(float lr);
+  int ensure_train(int64_t batch, int64_t probes);
+  // heads (mu_y, s_y) [n][2] of rows (ev, cd), fused kernel or layer by layer
+  int predict_rows(const double* mom, const int32_t* ev, const int32_t* cd, const float* cpar, int64_t n,
+                   float* heads);
   ~rwgt_mlp();
 };
+
+// Host <-> device copy of the parameters, gradients or Adam moments (which:
+// rwgt_mlp::kCopy*) packed layer by layer as W[out_used][in_used], b[out_used];
+// waits for the network's stream.  Setting parameters refreshes the operand
+// copies.
+int pack_params(rwgt_mlp* m, bool to_host, float* host, int which);
+// The feature map of a network that has none yet becomes the raw map of
+// npart particles; errors when the map and the network's width or npart
+// disagree.
+int resolve_map(rwgt_mlp* m, int32_t npart);

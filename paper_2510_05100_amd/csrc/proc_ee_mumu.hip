@@ -12,6 +12,12 @@ hipError_t launch_me_ee_mumu(int precision, const double* soa, int64_t nevt, con
   return launch_me_prec<Proc_ee_mumu>(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, s);
 }
 
+hipError_t launch_me_guarded_ee_mumu(int precision, const double* soa, int64_t nevt, const CardPair* cards,
+                                    int ncards, const double* w_in, double* w_out, double* me_out,
+                                    const GuardArgs& g, hipStream_t s) {
+  return launch_me_guarded_t<Proc_ee_mumu>(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, g, s);
+}
+
 void constants_ee_mumu(int* npart, int* ngood, int* ncol, int* ndiag) {
   *npart = gen_ee_mumu::NPART;
   *ngood = gen_ee_mumu::NGOOD;

@@ -12,6 +12,12 @@ hipError_t launch_me_gg_ttgg(int precision, const double* soa, int64_t nevt, con
   return launch_me_prec<Proc_gg_ttgg>(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, s);
 }
 
+hipError_t launch_me_guarded_gg_ttgg(int precision, const double* soa, int64_t nevt, const CardPair* cards,
+                                    int ncards, const double* w_in, double* w_out, double* me_out,
+                                    const GuardArgs& g, hipStream_t s) {
+  return launch_me_guarded_t<Proc_gg_ttgg>(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, g, s);
+}
+
 void constants_gg_ttgg(int* npart, int* ngood, int* ncol, int* ndiag) {
   *npart = gen_gg_ttgg::NPART;
   *ngood = gen_gg_ttgg::NGOOD;

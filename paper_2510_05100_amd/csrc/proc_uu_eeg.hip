@@ -12,6 +12,12 @@ hipError_t launch_me_uu_eeg(int precision, const double* soa, int64_t nevt, cons
   return launch_me_prec<Proc_uu_eeg>(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, s);
 }
 
+hipError_t launch_me_guarded_uu_eeg(int precision, const double* soa, int64_t nevt, const CardPair* cards,
+                                    int ncards, const double* w_in, double* w_out, double* me_out,
+                                    const GuardArgs& g, hipStream_t s) {
+  return launch_me_guarded_t<Proc_uu_eeg>(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, g, s);
+}
+
 void constants_uu_eeg(int* npart, int* ngood, int* ncol, int* ndiag) {
   *npart = gen_uu_eeg::NPART;
   *ngood = gen_uu_eeg::NGOOD;

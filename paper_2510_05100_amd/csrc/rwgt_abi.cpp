@@ -178,6 +178,13 @@ struct rwgt_ctx {
   // per-event strong coupling: alpha_s of each card
   double* as_cards = nullptr;
   int as_cards_cap = 0;
+  // cancellation guard of the mixed path: events whose kappa exceeds
+  // guard_kmax are re-evaluated in double precision (guard_kmax <= 0: off)
+  double guard_kmax = rwgt::kGuardKappaDefault;
+  int32_t* guard_list = nullptr;
+  unsigned int* guard_count = nullptr;
+  int64_t guard_cap = 0;
+  bool guard_ran = false;                  // the last evaluation ran the guard
   // non-finite outputs of the last evaluation: per-block counts on the device
   unsigned long long* nf_part = nullptr;
   unsigned long long* nf_host = nullptr;   // pinned
@@ -202,7 +209,8 @@ struct rwgt_ctx {
     if (hcards) hipHostFree(hcards);
     for (void* p : {sur_x, static_cast<void*>(sur_list), static_cast<void*>(sur_count), static_cast<void*>(sur_heads),
                     static_cast<void*>(sur_cards), static_cast<void*>(sur_cpar), static_cast<void*>(fac_probe),
-                    static_cast<void*>(fac_cards), static_cast<void*>(as_cards), static_cast<void*>(nf_part)})
+                    static_cast<void*>(fac_cards), static_cast<void*>(as_cards), static_cast<void*>(nf_part),
+                    static_cast<void*>(guard_list), static_cast<void*>(guard_count)})
       if (p) hipFree(p);
     if (nf_host) hipHostFree(nf_host);
   }
@@ -261,8 +269,21 @@ int build_cards(rwgt_ctx* c, const double* param_sets, int32_t nsets, bool with_
   return RWGT_OK;
 }
 
+// Device list and count of the guard's flagged events, for nevt events.
+int ensure_guard(rwgt_ctx* c, int64_t nevt) {
+  if (nevt <= c->guard_cap && c->guard_count) return RWGT_OK;
+  if (c->guard_list) { hipStreamSynchronize(c->stream); hipFree(c->guard_list); c->guard_list = nullptr; }
+  c->guard_cap = 0;
+  hipError_t e = hipSuccess;
+  if (!c->guard_count) e = hipMalloc(&c->guard_count, sizeof(unsigned int));
+  if (e == hipSuccess) e = hipMalloc(&c->guard_list, size_t(nevt) * sizeof(int32_t));
+  if (e != hipSuccess) return c->hip_fail(e, "hipMalloc(guard list)");
+  c->guard_cap = nevt;
+  return RWGT_OK;
+}
+
 int run(rwgt_ctx* c, bool reweight, const double* momenta, int64_t nevt, const double* w_in,
-        const double* param_sets, int32_t nsets, double* w_out, double* me_out) {
+        const double* param_sets, int32_t nsets, double* w_out, double* me_out, double* kappa_out = nullptr) {
   if (nevt < 0) return c->fail(RWGT_EINVAL, "nevt < 0");
   if (nsets < 1) return c->fail(RWGT_EINVAL, "nsets < 1");
   if (!param_sets) return c->fail(RWGT_EINVAL, "param_sets is NULL");
@@ -293,8 +314,26 @@ int run(rwgt_ctx* c, bool reweight, const double* momenta, int64_t nevt, const d
   e = rwgt::launch_ingest(c->def->npart, momenta, c->soa, nevt, c->stream);
   if (e != hipSuccess) return c->hip_fail(e, "ingest kernel");
   if (c->profiling) hipEventRecord(c->ev[1], c->stream);
-  e = rwgt::launch_me(c->def->id, c->precision, c->soa, nevt, c->dcards, int(cards.size()), w_in, w_out, me_out,
-                      c->stream);
+  c->guard_ran = false;
+  if (c->precision != RWGT_FP64 && (kappa_out || c->guard_kmax > 0.0)) {
+    rwgt::GuardArgs g;
+    if (kappa_out) {                             // kappa only: nothing flagged or re-evaluated
+      g.kmax = -1.0;
+      g.kappa = kappa_out;
+    } else {
+      rc = ensure_guard(c, nevt);
+      if (rc != RWGT_OK) return rc;
+      g.kmax = c->guard_kmax;
+      g.flagged = c->guard_list;
+      g.nflagged = c->guard_count;
+      c->guard_ran = true;
+    }
+    e = rwgt::launch_me_guarded(c->def->id, c->precision, c->soa, nevt, c->dcards, int(cards.size()), w_in, w_out,
+                                me_out, g, c->stream);
+  } else {
+    e = rwgt::launch_me(c->def->id, c->precision, c->soa, nevt, c->dcards, int(cards.size()), w_in, w_out, me_out,
+                        c->stream);
+  }
   if (e != hipSuccess) return c->hip_fail(e, "matrix-element kernel");
   if (c->profiling) hipEventRecord(c->ev[2], c->stream);
   return RWGT_OK;
@@ -722,7 +761,7 @@ int rwgt_xsec(rwgt_ctx* ctx, const double* weights_in, const double* weights_out
   constexpr int kBlocks = 512;
   double *part = nullptr, *out = nullptr;
   hipError_t e = hipSetDevice(ctx->device);
-  if (e == hipSuccess) e = hipMalloc(&part, size_t(nsets) * kBlocks * 3 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&part, size_t(nsets) * (3 * kBlocks + 3) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&out, size_t(nsets) * 3 * sizeof(double));
   if (e == hipSuccess)
     e = rwgt::launch_xsec(weights_in, weights_out, nevt, nsets, sigma, dsigma, norm, part, kBlocks, out, ctx->stream);
@@ -741,6 +780,39 @@ int rwgt_xsec(rwgt_ctx* ctx, const double* weights_in, const double* weights_out
                            "using dsigma * max(sigma'/sigma, sigma/sigma')\n", int(k));
   }
   return RWGT_OK;
+}
+
+int rwgt_set_mixed_guard(rwgt_ctx* ctx, double kappa_max) {
+  if (!ctx) return RWGT_EINVAL;
+  if (!(kappa_max == kappa_max)) return ctx->fail(RWGT_EINVAL, "kappa_max is NaN");
+  ctx->guard_kmax = kappa_max;
+  return RWGT_OK;
+}
+
+int rwgt_mixed_guard_count(rwgt_ctx* ctx, int64_t* n_reevaluated) {
+  if (!ctx || !n_reevaluated) return RWGT_EINVAL;
+  *n_reevaluated = 0;
+  if (!ctx->guard_ran) return RWGT_OK;
+  unsigned int h = 0;
+  hipError_t e = hipMemcpyAsync(&h, ctx->guard_count, sizeof(h), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return ctx->hip_fail(e, "guard count");
+  *n_reevaluated = int64_t(h);
+  return RWGT_OK;
+}
+
+int rwgt_cancellation(rwgt_ctx* ctx, const double* momenta, int64_t nevt, const double* param_sets, int32_t nsets,
+                      double* me2_out, double* kappa_out) {
+  if (!ctx) return RWGT_EINVAL;
+  ctx->err.clear();
+  if (ctx->precision == RWGT_FP64) return ctx->fail(RWGT_EINVAL, "the cancellation measure is of the mixed path");
+  if (!kappa_out && nevt > 0) return ctx->fail(RWGT_EINVAL, "kappa_out is NULL");
+  try {
+    ctx->nf_blocks = 0;
+    return run(ctx, false, momenta, nevt, nullptr, param_sets, nsets, nullptr, me2_out, kappa_out);
+  } catch (const std::exception& ex) {
+    return ctx->fail(RWGT_ENOMEM, ex.what());
+  }
 }
 
 int rwgt_flops(const rwgt_ctx* ctx, double* flops_per_me2) {

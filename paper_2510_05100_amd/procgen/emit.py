@@ -251,6 +251,7 @@ class Emitter:
             else:
                 expr = f"amp * cx<R>{{R({re}), R({im})}}"
             self.emit(f"jamp[{idx}] = jamp[{idx}] + {expr};")
+        self.emit(f"note_amp(jamp, amp, {len(colour)});")
         self.emit("term_fence();")
 
 
@@ -538,6 +539,7 @@ def generate(d: Diagrams, groups: int | None = None) -> str:
     for i in range(n):
         out.append(f"  const int h{i} = ((hel >> {n - 1 - i}) & 1) ? 1 : -1;")
     out.append("  for (int c = 0; c < NCOL; ++c) jamp[c] = cx<R>{R(0), R(0)};")
+    out.append("  note_reset(jamp);")
     out.append("  cx<R> amp;")
     out.extend(body)
     out.append("}")
@@ -550,6 +552,7 @@ def generate(d: Diagrams, groups: int | None = None) -> str:
     for i in range(n):
         out.append(f"  const int h{i} = ((hel >> {n - 1 - i}) & 1) ? 1 : -1;")
     out.append("  for (int c = 0; c < NCOL; ++c) jamp[c] = cx<R>{R(0), R(0)};")
+    out.append("  note_reset(jamp);")
     out.append("  cx<R> amp;")
     out.extend(em_g.lines)
     out.append("}")

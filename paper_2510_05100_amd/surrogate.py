@@ -8,11 +8,11 @@ the lepton pair under the card and under the original card: 18 inputs), or
 the raw map (momenta and card, 23 inputs).  It is trained on ratios from the
 exact matrix-element path and used with an exact fallback: where the
 calibrated error bound k exp(s) exceeds a threshold the event is reweighted
-exactly (rwgt_sur_eval).  Every numerical step of training and inference runs
-in the library's kernels (features, normalisation statistics, forward,
-backward, Adam, fused inference and gate); this module sequences the calls
-(data set assembly, shuffling, learning-rate schedule, the calibration
-quantile, checkpoints).
+exactly (rwgt_sur_eval).  Every step of training and inference runs in the
+library (features, normalisation statistics, the shuffled epoch loop with its
+learning-rate schedule, forward, backward, Adam, the calibration quantile,
+checkpoints, fused inference and gate); this module only sequences the calls
+and keeps the timings.
 
 Workload: 64 cards on the (M_Z, Gamma_Z, sin^2 theta_W) grid; training on
 62,500 events x 64 cards = 4e6 (event, card) pairs (seed 3000); calibration on
@@ -66,12 +66,6 @@ def exact_ratios(ctx, torch, mom_dev, rows):
     return out
 
 
-def _pairs(torch, n_events, n_cards):
-    """Event and card index of every (event, card) pair, card-major."""
-    idx = torch.arange(n_events * n_cards, device="cuda")
-    return (idx % n_events).to(torch.int32), (idx // n_events).to(torch.int32)
-
-
 class Surrogate:
     def __init__(self, cfg: Config | None = None, orig=None):
         import synth
@@ -91,41 +85,26 @@ class Surrogate:
             self.mlp = None
 
     # ------------------------------------------------------------- training
-    def fit(self, torch, mom_dev, net_cards_dev, y_dev, n_events, n_cards, log=print):
-        """y_dev: log ratios [n_cards][n_events] (float32, device)."""
+    def fit(self, torch, mom_dev, net_cards_dev, y_dev, n_events, n_cards, log=print, epochs_per_call=25):
+        """y_dev: log ratios [n_cards][n_events] (float32, device).  The
+        library fits the normalisations and runs the epochs (shuffle, features,
+        forward, backward, Adam, learning-rate schedule); this loop only
+        asks for them in pieces to log the loss."""
         cfg = self.cfg
         _abi.rwgt_mlp_set_stream(self.mlp, None)
-        total = n_events * n_cards
-        ev_all, cd_all = _pairs(torch, n_events, n_cards)
-        yflat = y_dev.reshape(-1)
-        _abi.rwgt_mlp_fit_normalisation(self.mlp, mom_dev, ev_all, cd_all, net_cards_dev, total)
-        _abi.rwgt_mlp_fit_target_scale(self.mlp, yflat, total)
-        del ev_all, cd_all
-        steps_per_epoch = total // cfg.batch
-        xbuf = torch.empty(_abi.rwgt_mlp_input_bytes(self.mlp, cfg.batch), dtype=torch.uint8, device="cuda")
-        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
-        gen = torch.Generator(device="cuda")
-        gen.manual_seed(cfg.seed)
-        nsteps = steps_per_epoch * cfg.epochs
+        assert mom_dev.shape[0] == n_events and y_dev.shape == (n_cards, n_events)
+        if _abi.rwgt_mlp_get_progress(self.mlp)[0] == 0:
+            _abi.rwgt_mlp_fit_grid(self.mlp, mom_dev, net_cards_dev, y_dev)
         t0 = time.perf_counter()
-        step = 0
-        for epoch in range(cfg.epochs):
-            perm = torch.randperm(total, device="cuda", generator=gen)
-            ev = (perm % n_events).to(torch.int32)
-            cd = (perm // n_events).to(torch.int32)
-            yp = yflat[perm].contiguous()
-            acc = 0.0
-            for b in range(steps_per_epoch):
-                sl = slice(b * cfg.batch, (b + 1) * cfg.batch)
-                lr = cfg.lr * (cfg.lr_final / cfg.lr) ** (step / max(1, nsteps - 1))
-                _abi.rwgt_mlp_features(self.mlp, mom_dev, ev[sl], cd[sl], net_cards_dev, cfg.batch, xbuf)
-                probe = b % 64 == 0                 # the loss is copied out only on the steps that read it
-                _abi.rwgt_mlp_train_step(self.mlp, xbuf, yp[sl], cfg.batch, lr, loss if probe else None)
-                if probe:
-                    acc += float(loss.item()) / cfg.batch
-                step += 1
-            self.history.append(acc / ((steps_per_epoch + 63) // 64))
-            log(f"epoch {epoch}: mean loss {self.history[-1]:.4g} ({time.perf_counter() - t0:.1f}s)")
+        done = _abi.rwgt_mlp_get_progress(self.mlp)[0]
+        while done < cfg.epochs:
+            end = min(cfg.epochs, done + epochs_per_call)
+            losses = _abi.rwgt_mlp_train(self.mlp, mom_dev, net_cards_dev, y_dev, cfg.batch, cfg.epochs, cfg.lr,
+                                         cfg.lr_final, cfg.seed, end)
+            for k, v in enumerate(losses):
+                self.history.append(float(v))
+                log(f"epoch {done + k}: mean loss {v:.4g} ({time.perf_counter() - t0:.1f}s)")
+            done = end
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
@@ -138,37 +117,31 @@ class Surrogate:
         return heads[:, 0], heads[:, 1]
 
     def calibrate(self, torch, mom_dev, net_cards_dev, y_dev, n_events, n_cards):
-        """k = quantile of |y - mu| / exp(s) over the calibration pairs."""
-        ev, cd = _pairs(torch, n_events, n_cards)
-        mu, s = self.predict(torch, mom_dev, cd, net_cards_dev, ev)
-        resid = torch.abs(y_dev.reshape(-1) - mu)
-        z = (resid / torch.exp(s)).cpu().numpy()
-        self.k = float(np.quantile(z, self.cfg.coverage))
-        _abi.rwgt_mlp_set_calibration(self.mlp, self.k)
-        r = resid.cpu().numpy()
-        return {"k": self.k, "median_abs_err": float(np.median(r)), "p90_abs_err": float(np.quantile(r, 0.9)),
-                "p999_abs_err": float(np.quantile(r, 0.999))}
+        """k = coverage quantile of |y - mu| / exp(s) over the calibration pairs (in the library)."""
+        assert mom_dev.shape[0] == n_events and y_dev.shape == (n_cards, n_events)
+        k, med, p90, p999 = _abi.rwgt_mlp_calibrate(self.mlp, mom_dev, net_cards_dev, y_dev, self.cfg.coverage)
+        self.k = k
+        return {"k": k, "median_abs_err": med, "p90_abs_err": p90, "p999_abs_err": p999}
 
     # ---------------------------------------------------------- checkpoints
     def save(self, path):
-        mean, std, (ym, ys) = _abi.rwgt_mlp_get_normalisation(self.mlp, self.n_in)
-        np.savez(path, params=_abi.rwgt_mlp_get_params(self.mlp), mean=mean, std=std, y_scale=np.array([ym, ys]),
-                 k=np.float64(self.k or 0.0), width=self.cfg.width, depth=self.cfg.depth,
-                 precision=self.cfg.precision, features=self.cfg.features, orig=np.array(self.orig),
-                 history=np.array(self.history))
+        """Everything a resumed run needs (library checkpoint: parameters, Adam
+        moments and step count, schedule and epoch, normalisations, k)."""
+        _abi.rwgt_mlp_save(self.mlp, path)
 
     @classmethod
-    def load(cls, path):
-        d = np.load(path)
-        cfg = Config(width=int(d["width"]), depth=int(d["depth"]), precision=int(d["precision"]),
-                     features=int(d["features"]))
-        s = cls(cfg, orig=tuple(float(v) for v in d["orig"]))
-        _abi.rwgt_mlp_set_params(s.mlp, d["params"])
-        _abi.rwgt_mlp_set_normalisation(s.mlp, d["mean"], d["std"])
-        _abi.rwgt_mlp_set_target_scale(s.mlp, float(d["y_scale"][0]), float(d["y_scale"][1]))
-        if float(d["k"]) > 0:
-            s.k = float(d["k"])
-            _abi.rwgt_mlp_set_calibration(s.mlp, s.k)
+    def load(cls, path, cfg: Config | None = None):
+        """A surrogate from a checkpoint; cfg (optional) carries the training
+        schedule to resume with (it must match the saved one)."""
+        shape, _, _ = _abi.rwgt_mlp_checkpoint_info(path)
+        n_in, width, depth, _, precision = shape
+        s = cls.__new__(cls)
+        s.cfg = cfg or Config(width=width, depth=depth, precision=precision)
+        s.mlp = _abi.rwgt_mlp_load(path)
+        s.n_in = n_in
+        s.orig = None
+        s.k = None
+        s.history = []
         return s
 
 

@@ -105,3 +105,46 @@ def test_bench_refuses_more_than_one_gpu():
                          text=True, timeout=120, cwd=ROOT)
     assert res.returncode == 2
     assert "one GPU only" in res.stderr and res.stdout == ""
+
+
+def test_train_order_is_a_permutation_per_epoch(lib):
+    """rwgt_train_order: every (seed, epoch) gives a bijection of [0, n), for n
+    just above a power of four (the cycle walk then rejects most of the
+    Feistel word space) and for the 4e6-pair training grid; another epoch or
+    seed gives another order; a window equals the same slice of the whole."""
+    import numpy as np
+    from paper_2510_05100_amd import _abi
+    for n in (1, 2, 3, 17, 4097, 65537):
+        for epoch in (0, 5):
+            o = _abi.rwgt_train_order(11, epoch, n)
+            np.testing.assert_array_equal(np.sort(o), np.arange(n))
+    full = _abi.rwgt_train_order(1, 0, 4_000_000)
+    np.testing.assert_array_equal(np.sort(full), np.arange(4_000_000))
+    assert not np.array_equal(full[:1000], _abi.rwgt_train_order(1, 1, 4_000_000, 0, 1000))
+    assert not np.array_equal(full[:1000], _abi.rwgt_train_order(2, 0, 4_000_000, 0, 1000))
+    np.testing.assert_array_equal(_abi.rwgt_train_order(1, 0, 4_000_000, 123_456, 4096), full[123_456:127_552])
+    # a shuffle, not a shift: consecutive positions land far apart in the grid
+    assert np.median(np.abs(np.diff(full[:4096]))) > 1e5
+    assert lib.rwgt_train_order(1, 0, 10, 5, 6, None) == -1
+    with pytest.raises(_abi.RwgtError):
+        _abi.rwgt_train_order(1, 0, 10, 5, 6)
+
+
+def test_checkpoint_reader_rejects_bad_files(lib, tmp_path):
+    """rwgt_mlp_checkpoint_info reads on the host only: a missing file is
+    EINVAL, a file without the magic, a truncated one and one with a flipped
+    byte are ECARD, with a message naming the cause."""
+    from paper_2510_05100_amd import _abi
+    with pytest.raises(_abi.RwgtError, match="EINVAL"):
+        _abi.rwgt_mlp_checkpoint_info(str(tmp_path / "missing.ckpt"))
+    junk = tmp_path / "junk.ckpt"
+    junk.write_bytes(b"not a checkpoint at all, just text")
+    with pytest.raises(_abi.RwgtError, match="not a surrogate checkpoint"):
+        _abi.rwgt_mlp_checkpoint_info(str(junk))
+    fake = tmp_path / "fake.ckpt"
+    fake.write_bytes(b"RWGTMLP\0" + bytes(200))
+    with pytest.raises(_abi.RwgtError, match="hash mismatch"):
+        _abi.rwgt_mlp_checkpoint_info(str(fake))
+    with pytest.raises(_abi.RwgtError, match="ECARD"):
+        _abi.rwgt_mlp_load(str(fake))
+    assert lib.rwgt_mlp_load(None, None) == -1

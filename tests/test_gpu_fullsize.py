@@ -57,6 +57,15 @@ def test_gg_ttgg_full_size(gg_events, precision, tol):
         err = np.abs(ratio / RATIO - 1.0)
         print(f"gg_ttgg precision {precision}: max |w'/w / (0.130/0.118)^4 - 1| = {err.max():.3g}", flush=True)
         assert err.max() < tol
+        # sigma', dsigma' of the nearly constant w' against the oracle on the same weights
+        from oracle import xsec as oxsec
+        for dsigma in (0.3, 0.0):
+            xs, xe, _ = rw.rwgt_xsec(r.ctx, w, out, 12.5, dsigma, 12.5 / N_FULL)
+            rx, re_, _ = oxsec.xsec(np.ones(N_FULL), ratio, 12.5, dsigma, 12.5 / N_FULL)
+            assert rel_err(xs, rx).max() < 1e-11
+            # dsigma = 0 leaves sigma std(w'), whose FP64 value is rounding noise (1e-16 of w'):
+            # its absolute error is what is bounded then
+            assert (rel_err(xe, re_).max() < 1e-9) if dsigma else (abs(xe[0] - re_[0]) < 1e-12 * 12.5 * RATIO)
         if precision == 0:
             me = torch.empty((1, N_FULL), dtype=torch.float64, device="cuda")
             r.me2(pd, synth.ORIG_QCD.row("gg_ttgg"), me)

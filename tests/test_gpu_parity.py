@@ -195,6 +195,29 @@ def test_xsec_against_oracle():
     assert abs(xs[2] - 12.5) < 1e-10          # the original card gives back sigma
 
 
+@pytest.mark.parametrize("dsigma", [0.3, 0.0])
+def test_xsec_near_constant_weights(dsigma):
+    """Delta sigma' when w' is nearly constant (what a pure alpha_s change
+    gives): 1e6 weights 1.4731 (1 + 1e-9 u), u uniform in [-1, 1].  A
+    variance taken as S2/N - mean^2 cancels to noise of order 1e-8 mean
+    here; taken about the mean it matches the oracle's two-pass std.  With
+    dsigma = 0 the error is sigma * std(w') alone."""
+    _print_case("xsec_near_constant", dsigma=dsigma)
+    torch = torch_cuda()
+    import paper_2510_05100_amd as rw
+    from oracle import xsec as oxsec
+    n = 1_000_000
+    u = np.random.default_rng(5).uniform(-1.0, 1.0, n)
+    w = np.ones(n)
+    wp = RATIO * (1.0 + 1e-9 * u)
+    with rw.Reweighter("g g > t t~ g g", synth.ORIG_QCD.slha()) as r:
+        xs, xe, fb = rw.rwgt_xsec(r.ctx, dev(w), dev(wp[None, :]), 12.5, dsigma, 12.5 / n)
+    rx, re_, rb = oxsec.xsec(w, wp, 12.5, dsigma, 12.5 / n)
+    print(f"xsec near-constant: dsigma' {xe[0]!r} oracle {re_[0]!r}", flush=True)
+    assert rel_err(xs, rx).max() < 1e-11 and rel_err(xe, re_).max() < 1e-9
+    assert not fb.any() and not rb.any()
+
+
 def test_device_against_stored_oracle_values():
     """|M|^2 and w' of the first events of each workload against the oracle
     values stored in tests/golden/me2_oracle.json (no oracle run needed)."""

@@ -230,3 +230,34 @@ def test_quantile_and_calibration_order_statistics():
     y = np.array([1.0, -4.0, 9.0, 16.0])
     assert abs(mlp.calibration_k(y, 0.0, s, 1.0) - 4.0) < 1e-14
     assert abs(mlp.calibration_k(y, 0.0, s, 0.5) - 2.5) < 1e-14
+
+
+def test_bf16_rounding_hand_values():
+    """bfloat16 keeps 8 significant bits: between 1 and 2 its spacing is 2^-7,
+    so 1 + 2^-8 is a tie that rounds to the even 1, 1 + 3 2^-8 a tie that
+    rounds to the even 1 + 2^-6, 1 + 2^-8 + 2^-20 rounds up; 0.3 = 153.6 2^-9
+    -> 154 2^-9; 0.7 = 179.2 2^-8 -> 179 2^-8; pi -> 3.140625 (402 2^-7);
+    signs are kept and zero stays zero."""
+    x = np.array([1.0, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, 1 + 2.0 ** -8 + 2.0 ** -20, 0.3, 0.7, np.pi, -0.7, 0.0])
+    want = np.array([1.0, 1.0, 1 + 2.0 ** -6, 1 + 2.0 ** -7, 154 * 2.0 ** -9, 179 * 2.0 ** -8, 3.140625,
+                     -179 * 2.0 ** -8, 0.0])
+    np.testing.assert_array_equal(mlp.bf16(x), want)
+
+
+def test_forward_bf16_hand_computed_three_layers():
+    """1 -> 2 -> 2 -> 2: the first layer's weight 2.01 is not a bfloat16 value
+    and stays as it is; its activations silu(2.01) = 1.77250... (226.88 2^-7)
+    and silu(-1) = -0.268941... (-137.70 2^-9) enter the hidden layer as
+    227 2^-7 and -138 2^-9, its weights 0.3 and 0.7 as 154 2^-9 and
+    179 2^-8; the head takes the hidden activations unrounded."""
+    w0, w1, w2 = np.array([[2.01], [-1.0]]), np.array([[0.3, 0.7], [1.0, 0.5]]), np.array([[1.0, -1.0], [0.25, 0.5]])
+    b1 = np.array([0.1, -0.2])
+    params = [(w0, np.zeros(2)), (w1, b1), (w2, np.zeros(2))]
+    h0 = np.array([227 / 128, -138 / 512])
+    z1 = np.array([154 / 512 * h0[0] + 179 / 256 * h0[1], h0[0] + 0.5 * h0[1]]) + b1
+    h1 = z1 / (1.0 + np.exp(-z1))
+    want = np.array([[h1[0] - h1[1], 0.25 * h1[0] + 0.5 * h1[1]]])
+    np.testing.assert_allclose(mlp.forward_bf16(params, np.array([[1.0]])), want, rtol=1e-15, atol=1e-16)
+    # and the plain network differs at the level of the roundings
+    plain, _ = mlp.forward(params, np.array([[1.0]]))
+    assert np.max(np.abs(plain - want)) > 1e-4
