@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-factored", action="store_true")
     ap.add_argument("--no-pcie", action="store_true", help="skip the pinned-host-memory (PCIe-inclusive) step")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the e+ e- -> mu+ mu- (1e4) and u u~ -> e+ e- g (1e6) legs")
     ap.add_argument("--surrogate-epochs", type=int, default=None,
                     help="training epochs of the surrogate networks (default: the Config default); fewer only "
                          "to keep a kernel trace short")
@@ -105,10 +107,92 @@ def time_mode(rw, torch, precision, p_dev, w_dev, rows, nevt, steps, warmup):
     dt = (time.perf_counter() - t0) / steps
     w = out.cpu().numpy()
     flops = rw.rwgt_flops(r.ctx)
+    guard = rw.rwgt_mixed_guard_count(r.ctx)
+    # |M|^2 under the original card (untimed), for the per-result errors
+    me = torch.empty((1, nevt), dtype=torch.float64, device="cuda")
+    r.me2(p_dev, synth.ORIG_QCD.row("gg_ttgg"), me)
+    me = me.cpu().numpy()[0]
     r.close()
-    err = float(np.max(np.abs(w / RATIO - 1.0)))
+    rel = np.abs(w / RATIO - 1.0)
     return dict(ms_per_step=dt * 1e3, me_ms=float(np.mean(me_ms)), ingest_ms=float(np.mean(ing_ms)),
-                max_rel_err=err, flops_per_me2=flops, w=w)
+                max_rel_err=float(rel.max()), p999_rel_err=float(np.quantile(rel, 0.999)), flops_per_me2=flops,
+                w=w, me=me, reevaluated=guard)
+
+
+def mixed_errors(rw, torch, p, p_dev, w_dev, rows, x, f, sample=200):
+    """Errors of the mixed results per result kind: w' over every event
+    against the exact ratio; |M|^2 over every event against the FP64 path (which
+    agrees with the oracle to 1e-13) and on an evenly spaced sample against
+    the oracle itself; and w' with the guard off, for comparison."""
+    import synth
+    from oracle import reweight
+    me_rel = np.abs(x["me"] / f["me"] - 1.0)
+    idx = np.linspace(0, p.shape[0] - 1, sample).astype(np.int64)
+    ref = reweight.me2("gg_ttgg", p[idx], synth.ORIG_QCD)
+    with rw.Reweighter("g g > t t~ g g", synth.ORIG_QCD.slha(), rw.RWGT_MIXED_FP16) as r:
+        rw.rwgt_set_mixed_guard(r.ctx, 0.0)
+        out = torch.empty((1, p.shape[0]), dtype=torch.float64, device="cuda")
+        r.eval(p_dev, w_dev, rows, out)
+        plain = np.abs(out.cpu().numpy() / RATIO - 1.0)
+    return {"w_max_rel_err": x["max_rel_err"], "w_p999_rel_err": x["p999_rel_err"],
+            "me2_max_rel_err_vs_fp64_path": float(me_rel.max()),
+            "me2_p999_rel_err_vs_fp64_path": float(np.quantile(me_rel, 0.999)),
+            "me2_max_rel_err_vs_oracle": float(np.max(np.abs(x["me"][idx] / ref - 1.0))),
+            "oracle_sample": f"{sample} evenly spaced events",
+            "w_max_rel_err_guard_off": float(plain.max())}
+
+
+def workload_leg(rw, torch, proc, orig, new, n, steps, warmup, oracle_sample):
+    """One of the electroweak workloads at its own size (e+ e- -> mu+ mu-, 1e4
+    events, or u u~ -> e+ e- g, 1e6 events, one new card), FP64 and mixed:
+    reweighted events/s of the same timed rwgt_eval step as the headline,
+    errors of w' and |M|^2 against the oracle on an evenly spaced sample, the
+    mixed w' against the FP64 path on every event, and the FLOP rate of the
+    matrix-element launch against the vector FP64 (FP32) peak."""
+    import synth
+    from oracle import reweight
+    text = synth.PROCESSES[proc]
+    p = synth.events(proc, n)
+    p_dev = torch.as_tensor(p).cuda()
+    w_dev = torch.ones(n, dtype=torch.float64, device="cuda")
+    rows = new.row(proc)[None, :]
+    idx = np.linspace(0, n - 1, min(n, oracle_sample)).astype(np.int64)
+    ref_w, ref_me, _ = reweight.reweight(proc, p[idx], np.ones(idx.size), orig, [new])
+    out, legs = {}, {}
+    for mode, prec in (("fp64", rw.RWGT_FP64), ("mixed", rw.RWGT_MIXED_FP16)):
+        r = rw.Reweighter(text, orig.slha(), prec)
+        w = torch.empty((1, n), dtype=torch.float64, device="cuda")
+        me = torch.empty((1, n), dtype=torch.float64, device="cuda")
+        rw.rwgt_set_profiling(r.ctx, True)
+        for _ in range(warmup):
+            r.eval(p_dev, w_dev, rows, w)
+        torch.cuda.synchronize()
+        me_ms = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r.eval(p_dev, w_dev, rows, w)
+            me_ms.append(rw.rwgt_kernel_times(r.ctx)[1])
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        guard = rw.rwgt_mixed_guard_count(r.ctx)
+        r.me2(p_dev, orig.row(proc), me)
+        flops = rw.rwgt_flops(r.ctx) * n * 2
+        r.close()
+        wh, meh = w.cpu().numpy()[0], me.cpu().numpy()[0]
+        out[mode] = wh
+        kernel_ms = float(np.mean(me_ms))
+        legs[mode] = {"ms_per_step": dt * 1e3, "value": n / dt, "me_kernel_ms": kernel_ms,
+                      "w_max_rel_err_vs_oracle": float(np.max(np.abs(wh[idx] / ref_w[0] - 1.0))),
+                      "me2_max_rel_err_vs_oracle": float(np.max(np.abs(meh[idx] / ref_me - 1.0))),
+                      "roofline": {"bound": "alu", "achieved": flops / (kernel_ms * 1e-3) / 1e12, "peak": 78.6,
+                                   "unit": "TFLOP/s", "frac": flops / (kernel_ms * 1e-3) / PEAK_FP64_VALU}}
+        if mode == "mixed":
+            rel = np.abs(wh / out["fp64"] - 1.0)
+            legs[mode].update({"w_max_rel_err_vs_fp64_path": float(rel.max()),
+                               "w_p999_rel_err_vs_fp64_path": float(np.quantile(rel, 0.999)),
+                               "guard_reevaluated": guard})
+    return {"workload": f"{text}, {n} events, 1 new card", "events": n, "oracle_sample": int(idx.size),
+            "unit": "reweighted events/s", **legs}
 
 
 def _limit_threads():
@@ -354,7 +438,18 @@ def main():
         x = res["mixed"]
         line["mixed"] = {"value": a.events * nsets / (x["ms_per_step"] * 1e-3), "ms_per_step": x["ms_per_step"],
                          "max_rel_err": x["max_rel_err"], "dtype": "f32 amplitudes, f64 momenta/denominators/ratio",
-                         "roofline": roofline(x, PEAK_FP32_VALU_UNPACKED, "mixed")}
+                         "roofline": roofline(x, PEAK_FP32_VALU_UNPACKED, "mixed"),
+                         "guard": {"kappa_max": 300.0, "reevaluated_fp64": x["reevaluated"],
+                                   "fraction": x["reevaluated"] / a.events},
+                         "errors": mixed_errors(rw, torch, p, p_dev, w_dev, rows, x, m)}
+    if not a.no_workloads:
+        line["workloads"] = {}
+        for key, proc, orig, new, n, sample in (("ee_mumu_1e4", "ee_mumu", synth.ORIG_EW, synth.NEW_EE, 10_000, 10_000),
+                                                ("uu_eeg_1e6", "uu_eeg", synth.ORIG_EW, synth.NEW_UU, 1_000_000, 1000)):
+            line["workloads"][key] = workload_leg(rw, torch, proc, orig, new, n, steps=a.steps, warmup=a.warmup,
+                                                  oracle_sample=sample)
+            log(f"{key}: fp64 {line['workloads'][key]['fp64']['value']:.3g}, mixed "
+                f"{line['workloads'][key]['mixed']['value']:.3g} reweighted events/s")
     if main_mode == "fp64" and not a.no_pcie:
         line["pcie_inclusive"] = pcie_inclusive(rw, torch, p, rows, a.events, steps=3)
         log(f"pcie-inclusive: {line['pcie_inclusive']['ms_per_step']:.2f} ms/step")

@@ -57,7 +57,11 @@ enum {
   RWGT_MIXED_BF16 = 2   /* float amplitudes, BF16 hi/mid/lo MFMA colour sum, double ratio */
 };
 
-/* Create a context for one process on the current HIP device.
+/* Create a context for one process on the current HIP device: the paper's
+ * per-process reweighting object (Tensorial event adaption section, Generic
+ * and SLHA parameter reweighting: a weight function per process, evaluated
+ * under an original SLHA card that each iteration overrides; MadtRex section,
+ * Usage: tree-level, helicity-summed amplitudes, precision chosen by fptype).
  *  process:    "e+ e- > mu+ mu-", "u u~ > e+ e- g" or "g g > t t~ g g"
  *              (whitespace-insensitive);
  *  param_card: SLHA text of the ORIGINAL card (blocks SMINPUTS 1 = 1/alpha,
@@ -68,17 +72,24 @@ enum {
  * Errors: RWGT_EINVAL, RWGT_EPROCESS, RWGT_ECARD, RWGT_EDEVICE, RWGT_ENOMEM. */
 int rwgt_create(const char *process, const char *param_card, int precision, rwgt_ctx **out);
 
-/* Free the context and its device buffers (after its queued work).  NULL is a no-op. */
+/* Free the context and its device buffers (after its queued work).  NULL is a
+ * no-op.  (The release counterpart of rwgt_create; the paper's objects are
+ * scoped C++ values.) */
 void rwgt_destroy(rwgt_ctx *ctx);
 
-/* Number of columns of a param_sets row and their names ("SMINPUTS 3", ...).
- * names may be NULL; otherwise it receives npar pointers owned by ctx. */
+/* Number of columns of a param_sets row and their names ("SMINPUTS 3", ...):
+ * the SLHA entries (block, index) a reweighting iteration may override
+ * (Tensorial event adaption section, SLHA parameter reweighting).  names may
+ * be NULL; otherwise it receives npar pointers owned by ctx. */
 int rwgt_param_layout(const rwgt_ctx *ctx, int32_t *npar, const char **names);
 
 /* The original card's values in layout order (host array of npar doubles). */
 int rwgt_original_params(const rwgt_ctx *ctx, double *values);
 
-/* Stream for subsequent calls: a hipStream_t passed as void* (NULL = null stream). */
+/* Stream for subsequent calls: a hipStream_t passed as void* (NULL = null
+ * stream).  (Device-side ordering of the data-parallel amplitude calls the
+ * MadtRex section's Backend details hand to the GPU; the paper has no stream
+ * interface of its own.) */
 int rwgt_set_stream(rwgt_ctx *ctx, void *stream);
 
 /* Reweight: weights_out[k][i] = (weights_in[i] * (1/|M|^2_orig[i])) * |M|^2_k[i]
@@ -115,7 +126,10 @@ int rwgt_eval_alphas(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const d
                      const double *alphas_orig, const double *scales, const double *param_sets, int32_t nsets,
                      double *weights_out);
 
-/* |M|^2 itself for each card of param_sets: me2_out[k][i].  Same rules as rwgt_eval. */
+/* |M|^2 itself for each card of param_sets: me2_out[k][i] -- the weight
+ * function of parameter reweighting, which is also its normaliser under the
+ * original card (MadtRex section, Backend details; Tensorial event adaption
+ * section, Generic reweighting).  Same rules as rwgt_eval. */
 int rwgt_me2(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const double *param_sets, int32_t nsets,
              double *me2_out);
 
@@ -142,8 +156,9 @@ int rwgt_cancellation(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const 
                       double *me2_out, double *kappa_out);
 
 /* Number of non-finite entries (NaN or +-inf) in the output array of the
- * last rwgt_eval, rwgt_me2, rwgt_eval_factored or rwgt_eval_alphas call on
- * ctx (weights_out or me2_out, nsets * nevt entries); 0 when that call failed
+ * last rwgt_eval, rwgt_me2, rwgt_eval_factored, rwgt_eval_alphas,
+ * rwgt_eval_cards or rwgt_sur_eval call on ctx (weights_out or me2_out,
+ * nsets * nevt entries, or nevt); 0 when that call failed
  * or had nevt = 0.  Non-finite momenta or weights give non-finite outputs
  * (nothing is clamped), and a zero original |M|^2 gives w' = 0, which is
  * finite (teaRex section, the normaliser's guard).  The count is taken on the
@@ -151,7 +166,10 @@ int rwgt_cancellation(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const 
  * for it.  Errors: RWGT_EINVAL (NULL), RWGT_EDEVICE. */
 int rwgt_nonfinite(rwgt_ctx *ctx, int64_t *count);
 
-/* Message of the last failed call on ctx (empty string if none). */
+/* Message of the last failed call on ctx (empty string if none).  The
+ * paper's library throws runtime errors or prints warnings (Tensorial event
+ * adaption section, Generic reweighting); across this C ABI an error is a
+ * return code plus this message. */
 const char *rwgt_last_error(const rwgt_ctx *ctx);
 
 /* Message of the last failed rwgt_create on this thread (no context exists then). */
@@ -200,7 +218,9 @@ int rwgt_kernel_times(rwgt_ctx *ctx, float *ingest_ms, float *me_ms);
  * size, workgroups per CU, helicity split) comes from rwgt_batch_set_schedule,
  * the tuning cache written by rwgt_batch_tune, or a default.  The paper runs
  * subprocesses on a CPU thread pool and notes that sequential subprocesses
- * leave the GPU latency-bound; this is the single-launch alternative.
+ * leave the GPU latency-bound (MadtRex section, Runtime comparisons); this is
+ * the single-launch alternative, and every rwgt_batch_* call below belongs to
+ * it.
  * Family: e+ e- > mu+ mu- and u u~ > e+ e- g, all contexts of one precision.
  */
 typedef struct rwgt_batch rwgt_batch;
@@ -411,9 +431,10 @@ const char *rwgt_mlp_checkpoint_error(void);
 /* Exact reweighting with a card per event (the path rwgt_sur_eval falls back
  * to, on every event): event i gets card card_index[i] (DEVICE int32, in
  * [0, ncards)) of param_table (HOST [ncards][npar], the context's layout),
- * w'_i = (w_i / |M|^2(p_i; original)) |M|^2(p_i; card).  Processes of the
- * electroweak family.  Errors as rwgt_eval, RWGT_EPROCESS for other
- * processes. */
+ * w'_i = (w_i / |M|^2(p_i; original)) |M|^2(p_i; card).  An index outside
+ * [0, ncards) reads no card: that event's w' is NaN, counted by
+ * rwgt_nonfinite.  Processes of the electroweak family.  Errors as rwgt_eval,
+ * RWGT_EPROCESS for other processes. */
 int rwgt_eval_cards(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const double *weights_in,
                     const double *param_table, int32_t ncards, const int32_t *card_index, double *weights_out);
 
@@ -426,7 +447,9 @@ int rwgt_eval_cards(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const do
  * momenta and the card's (M_Z, Gamma_Z, sin^2 theta_W).  Networks eligible
  * for rwgt_mlp_predict run as one fused kernel (features, layers, heads and
  * gate), others layer by layer.  *n_fallback (HOST, optional; waits for the
- * call) receives the number of exact evaluations.  Processes of the
+ * call) receives the number of exact evaluations.  A card index outside
+ * [0, ncards) gives that event NaN inputs, so it falls back, and the exact
+ * path writes NaN for it (counted by rwgt_nonfinite).  Processes of the
  * electroweak family. */
 int rwgt_sur_eval(rwgt_ctx *ctx, rwgt_mlp *mlp, const double *momenta, int64_t nevt, const double *weights_in,
                   const double *param_table, int32_t ncards, const int32_t *card_index, double err_threshold,

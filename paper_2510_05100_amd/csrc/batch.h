@@ -37,9 +37,10 @@ hipError_t launch_batch(int family, int precision, const BatchSeg* segs, int nse
 // Exact reweighting with a card per event: the events list[0 .. *count) (device
 // list and count, at most n_all of them), or every event 0 .. n_all-1 when
 // list is NULL.  One lane per (event, kept helicity), at most max_blocks
-// workgroups of 256 lanes (grid-stride beyond).
+// workgroups of 256 lanes (grid-stride beyond).  Event e uses cards[0] and
+// cards[1 + card_index[e]]; an index outside [0, ncards) gives w' = NaN.
 hipError_t launch_exact_list(int family, int precision, int proc, const double* mom, const int32_t* list,
-                             const unsigned int* count, int64_t n_all, const int32_t* card_index,
+                             const unsigned int* count, int64_t n_all, const int32_t* card_index, int ncards,
                              const CardPair* cards, const double* w_in, double* w_out, int max_blocks,
                              hipStream_t s);
 

@@ -159,12 +159,14 @@ static hipError_t launch_batch_t(const BatchSeg* segs, int nseg, int64_t ntiles,
 // helicity and one card per lane keeps the registers to a few waves per
 // SIMD, and a short fallback list still fills the chip.  Events
 // list[0 .. *count) (the count stays on the device, at most n_all), or
-// 0 .. n_all-1 without a list; grid-stride over events.
+// 0 .. n_all-1 without a list; grid-stride over events.  A card index
+// outside [0, ncards) reads no card: the event's w' is NaN (the same
+// decision on every lane of its group).
 template <class R, class PROC>
 __global__ __launch_bounds__(256) void exact_hel_kernel(const double* __restrict__ mom,
                                                         const int32_t* __restrict__ list,
                                                         const unsigned int* __restrict__ count, int64_t n_all,
-                                                        const int32_t* __restrict__ card_index,
+                                                        const int32_t* __restrict__ card_index, int ncards,
                                                         const CardPair* __restrict__ cards,
                                                         const double* __restrict__ w_in, double* __restrict__ w_out) {
   constexpr int G2 = 2 * PROC::NGOOD;
@@ -175,36 +177,40 @@ __global__ __launch_bounds__(256) void exact_hel_kernel(const double* __restrict
   const int64_t per_block = blockDim.x / G2;
   for (int64_t i = int64_t(blockIdx.x) * per_block + threadIdx.x / G2; i < n; i += int64_t(gridDim.x) * per_block) {
     const int64_t e = list ? int64_t(list[i]) : i;
-    hel_group_event<R, PROC>(mom + e * (PROC::NPART * 4), j, lane0, cards[0], cards[1 + card_index[e]], w_in + e,
-                             w_out + e);
+    const int32_t k = card_index[e];
+    if (k < 0 || k >= ncards) {
+      if (j == 0) w_out[e] = __builtin_nan("");
+      continue;
+    }
+    hel_group_event<R, PROC>(mom + e * (PROC::NPART * 4), j, lane0, cards[0], cards[1 + k], w_in + e, w_out + e);
   }
 }
 
 template <class R>
 static void launch_exact_hel(int proc, const double* mom, const int32_t* list, const unsigned int* count,
-                             int64_t n_all, const int32_t* card_index, const CardPair* cards, const double* w_in,
-                             double* w_out, int max_blocks, hipStream_t s) {
+                             int64_t n_all, const int32_t* card_index, int ncards, const CardPair* cards,
+                             const double* w_in, double* w_out, int max_blocks, hipStream_t s) {
   const int g = 2 * (proc == 0 ? Proc_ee_mumu::NGOOD : Proc_uu_eeg::NGOOD);   // lanes per event
   const int64_t need = (n_all * g + 255) / 256;
   const unsigned blocks = unsigned(need < max_blocks ? (need < 1 ? 1 : need) : max_blocks);
   if (proc == 0)
     hipLaunchKernelGGL((exact_hel_kernel<R, Proc_ee_mumu>), dim3(blocks), dim3(256), 0, s, mom, list, count, n_all,
-                       card_index, cards, w_in, w_out);
+                       card_index, ncards, cards, w_in, w_out);
   else
     hipLaunchKernelGGL((exact_hel_kernel<R, Proc_uu_eeg>), dim3(blocks), dim3(256), 0, s, mom, list, count, n_all,
-                       card_index, cards, w_in, w_out);
+                       card_index, ncards, cards, w_in, w_out);
 }
 
 hipError_t launch_exact_list(int family, int precision, int proc, const double* mom, const int32_t* list,
-                             const unsigned int* count, int64_t n_all, const int32_t* card_index,
+                             const unsigned int* count, int64_t n_all, const int32_t* card_index, int ncards,
                              const CardPair* cards, const double* w_in, double* w_out, int max_blocks,
                              hipStream_t s) {
   if (family != kFamilyElectroweak || (proc != 0 && proc != 1)) return hipErrorInvalidValue;
   if (n_all <= 0) return hipSuccess;
   if (precision == kPrecFP64)
-    launch_exact_hel<double>(proc, mom, list, count, n_all, card_index, cards, w_in, w_out, max_blocks, s);
+    launch_exact_hel<double>(proc, mom, list, count, n_all, card_index, ncards, cards, w_in, w_out, max_blocks, s);
   else
-    launch_exact_hel<float>(proc, mom, list, count, n_all, card_index, cards, w_in, w_out, max_blocks, s);
+    launch_exact_hel<float>(proc, mom, list, count, n_all, card_index, ncards, cards, w_in, w_out, max_blocks, s);
   return hipGetLastError();
 }
 

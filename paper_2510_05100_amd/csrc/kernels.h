@@ -21,8 +21,11 @@ hipError_t launch_ingest(int npart, const double* aos, double* soa, int64_t nevt
 hipError_t launch_me(int proc, int precision, const double* soa, int64_t nevt, const CardPair* cards, int ncards,
                      const double* w_in, double* w_out, double* me_out, hipStream_t s);
 
-// Default threshold of the mixed path's cancellation guard (0: off).
-constexpr double kGuardKappaDefault = 0.0;
+// Default threshold of the mixed path's cancellation guard: measured on 4e6
+// g g -> t t~ g g events (FP16 colour sum), it re-evaluates 0.10 % of them and
+// leaves a largest w' error of 3.6e-6 (none: 6.9e-6); on 1e6 u u~ -> e+ e- g
+// events 0.13 % and 2.3e-6 on w', 4.1e-6 on |M|^2 (none: 6.0e-5).
+constexpr double kGuardKappaDefault = 300.0;
 
 // Cancellation guard of the mixed path (me_kernel.h, launch_me_guarded).
 struct GuardArgs {

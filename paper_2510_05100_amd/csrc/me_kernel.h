@@ -238,6 +238,60 @@ __global__ __launch_bounds__(kMeBlock) void me_kernel(const double* __restrict__
 
 static __global__ void zero_count_kernel(unsigned int* c) { *c = 0u; }
 
+// Double-precision re-evaluation of the events rows[0 .. *nrows) of a
+// many-flow process, one wave per event (grid-stride over the list), one lane
+// per kept helicity: each lane evaluates its helicity's |M_h|^2 (flows in
+// LDS) under every card, and lane 0 adds the lanes' values in me_kernel's
+// order (the first half of the helicities in sequence, the second half in
+// sequence, then their sum).  The per-helicity code is me_kernel's, but with
+// the helicity per lane instead of per wave the compiler may round a last bit
+// differently (measured: within 1 ulp of me_kernel's result).
+// A short list keeps the chip busy for one helicity's evaluation per card,
+// where one lane per event would take a whole helicity loop.
+template <class PROC>
+__global__ __launch_bounds__(64) void me_wave_kernel(const double* __restrict__ soa, int64_t nevt,
+                                                     const CardPair* __restrict__ cards, int ncards,
+                                                     const double* __restrict__ w_in, double* __restrict__ w_out,
+                                                     double* __restrict__ me_out, const int32_t* __restrict__ rows,
+                                                     const unsigned int* __restrict__ nrows) {
+  constexpr int NG = PROC::NGOOD;
+  static_assert(NG <= 64 && hel_split<PROC>() == 2 && NG % 2 == 0, "one wave holds an event's helicities");
+  __shared__ cx<double> lds_jamp[PROC::NCOL * 64];
+  const int lane = int(threadIdx.x);
+  const int ih = lane < NG ? lane : NG - 1;
+  const int64_t n = int64_t(*nrows);
+  for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
+    const int64_t i = int64_t(rows[r]);
+    double P[PROC::NPART][4];
+#pragma unroll
+    for (int a = 0; a < PROC::NPART; ++a)
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) P[a][mu] = soa[int64_t(a * 4 + mu) * nevt + i];
+    double norm = 0.0;
+    for (int k = 0; k < ncards; ++k) {
+      LdsJamp<double, PROC::NCOL, 64> jamp{lds_jamp + lane};
+      PROC::template jamps_grouped<double>(P, PROC::good(ih), cards[k].d, jamp);
+      const double hm = double(PROC::template colour_sum<double>(jamp));
+      double m0 = 0.0, m1 = 0.0;
+      for (int h = 0; h < NG / 2; ++h) m0 += __shfl(hm, h);
+      for (int h = NG / 2; h < NG; ++h) m1 += __shfl(hm, h);
+      double me = m0;
+      me += m1;
+      me *= PROC::AVERAGE;
+      if (lane == 0) {
+        if (me_out) me_out[int64_t(k) * nevt + i] = me;
+        if (w_out) {
+          if (k == 0) {
+            norm = (me == 0.0 ? 0.0 : 1.0 / me) * w_in[i];
+          } else {
+            w_out[int64_t(k - 1) * nevt + i] = norm * me;
+          }
+        }
+      }
+    }
+  }
+}
+
 template <class PROC, class R, class CT, bool GUARD = false, bool INDEXED = false>
 inline hipError_t launch_me_t(const double* soa, int64_t nevt, const CardPair* cards, int ncards,
                               const double* w_in, double* w_out, double* me_out, hipStream_t s,
@@ -251,8 +305,9 @@ inline hipError_t launch_me_t(const double* soa, int64_t nevt, const CardPair* c
 
 // Mixed precision with the cancellation guard: the float-amplitude kernel
 // flags the events whose kappa exceeds g.kmax (g.kmax < 0: none, kappa only),
-// then the double-precision kernel re-evaluates the flagged events in place
-// (one workgroup per event group of the whole range; groups past the flagged
+// then double precision re-evaluates the flagged events in place: one wave
+// per event and a lane per helicity for many-flow processes (me_wave_kernel),
+// else the one-lane-per-event kernel over the list (groups past the flagged
 // count leave at once).
 template <class PROC>
 inline hipError_t launch_me_guarded_t(int precision, const double* soa, int64_t nevt, const CardPair* cards,
@@ -266,10 +321,17 @@ inline hipError_t launch_me_guarded_t(int precision, const double* soa, int64_t 
       : launch_me_t<PROC, float, std::conditional_t<many, _Float16, void>, true>(soa, nevt, cards, ncards, w_in,
                                                                                  w_out, me_out, s, g);
   if (e != hipSuccess || g.kmax < 0.0 || !g.flagged || !g.nflagged) return e;
-  GuardArgs gi;
-  gi.rows = g.flagged;
-  gi.nrows = g.nflagged;
-  return launch_me_t<PROC, double, void, false, true>(soa, nevt, cards, ncards, w_in, w_out, me_out, s, gi);
+  if constexpr (hel_split<PROC>() > 1) {
+    const int64_t blocks = nevt < 4096 ? nevt : 4096;
+    hipLaunchKernelGGL(me_wave_kernel<PROC>, dim3(unsigned(blocks)), dim3(64), 0, s, soa, nevt, cards, ncards, w_in,
+                       w_out, me_out, g.flagged, g.nflagged);
+    return hipGetLastError();
+  } else {
+    GuardArgs gi;
+    gi.rows = g.flagged;
+    gi.nrows = g.nflagged;
+    return launch_me_t<PROC, double, void, false, true>(soa, nevt, cards, ncards, w_in, w_out, me_out, s, gi);
+  }
 }
 
 // Precision dispatch: FP64; or float amplitudes with the colour sum on the

@@ -24,6 +24,7 @@ struct FeatureMap {
   int npart = 0;
   int res_a = 2, res_b = 3;            // the resonant pair of the propagator features
   double mz0 = 0.0, wz0 = 0.0;         // original card's Z mass and width
+  int ncards = 0x7fffffff;             // card indices at or beyond this (or < 0) give NaN features
 };
 
 inline int feature_count(int kind, int npart) {

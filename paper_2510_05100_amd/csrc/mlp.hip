@@ -499,12 +499,17 @@ __global__ __launch_bounds__(256) void features_k(const FeatureMap fm, const dou
   float f[kMlpMaxIn];
   if (r < n) {
     const int64_t e = ev ? int64_t(ev[r]) : r;
-    const int c = cidx[r];
+    const int c0 = cidx[r];
+    const bool ok = c0 >= 0 && c0 < fm.ncards;           // an index out of range reads card 0, gives NaN
+    const int c = ok ? c0 : 0;
     double p[NPART * 4];
     load_event<NPART>(mom, e, p);
     const float card[3] = {cpar[3 * c], cpar[3 * c + 1], cpar[3 * c + 2]};
     feature_row<NPART, KIND>(fm, p, card, f);
     standardise(f, mean, istd);
+    if (!ok)
+#pragma unroll
+      for (int k = 0; k < kMlpMaxIn; ++k) f[k] = __builtin_nanf("");
   } else {
 #pragma unroll
     for (int k = 0; k < kMlpMaxIn; ++k) f[k] = 0.0f;
@@ -649,12 +654,17 @@ __device__ __forceinline__ void infer_rows(const InferArgs& a, const InferWeight
   float f[kMlpMaxIn];
   {
     const int64_t e = a.ev ? int64_t(a.ev[rr]) : rr;
-    const int c = a.cidx[rr];
+    const int c0 = a.cidx[rr];
+    const bool ok = c0 >= 0 && c0 < a.fm.ncards;         // an index out of range reads card 0, gives NaN
+    const int c = ok ? c0 : 0;
     double p[NPART * 4];
     load_event<NPART>(a.mom, e, p);
     const float card[3] = {a.cpar[3 * c], a.cpar[3 * c + 1], a.cpar[3 * c + 2]};
     feature_row<NPART, KIND>(a.fm, p, card, f);
     standardise(f, a.mean, a.istd);
+    if (!ok)
+#pragma unroll
+      for (int k = 0; k < kMlpMaxIn; ++k) f[k] = __builtin_nanf("");
   }
   // this lane's half of the inputs (a bitwise blend, so that the choice does
   // not become a lane-dependent index into f)

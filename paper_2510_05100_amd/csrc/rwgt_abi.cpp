@@ -294,7 +294,7 @@ int run(rwgt_ctx* c, bool reweight, const double* momenta, int64_t nevt, const d
   if (!momenta) return c->fail(RWGT_EINVAL, "momenta is NULL");
   if (reweight && !w_in) return c->fail(RWGT_EINVAL, "weights_in is NULL");
   if (reweight && !w_out) return c->fail(RWGT_EINVAL, "weights_out is NULL");
-  if (!reweight && !me_out) return c->fail(RWGT_EINVAL, "me2_out is NULL");
+  if (!reweight && !me_out && !kappa_out) return c->fail(RWGT_EINVAL, "me2_out is NULL");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return c->hip_fail(e, "hipSetDevice");
   rc = ensure_buffers(c, nevt, int(cards.size()));
@@ -1230,9 +1230,10 @@ int rwgt_eval_cards(rwgt_ctx* c, const double* momenta, int64_t nevt, const doub
     if (rc != RWGT_OK) return rc;
     hipError_t e = rwgt::launch_exact_list(rwgt::kFamilyElectroweak,
                                            c->precision == RWGT_FP64 ? rwgt::kPrecFP64 : rwgt::kPrecMixedFP16, proc,
-                                           momenta, nullptr, nullptr, nevt, card_index, c->sur_cards, w_in, w_out,
-                                           16 * compute_units(c->device), c->stream);
-    return e == hipSuccess ? RWGT_OK : c->hip_fail(e, "card-per-event evaluation");
+                                           momenta, nullptr, nullptr, nevt, card_index, ncards, c->sur_cards, w_in,
+                                           w_out, 16 * compute_units(c->device), c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "card-per-event evaluation");
+    return count_nonfinite(c, w_out, nevt);
   } catch (const std::exception& ex) {
     return c->fail(RWGT_ENOMEM, ex.what());
   }
@@ -1247,7 +1248,6 @@ int rwgt_sur_eval(rwgt_ctx* c, rwgt_mlp* m, const double* momenta, int64_t nevt,
   if (nevt < 0 || ncards < 1 || !param_table) return c->fail(RWGT_EINVAL, "bad sizes or NULL param_table");
   const int proc = family_index(c->def->id);
   if (proc < 0) return c->fail(RWGT_EPROCESS, "the surrogate path covers the electroweak family");
-  constexpr int kNparam = rwgt::kMlpCardParams;              // M_Z, Gamma_Z, sin^2 theta_W
   const int npart = c->def->npart;
   if (m->fm.npart != 0 ? m->fm.npart != npart : m->n_in != rwgt::feature_count(rwgt::kFeatRaw, npart))
     return c->fail(RWGT_EINVAL, "the network's feature map does not fit this process");
@@ -1260,14 +1260,28 @@ int rwgt_sur_eval(rwgt_ctx* c, rwgt_mlp* m, const double* momenta, int64_t nevt,
     hipStream_t st = c->stream;
     hipError_t e = hipSuccess;
     rwgt_mlp_set_stream(m, st);
+    // card indices outside [0, ncards) give NaN features, so the gate sends
+    // those events to the exact path, which writes NaN for them
+    const rwgt::FeatureMap fm_network = m->fm;
+    if (m->fm.npart == 0) {                                   // the raw map of this process
+      m->fm.kind = rwgt::kFeatRaw;
+      m->fm.npart = npart;
+    }
+    rwgt::FeatureMap fm = m->fm;
+    fm.ncards = ncards;
     if (m->fused()) {
       // one pass: features, layers, heads, gate (w' or an entry in the list)
+      m->fm = fm;
       rc = m->infer(momenta, nullptr, card_index, c->sur_cpar, nevt, nullptr, w_in, w_out, c->sur_list, c->sur_count,
                     float(threshold));
+      m->fm = fm_network;
       if (rc != RWGT_OK) return c->fail(rc, m->err);
     } else {
-      rc = rwgt_mlp_features(m, momenta, npart, nullptr, card_index, c->sur_cpar, kNparam, nevt, c->sur_x);
-      if (rc == RWGT_OK) rc = rwgt_mlp_forward(m, c->sur_x, nevt, nullptr);
+      m->fm = fm_network;
+      e = rwgt::mlp_features(fm, momenta, nullptr, card_index, c->sur_cpar, m->mean, m->istd,
+                             static_cast<float*>(c->sur_x), nevt, rows, m->layers[0].in, st);
+      if (e != hipSuccess) return c->hip_fail(e, "surrogate features");
+      rc = rwgt_mlp_forward(m, c->sur_x, nevt, nullptr);
       if (rc != RWGT_OK) return c->fail(rc, m->err);
       e = rwgt::mlp_gate(m->z.back(), 32, nevt, m->ym, m->ys, m->k_cal, float(threshold), w_in, w_out, c->sur_list,
                          c->sur_count, st);
@@ -1275,9 +1289,11 @@ int rwgt_sur_eval(rwgt_ctx* c, rwgt_mlp* m, const double* momenta, int64_t nevt,
     if (e == hipSuccess)
       e = rwgt::launch_exact_list(rwgt::kFamilyElectroweak,
                                   c->precision == RWGT_FP64 ? rwgt::kPrecFP64 : rwgt::kPrecMixedFP16, proc, momenta,
-                                  c->sur_list, c->sur_count, nevt, card_index, c->sur_cards, w_in, w_out,
+                                  c->sur_list, c->sur_count, nevt, card_index, ncards, c->sur_cards, w_in, w_out,
                                   16 * compute_units(c->device), st);
     if (e != hipSuccess) return c->hip_fail(e, "surrogate gate / exact fallback");
+    rc = count_nonfinite(c, w_out, nevt);
+    if (rc != RWGT_OK) return rc;
     if (n_fallback) {
       unsigned int cnt = 0;
       e = hipMemcpyAsync(&cnt, c->sur_count, 4, hipMemcpyDeviceToHost, st);

@@ -16,7 +16,12 @@ import numpy as np
 from . import _abi
 
 PROCESSES = ("e+ e- > mu+ mu-", "u u~ > e+ e- g", "g g > t t~ g g")
-FPTYPE = {"d": _abi.RWGT_FP64, "f": _abi.RWGT_MIXED_FP16, "m": _abi.RWGT_MIXED_FP16}
+# The reweighting card's "change fptype": d is FP64 and f single-precision
+# amplitudes (the library's mixed mode).  The paper's default m keeps the
+# amplitudes in FP64 and only the colour algebra in FP32; it runs here as FP64
+# (no FP32 amplitudes: at least as accurate, and the FP64 colour sum costs
+# about a tenth of the evaluation on these vector units).
+FPTYPE = {"d": _abi.RWGT_FP64, "f": _abi.RWGT_MIXED_FP16, "m": _abi.RWGT_FP64}
 
 
 def reweight_lhe(in_path, out_path, param_card, rwgt_card, precision=None, factored=False, running_alphas=False,
@@ -25,8 +30,8 @@ def reweight_lhe(in_path, out_path, param_card, rwgt_card, precision=None, facto
 
     param_card: SLHA text of the original card; rwgt_card: reweighting-card
     text ("launch rwgt_name=..." / "set BLOCK ID VALUE").  precision: an
-    RWGT_* constant, else the card's "change fptype" (d: FP64; f or m: mixed),
-    else FP64.  factored: use the coupling-factored path.  running_alphas:
+    RWGT_* constant, else the card's "change fptype" (d or m: FP64; f:
+    mixed), else FP64.  factored: use the coupling-factored path.  running_alphas:
     the strong coupling per event (the event's AQCDUP for the original card,
     each card's alpha_s run to the event's SCALUP; rwgt_eval_alphas).
     Returns a summary

@@ -6,8 +6,9 @@ holds at any size; sampled outputs against the oracle one by one.
 
 - g g -> t t~ g g with alpha_s 0.118 -> 0.130: every diagram carries g_s^4,
   so w'/w = (0.130/0.118)^4 on every event: FP64 to 1e-12 (as at small
-  sizes), mixed (FP16 and BF16 colour sums) to 2e-5 (the mixed path's
-  bound; FP16 measures 6.86e-6, BF16 6.88e-6).
+  sizes), mixed (FP16 and BF16 colour sums) to 1e-5, the target, with the
+  cancellation guard at its default (about 0.1 % of the events re-evaluated
+  in FP64; without it FP16 measures 6.86e-6 here and 1.05e-5 on 1e7 events).
   |M|^2 under the original card on 40 evenly spaced events against the
   oracle's Berends-Giele recursion: 1e-10 (the small-size tolerance).
 - u u~ -> e+ e- g with the M_Z, Gamma_Z, sin^2 theta_W card: w' finite and
@@ -41,7 +42,7 @@ def gg_events():
     return synth.events("gg_ttgg", N_FULL)
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 2e-5), (2, 2e-5)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5), (2, 1e-5)])
 def test_gg_ttgg_full_size(gg_events, precision, tol):
     _case("gg_ttgg", precision=precision, n=N_FULL)
     torch = torch_cuda()
@@ -55,8 +56,11 @@ def test_gg_ttgg_full_size(gg_events, precision, tol):
         assert rw.rwgt_nonfinite(r.ctx) == 0
         ratio = out.cpu().numpy()[0]
         err = np.abs(ratio / RATIO - 1.0)
-        print(f"gg_ttgg precision {precision}: max |w'/w / (0.130/0.118)^4 - 1| = {err.max():.3g}", flush=True)
+        nre = rw.rwgt_mixed_guard_count(r.ctx)
+        print(f"gg_ttgg precision {precision}: max |w'/w / (0.130/0.118)^4 - 1| = {err.max():.3g}, "
+              f"{nre} events re-evaluated in FP64 by the guard", flush=True)
         assert err.max() < tol
+        assert nre == 0 if precision == 0 else 0 < nre < 0.005 * N_FULL
         # sigma', dsigma' of the nearly constant w' against the oracle on the same weights
         from oracle import xsec as oxsec
         for dsigma in (0.3, 0.0):

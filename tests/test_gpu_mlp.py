@@ -386,3 +386,48 @@ def test_surrogate_gain_on_the_workload():
     assert summary["fallback_fraction"] < 0.5 and loose["fallback_fraction"] < 0.02
     n = summary["heldout_events"]
     assert summary["events_beyond_threshold"] <= 1e-3 * n and loose["events_beyond_threshold"] <= 1e-3 * n
+
+
+@pytest.mark.parametrize("width", [128, 96])
+def test_card_index_out_of_range(width):
+    """A card index outside [0, ncards) reads no card: rwgt_eval_cards writes
+    NaN for that event, rwgt_sur_eval sends it to the exact path (NaN inputs)
+    which writes NaN, rwgt_nonfinite counts them, and every other event is
+    unchanged.  Width 128: the fused kernel; 96: layer by layer."""
+    print(f"[case] card index out of range width={width}", flush=True)
+    torch = torch_cuda()
+    import paper_2510_05100_amd as rw
+    n = 500
+    p = synth.events("uu_eeg", n)
+    grid = synth.batch_grid()
+    table = np.stack([c.row("uu_eeg") for c in grid[:8]])
+    good = (np.arange(n) % 8).astype(np.int32)
+    bad = good.copy()
+    bad[[3, 200, 499]] = [-1, 8, 1 << 30]
+    ctx = rw.rwgt_create(PROCESS_TEXT["uu_eeg"], synth.ORIG_EW.slha(), 0)
+    kind = rw.RWGT_FEAT_PHYS
+    m = rw.rwgt_mlp_create(rw.n_features(kind, 5), width, 3, 2, 0, 1)
+    try:
+        rw.rwgt_set_stream(ctx, None)
+        rw.rwgt_mlp_set_stream(m, None)
+        rw.rwgt_mlp_set_features(m, kind, 5, (2, 3), (synth.ORIG_EW.MZ, synth.ORIG_EW.WZ))
+        pd, wd = dev(p), dev(np.ones(n))
+        ref = torch.empty(n, dtype=torch.float64, device="cuda")
+        got = torch.empty(n, dtype=torch.float64, device="cuda")
+        rw.rwgt_eval_cards(ctx, pd, wd, table, torch.as_tensor(good).cuda(), ref)
+        rw.rwgt_eval_cards(ctx, pd, wd, table, torch.as_tensor(bad).cuda(), got)
+        assert rw.rwgt_nonfinite(ctx) == 3
+        r, g = ref.cpu().numpy(), got.cpu().numpy()
+        sel = np.isin(np.arange(n), [3, 200, 499])
+        assert np.all(np.isnan(g[sel])) and np.array_equal(g[~sel], r[~sel])
+        for thr in (1e30, 0.0):                 # the network answers everything it can / nothing
+            sur = torch.empty(n, dtype=torch.float64, device="cuda")
+            nfb = rw.rwgt_sur_eval(ctx, m, pd, wd, table, torch.as_tensor(bad).cuda(), thr, sur)
+            s = sur.cpu().numpy()
+            assert rw.rwgt_nonfinite(ctx) == 3 and np.all(np.isnan(s[sel])) and np.all(np.isfinite(s[~sel]))
+            assert nfb >= 3
+            if thr == 0.0:
+                assert np.array_equal(s[~sel], r[~sel])
+    finally:
+        rw.rwgt_mlp_destroy(m)
+        rw.rwgt_destroy(ctx)

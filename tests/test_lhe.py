@@ -196,6 +196,9 @@ set RWGTEW 1 0.2312
     orig = synth.ORIG_EW
     sets, names, fp = rw.rwgt_reweight_card(PROC["uu_eeg"], orig.slha(), card)
     assert names == ["mz_up", "alpha_s", "rwgt_3"] and fp == "m"
+    # the paper's m keeps FP64 amplitudes: it runs as FP64, never on single-precision amplitudes
+    from paper_2510_05100_amd import lhe as rlhe
+    assert rlhe.FPTYPE["m"] == rw.RWGT_FP64 and rlhe.FPTYPE["d"] == rw.RWGT_FP64
     base = orig.row("uu_eeg")
     want = np.tile(base, (3, 1))
     want[0, 3], want[0, 4] = 91.5, 2.6
