@@ -303,6 +303,8 @@ def batched_leg(rw, torch, precision, steps, warmup):
     pools = {p: torch.as_tensor(synth.events(p, 200_000)).cuda() for p in procs}
     ones = torch.ones(200_000, dtype=torch.float64, device="cuda")
     ctxs = [rw.rwgt_create(texts[p], synth.ORIG_EW.slha(), precision) for p in procs]
+    for ctx in ctxs:                      # the batched form runs unguarded: compare with the unguarded plain path
+        rw.rwgt_set_mixed_guard(ctx, 0.0)
     items, plain_out = [], []
     for c, card in enumerate(grid):
         for j, p in enumerate(procs):

@@ -144,7 +144,8 @@ int rwgt_me2(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const double *p
  * above kappa_max are evaluated again, in double precision, within the same
  * rwgt_eval / rwgt_me2 call, and their outputs replaced.  kappa_max <= 0
  * turns the guard off; the default is the library's calibrated value.
- * Applies to rwgt_eval and rwgt_me2 on mixed contexts. */
+ * Applies to rwgt_eval and rwgt_me2 on mixed contexts (the batched,
+ * factored, per-event-alpha_s and card-per-event paths run unguarded). */
 int rwgt_set_mixed_guard(rwgt_ctx *ctx, double kappa_max);
 /* Events re-evaluated in double precision by the last rwgt_eval / rwgt_me2
  * call on ctx (0 if the guard did not run); waits for the stream. */

@@ -62,6 +62,8 @@ def test_batch_matches_plain_and_oracle(precision, hel_split):
     segments) equal the plain path to the bit."""
     print(f"[case] batch precision={precision} hel_split={hel_split}", flush=True)
     torch, rw, ctxs, jobs, pools = _setup(precision)
+    for c in ctxs:                             # the batched form has no cancellation guard: compare unguarded
+        rw.rwgt_set_mixed_guard(c, 0.0)
     b = rw.rwgt_batch_create(ctxs)
     try:
         segs, keep = _segments(rw, jobs)
@@ -77,15 +79,15 @@ def test_batch_matches_plain_and_oracle(precision, hel_split):
             torch.cuda.synchronize()
             got = job["out"].cpu().numpy()
             assert np.array_equal(got, ref.cpu().numpy()[0])
-        if precision == 0:
-            for job in jobs[:4]:
-                if job["n"] == 0:
-                    continue
-                idx = np.arange(0, job["n"], max(1, job["n"] // 40))
-                want, _, _ = reweight.reweight(job["proc"], pools[job["proc"]][idx], job["w"][idx],
-                                               synth.ORIG_EW, [job["card"]])
-                bar = 1e-12 if job["proc"] == "ee_mumu" else 1e-11
-                assert np.max(rel_err(job["out"].cpu().numpy()[idx], want[0])) < bar
+        # sampled events against the oracle: FP64 at the parity bars, mixed at 1e-5 (w' target)
+        for job in jobs[:4]:
+            if job["n"] == 0:
+                continue
+            idx = np.arange(0, job["n"], max(1, job["n"] // 40))
+            want, _, _ = reweight.reweight(job["proc"], pools[job["proc"]][idx], job["w"][idx],
+                                           synth.ORIG_EW, [job["card"]])
+            bar = 1e-5 if precision else (1e-12 if job["proc"] == "ee_mumu" else 1e-11)
+            assert np.max(rel_err(job["out"].cpu().numpy()[idx], want[0])) < bar
     finally:
         rw.rwgt_batch_destroy(b)
         for c in ctxs:
