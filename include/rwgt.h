@@ -198,6 +198,19 @@ int rwgt_flops(const rwgt_ctx *ctx, double *flops_per_me2);
 int rwgt_xsec(rwgt_ctx *ctx, const double *weights_in, const double *weights_out, int64_t nevt, int32_t nsets,
               double sigma, double dsigma, double norm, double *xsec, double *xerr, int32_t *fallback);
 
+/* rwgt_xsec for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result bit for bit, with the partial sums in a
+ * static device array of the library (about 790 KB per GPU, held until the
+ * process ends) instead of per-call allocations.  At most 64 cards
+ * (nsets > 64: RWGT_EINVAL).  The array is shared by every call on a GPU:
+ * calls that overlap on one GPU (two host threads, or two streams) race and
+ * must be serialised by the caller.  Nothing in the array needs clearing (each
+ * call writes every partial it reads).  Errors as rwgt_xsec. */
+int rwgt_xsec_noalloc(rwgt_ctx *ctx, const double *weights_in, const double *weights_out, int64_t nevt,
+                      int32_t nsets, double sigma, double dsigma, double norm, double *xsec, double *xerr,
+                      int32_t *fallback);
+
 /* Record HIP events around the ingest and matrix-element kernels of each
  * subsequent rwgt_eval / rwgt_me2 (on the context's stream). */
 int rwgt_set_profiling(rwgt_ctx *ctx, int enable);

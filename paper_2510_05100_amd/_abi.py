@@ -171,6 +171,7 @@ SIGNATURES["rwgt_xsec"] = (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctyp
                                           ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int32)])
+SIGNATURES["rwgt_xsec_noalloc"] = SIGNATURES["rwgt_xsec"]
 
 _lib = None
 
@@ -657,15 +658,16 @@ def rwgt_sur_eval(ctx, mlp, momenta, weights_in, param_table, card_index, err_th
     return nfb.value
 
 
-def rwgt_xsec(ctx, weights_in, weights_out, sigma, dsigma, norm):
-    """(sigma'[k], dsigma'[k], fallback[k]) for weights_out [nsets, nevt]."""
+def rwgt_xsec(ctx, weights_in, weights_out, sigma, dsigma, norm, entry="rwgt_xsec"):
+    """(sigma'[k], dsigma'[k], fallback[k]) for weights_out [nsets, nevt]
+    (entry "rwgt_xsec_noalloc": the same through the no-allocation entry point)."""
     _check_device(weights_in, "weights_in")
     _check_device(weights_out, "weights_out")
     nsets, nevt = weights_out.shape
     xs = np.zeros(nsets)
     xe = np.zeros(nsets)
     fb = np.zeros(nsets, dtype=np.int32)
-    rc = load().rwgt_xsec(ctx, _dp(weights_in), _dp(weights_out), nevt, nsets, sigma, dsigma, norm,
+    rc = getattr(load(), entry)(ctx, _dp(weights_in), _dp(weights_out), nevt, nsets, sigma, dsigma, norm,
                           xs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                           xe.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                           fb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -770,6 +771,75 @@ int rwgt_xsec(rwgt_ctx* ctx, const double* weights_in, const double* weights_out
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (part) hipFree(part);
   if (out) hipFree(out);
+  if (e != hipSuccess) return ctx->hip_fail(e, "cross-section reduction");
+  for (int32_t k = 0; k < nsets; ++k) {
+    xsec[k] = host[k * 3];
+    xerr[k] = host[k * 3 + 1];
+    if (fallback) fallback[k] = host[k * 3 + 2] != 0.0;
+    if (host[k * 3 + 2] != 0.0)
+      std::fprintf(stderr, "rwgt: error propagation for card %d gave no positive finite value; "
+                           "using dsigma * max(sigma'/sigma, sigma/sigma')\n", int(k));
+  }
+  return RWGT_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ rwgt_xsec without allocation
+// Scratch of rwgt_xsec_noalloc: the two passes' block partials and the
+// per-card sums and results for up to kXsecStaticSets cards, in a static
+// device array (each GPU holds its own copy until the process ends).  Host
+// code reaches it only through the address hipGetSymbolAddress returns on
+// that device (the array's name is a host-side stand-in there).
+namespace {
+constexpr int kXsecStaticBlocks = 512;
+constexpr int kXsecStaticSets = 64;
+constexpr size_t kXsecStaticDoubles = size_t(kXsecStaticSets) * (3 * kXsecStaticBlocks + 3) + 3 * kXsecStaticSets;
+__device__ __align__(256) double scratch[kXsecStaticDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's device address on the current device (looked up once
+// per device).
+hipError_t static_scratch(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
+int rwgt_xsec_noalloc(rwgt_ctx* ctx, const double* weights_in, const double* weights_out, int64_t nevt,
+                      int32_t nsets, double sigma, double dsigma, double norm, double* xsec, double* xerr,
+                      int32_t* fallback) {
+  if (!ctx) return RWGT_EINVAL;
+  ctx->err.clear();
+  if (nevt < 1 || nsets < 1 || !weights_in || !weights_out || !xsec || !xerr)
+    return ctx->fail(RWGT_EINVAL, "bad arguments");
+  if (nsets > kXsecStaticSets)
+    return ctx->fail(RWGT_EINVAL, "nsets exceeds the static scratch of rwgt_xsec_noalloc (64 cards)");
+  double* base = nullptr;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = static_scratch(ctx->device, &base);
+  if (e != hipSuccess) return ctx->hip_fail(e, "static scratch address");
+  double* part = base;                                                  // nsets * (3 nblocks + 3)
+  double* out = base + size_t(nsets) * (3 * kXsecStaticBlocks + 3);     // nsets * 3
+  e = rwgt::launch_xsec(weights_in, weights_out, nevt, nsets, sigma, dsigma, norm, part, kXsecStaticBlocks, out,
+                        ctx->stream);
+  double host[3 * kXsecStaticSets];
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(host, out, size_t(nsets) * 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return ctx->hip_fail(e, "cross-section reduction");
   for (int32_t k = 0; k < nsets; ++k) {
     xsec[k] = host[k * 3];
