@@ -241,11 +241,30 @@ def cpu_oracle(p, sample, workers):
     return res
 
 
+def host_cpu():
+    """(CPU model, logical CPUs of the host, CPUs this process may use)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return model, os.cpu_count() or 1, usable
+
+
 def cpu_baseline(res, total, gpu_w):
     """The cpu_baseline object: the all-cores rate when it was measured (else
     the single-core one), with the single-core figure beside it, and the
-    sampled parity of the GPU path against the oracle."""
+    sampled parity of the GPU path against the oracle.  The all-cores run
+    uses one single-thread process per core of this process's CPU share
+    (capped by --cpu-workers, 16 by default: the host share of one GPU)."""
     idx, w = res["idx"], res["w"]
+    model, logical, usable = host_cpu()
+    host = {"cpu_model": model, "host_logical_cpus": logical, "cpus_usable_by_this_process": usable}
     parity = float(np.max(np.abs(gpu_w[0, idx] / w - 1.0)))
     single = (f"single core: {idx.size} events (evenly spaced) in {res['single_s']:.1f} s, "
               f"{res['single']:.1f} reweighted events/s")
@@ -254,11 +273,11 @@ def cpu_baseline(res, total, gpu_w):
                 "sample": f"{res['multi_sample']} of the {total} g g -> t t~ g g events (evenly spaced), original + "
                           f"1 new card, FP64 numpy Berends-Giele oracle, {res['workers']} processes of one thread "
                           f"each, {res['multi_s']:.1f} s; {single}",
-                "single_core_value": res["single"], "gpu_vs_oracle_max_rel_err": parity}
+                "single_core_value": res["single"], "gpu_vs_oracle_max_rel_err": parity, **host}
     return {"value": res["single"], "unit": "reweighted events/s", "cores": 1, "kind": "oracle",
             "sample": f"{idx.size} of the {total} g g -> t t~ g g events (evenly spaced), original + 1 new card, "
                       f"FP64 numpy Berends-Giele oracle, single thread, {res['single_s']:.1f} s",
-            "single_core_value": res["single"], "gpu_vs_oracle_max_rel_err": parity}
+            "single_core_value": res["single"], "gpu_vs_oracle_max_rel_err": parity, **host}
 
 
 def pcie_inclusive(rw, torch, p, rows, events, steps):
@@ -397,7 +416,7 @@ def main():
     log(f"generated {a.events} events in {time.perf_counter() - t:.1f}s")
     oracle_res = None
     if not a.no_cpu_baseline:                 # host cores first, before any GPU state exists
-        oracle_res = cpu_oracle(p, a.cpu_sample, max(1, min(a.cpu_workers, os.cpu_count() or 1)))
+        oracle_res = cpu_oracle(p, a.cpu_sample, max(1, min(a.cpu_workers, host_cpu()[2])))
         log(f"oracle: {oracle_res['single']:.1f} events/s on one core" +
             (f", {oracle_res['multi']:.1f} on {oracle_res['workers']}" if "multi" in oracle_res else ""))
     import torch
