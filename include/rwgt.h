@@ -16,9 +16,10 @@
  *
  * Conventions shared by every entry point:
  *  - momenta: [nevt][npart][4] doubles (E, px, py, pz) in GeV, particle order
- *    as in the process string, incoming first, DEVICE memory;
+ *    as in the process string, incoming first, DEVICE memory (rwgt_eval and
+ *    rwgt_me2 also take host memory, see there);
  *  - weights_in [nevt], weights_out [nsets][nevt], me2_out [nsets][nevt]:
- *    doubles in DEVICE memory;
+ *    doubles in DEVICE memory (host memory as for momenta);
  *  - param_sets [nsets][npar]: doubles in HOST memory, one row per new card,
  *    columns in the order reported by rwgt_param_layout;
  *  - the caller owns every array; the library never frees caller memory;
@@ -94,6 +95,15 @@ int rwgt_set_stream(rwgt_ctx *ctx, void *stream);
 
 /* Reweight: weights_out[k][i] = (weights_in[i] * (1/|M|^2_orig[i])) * |M|^2_k[i]
  * for the nsets cards in param_sets.  nevt = 0 is a no-op.
+ * momenta, weights_in and weights_out may each be memory of the context's
+ * device or host memory (told apart with hipPointerGetAttributes): host
+ * arrays, and other devices' memory, are copied through a device staging
+ * buffer that the context keeps (grown as needed, freed by rwgt_destroy) on
+ * the context's stream.  Pinned host memory (hipHostMalloc) keeps the call
+ * asynchronous: synchronise the stream before reading a host weights_out or
+ * reusing a host input.  With any pageable host array the call waits for the
+ * stream before it returns, outputs copied back.  The device path is the same
+ * either way, so results are equal bit for bit.
  * Errors: RWGT_EINVAL, RWGT_EPARAM, RWGT_EDEVICE, RWGT_ENOMEM. */
 int rwgt_eval(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const double *weights_in,
               const double *param_sets, int32_t nsets, double *weights_out);
@@ -129,7 +139,8 @@ int rwgt_eval_alphas(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const d
 /* |M|^2 itself for each card of param_sets: me2_out[k][i] -- the weight
  * function of parameter reweighting, which is also its normaliser under the
  * original card (MadtRex section, Backend details; Tensorial event adaption
- * section, Generic reweighting).  Same rules as rwgt_eval. */
+ * section, Generic reweighting).  Same rules as rwgt_eval, host arrays
+ * included. */
 int rwgt_me2(rwgt_ctx *ctx, const double *momenta, int64_t nevt, const double *param_sets, int32_t nsets,
              double *me2_out);
 

@@ -201,6 +201,16 @@ def _ptr(t):
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
 
+def _check_f64(t, name):
+    """A contiguous float64 torch tensor in device or host memory (rwgt_eval
+    and rwgt_me2 copy host arrays through the library's staging buffer)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 tensor")
+
+
 def _check_device(t, name, shape_prefix=None):
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
@@ -268,10 +278,12 @@ def rwgt_set_stream(ctx, stream=None):
 
 
 def rwgt_eval(ctx, momenta, weights_in, param_sets, weights_out):
-    """weights_out[k, i] = weights_in[i] / |M|^2_orig[i] * |M|^2_k[i] (enqueued on the set stream)."""
-    _check_device(momenta, "momenta")
-    _check_device(weights_in, "weights_in")
-    _check_device(weights_out, "weights_out")
+    """weights_out[k, i] = weights_in[i] / |M|^2_orig[i] * |M|^2_k[i] (enqueued on the set stream).
+    Tensors on the GPU or in host memory (pinned: still asynchronous;
+    pageable: the call waits)."""
+    _check_f64(momenta, "momenta")
+    _check_f64(weights_in, "weights_in")
+    _check_f64(weights_out, "weights_out")
     nevt = momenta.shape[0] if momenta.dim() > 0 else 0
     params, pptr = _host_params(param_sets)
     if weights_out.numel() != params.shape[0] * nevt or weights_in.numel() != nevt:
@@ -316,8 +328,9 @@ def rwgt_eval_factored(ctx, momenta, weights_in, param_sets, weights_out):
 
 
 def rwgt_me2(ctx, momenta, param_sets, me2_out):
-    _check_device(momenta, "momenta")
-    _check_device(me2_out, "me2_out")
+    """me2_out[k, i] = |M|^2_k[i]; tensors on the GPU or in host memory, as rwgt_eval."""
+    _check_f64(momenta, "momenta")
+    _check_f64(me2_out, "me2_out")
     nevt = momenta.shape[0]
     params, pptr = _host_params(param_sets)
     if me2_out.numel() != params.shape[0] * nevt:

@@ -186,6 +186,10 @@ struct rwgt_ctx {
   unsigned int* guard_count = nullptr;
   int64_t guard_cap = 0;
   bool guard_ran = false;                  // the last evaluation ran the guard
+  // device copies of caller arrays that live in host memory (rwgt_eval,
+  // rwgt_me2): momenta, then weights in, then outputs
+  double* stage = nullptr;
+  size_t stage_bytes = 0;
   // non-finite outputs of the last evaluation: per-block counts on the device
   unsigned long long* nf_part = nullptr;
   unsigned long long* nf_host = nullptr;   // pinned
@@ -211,7 +215,7 @@ struct rwgt_ctx {
     for (void* p : {sur_x, static_cast<void*>(sur_list), static_cast<void*>(sur_count), static_cast<void*>(sur_heads),
                     static_cast<void*>(sur_cards), static_cast<void*>(sur_cpar), static_cast<void*>(fac_probe),
                     static_cast<void*>(fac_cards), static_cast<void*>(as_cards), static_cast<void*>(nf_part),
-                    static_cast<void*>(guard_list), static_cast<void*>(guard_count)})
+                    static_cast<void*>(guard_list), static_cast<void*>(guard_count), static_cast<void*>(stage)})
       if (p) hipFree(p);
     if (nf_host) hipHostFree(nf_host);
   }
@@ -356,6 +360,88 @@ int count_nonfinite(rwgt_ctx* c, const double* out, int64_t n) {
   return RWGT_OK;
 }
 
+// Where a caller array lives.  Memory of this context's device (device or
+// managed allocations) is used in place (kHere); anything else is copied
+// through the context's staging buffer: pinned host memory and other devices'
+// memory asynchronously on the stream (kCopy), pageable host memory the same
+// way but with the call waiting for its stream before it returns (kCopyWait).
+enum class Mem { kHere, kCopy, kCopyWait };
+
+Mem where(const rwgt_ctx* c, const void* p) {
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();                     // older runtimes reject unregistered host memory
+    return Mem::kCopyWait;
+  }
+  const bool dev = a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+  if (dev && a.device == c->device) return Mem::kHere;
+  return dev || a.type == hipMemoryTypeHost ? Mem::kCopy : Mem::kCopyWait;
+}
+
+// The caller's momenta, input weights and output of one rwgt_eval / rwgt_me2
+// call, replaced by staging-buffer addresses where they are not device memory
+// of this context; finish() copies the output back.
+struct Staged {
+  const double* mom;
+  const double* w_in;
+  double* out;
+  double* out_host = nullptr;                    // caller's output, when staged
+  size_t out_bytes = 0;
+  bool wait = false;                             // some array is pageable host memory
+
+  int begin(rwgt_ctx* c, int64_t nevt, int64_t nout) {
+    if (nevt <= 0 || !mom || !out) return RWGT_OK;   // run() reports the errors
+    const size_t mbytes = size_t(nevt) * size_t(c->def->npart) * 4 * sizeof(double);
+    const size_t wbytes = size_t(nevt) * sizeof(double);
+    const size_t obytes = size_t(nout) * sizeof(double);
+    const Mem wm = where(c, mom), ww = w_in ? where(c, w_in) : Mem::kHere, wo = where(c, out);
+    if (wm == Mem::kHere && ww == Mem::kHere && wo == Mem::kHere) return RWGT_OK;
+    wait = wm == Mem::kCopyWait || ww == Mem::kCopyWait || wo == Mem::kCopyWait;
+    const size_t need = (wm != Mem::kHere ? mbytes : 0) + (ww != Mem::kHere ? wbytes : 0) +
+                        (wo != Mem::kHere ? obytes : 0);
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return c->hip_fail(e, "hipSetDevice");
+    if (need > c->stage_bytes) {
+      if (c->stage) {
+        e = hipStreamSynchronize(c->stream);   // earlier calls may still read it
+        if (e != hipSuccess) return c->hip_fail(e, "hipStreamSynchronize");
+        hipFree(c->stage);
+        c->stage = nullptr;
+        c->stage_bytes = 0;
+      }
+      e = hipMalloc(&c->stage, need);
+      if (e != hipSuccess) return c->hip_fail(e, "hipMalloc(staging)");
+      c->stage_bytes = need;
+    }
+    char* at = reinterpret_cast<char*>(c->stage);
+    if (wm != Mem::kHere) {
+      e = hipMemcpyAsync(at, mom, mbytes, hipMemcpyDefault, c->stream);
+      if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync(momenta)");
+      mom = reinterpret_cast<const double*>(at);
+      at += mbytes;
+    }
+    if (ww != Mem::kHere) {
+      e = hipMemcpyAsync(at, w_in, wbytes, hipMemcpyDefault, c->stream);
+      if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync(weights_in)");
+      w_in = reinterpret_cast<const double*>(at);
+      at += wbytes;
+    }
+    if (wo != Mem::kHere) {
+      out_host = out;
+      out_bytes = obytes;
+      out = reinterpret_cast<double*>(at);
+    }
+    return RWGT_OK;
+  }
+
+  int finish(rwgt_ctx* c) {
+    hipError_t e = hipSuccess;
+    if (out_host) e = hipMemcpyAsync(out_host, out, out_bytes, hipMemcpyDefault, c->stream);
+    if (e == hipSuccess && wait) e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? RWGT_OK : c->hip_fail(e, "copy of the output to host memory");
+  }
+};
+
 }  // namespace
 
 extern "C" {
@@ -421,8 +507,12 @@ int rwgt_eval(rwgt_ctx* ctx, const double* momenta, int64_t nevt, const double* 
   ctx->err.clear();
   try {
     ctx->nf_blocks = 0;
-    const int rc = run(ctx, true, momenta, nevt, weights_in, param_sets, nsets, weights_out, nullptr);
-    return rc == RWGT_OK ? count_nonfinite(ctx, weights_out, int64_t(nsets) * nevt) : rc;
+    if (nsets < 1) return ctx->fail(RWGT_EINVAL, "nsets < 1");
+    Staged st{momenta, weights_in, weights_out};
+    int rc = st.begin(ctx, nevt, int64_t(nsets) * nevt);
+    if (rc == RWGT_OK) rc = run(ctx, true, st.mom, nevt, st.w_in, param_sets, nsets, st.out, nullptr);
+    if (rc == RWGT_OK) rc = count_nonfinite(ctx, st.out, int64_t(nsets) * nevt);
+    return rc == RWGT_OK ? st.finish(ctx) : rc;
   } catch (const std::exception& ex) {
     return ctx->fail(RWGT_ENOMEM, ex.what());
   }
@@ -580,8 +670,12 @@ int rwgt_me2(rwgt_ctx* ctx, const double* momenta, int64_t nevt, const double* p
   ctx->err.clear();
   try {
     ctx->nf_blocks = 0;
-    const int rc = run(ctx, false, momenta, nevt, nullptr, param_sets, nsets, nullptr, me2_out);
-    return rc == RWGT_OK ? count_nonfinite(ctx, me2_out, int64_t(nsets) * nevt) : rc;
+    if (nsets < 1) return ctx->fail(RWGT_EINVAL, "nsets < 1");
+    Staged st{momenta, nullptr, me2_out};
+    int rc = st.begin(ctx, nevt, int64_t(nsets) * nevt);
+    if (rc == RWGT_OK) rc = run(ctx, false, st.mom, nevt, nullptr, param_sets, nsets, nullptr, st.out);
+    if (rc == RWGT_OK) rc = count_nonfinite(ctx, st.out, int64_t(nsets) * nevt);
+    return rc == RWGT_OK ? st.finish(ctx) : rc;
   } catch (const std::exception& ex) {
     return ctx->fail(RWGT_ENOMEM, ex.what());
   }
