@@ -104,9 +104,69 @@ hipError_t mlp_gather_pairs(const Shuffle& sh, int64_t pos0, int64_t n, int64_t 
 hipError_t mlp_log_ratio(const double* w_new, const double* w_old, float* y, int64_t n, hipStream_t s);
 hipError_t mlp_gate(const float* z, int ld, int64_t n, float ym, float ys, float k_cal, float threshold,
                     const double* w_in, double* w_out, int32_t* list, unsigned int* count, hipStream_t s);
+// Packed operand order of the fused kernels (pack_pos in mlp.hip); with
+// transposed, W^T is packed: rows_used / cols_used then count rows and
+// columns of W^T (element (row, col) = w[col * ld + row]).
 hipError_t mlp_pack(const float* w, int ld, int rows_used, int cols_used, int nblocks, int nchunks, void* hi,
-                    void* lo, hipStream_t s);
+                    void* lo, hipStream_t s, bool transposed = false);
 hipError_t mlp_infer(int width, const InferArgs& a, hipStream_t s);
+
+// Fused training step of the networks the fused inference kernel runs (two
+// heads).  mlp_train_grads: every row tile's inputs, forward and backward
+// pass, and per workgroup the sums over its rows of every gradient (and of
+// the loss) into its slot of part; mlp_train_update: those sums added in
+// workgroup order into the gradient buffers, then (adam) the Adam step and
+// every copy of each new parameter.
+constexpr int kTrainMaxLayers = kMlpMaxHidden + 2;
+constexpr int kTrainMaxGroups = 256;   // workgroups of one step (more tiles: each takes several)
+struct TrainArgs {
+  const float* x = nullptr;            // input rows [rows][32] (NULL: pairs of a card-major grid)
+  const float* y = nullptr;            // their targets [rows]
+  Shuffle sh;                          // pairs: positions pos0 .. pos0 + n - 1 of this order
+  int64_t pos0 = 0;
+  int64_t nevt = 0;                    // events of the grid (pair j: event j % nevt, card j / nevt)
+  const double* mom = nullptr;
+  const float* cpar = nullptr;
+  const float* ygrid = nullptr;        // targets per pair
+  FeatureMap fm;
+  const float* mean = nullptr;
+  const float* istd = nullptr;
+  int64_t n = 0;                       // rows of the step (the loss averages over them)
+  int64_t rows = 0;                    // readable rows of x
+  const void* w0hi = nullptr;          // packed weights as InferArgs
+  const void* w0lo = nullptr;
+  const float* b0 = nullptr;
+  const void* wh = nullptr;
+  const void* wht = nullptr;           // the hidden layers' W^T in the same packed order
+  const float* bh = nullptr;
+  int nh = 0;
+  const float* whead = nullptr;        // FP32 [32][width], rows 0 and 1 used
+  const float* bhead = nullptr;
+  float lambda = 0.0f, ym = 0.0f, ys = 1.0f;
+  float* zws = nullptr;                // pre-activations, train_zws_floats(width, nh) per workgroup
+  float* part = nullptr;               // [workgroups][pstride]: gradient sums, then the loss at [total]
+  int64_t pstride = 0;
+  int64_t total = 0;                   // parameters (the Adam segments concatenated)
+  int64_t off_w[kTrainMaxLayers] = {}; // begin of each layer's W and b segment
+  int64_t off_b[kTrainMaxLayers] = {};
+  int tiles = 0;                       // row tiles (train_tile_rows(width) rows each)
+  int groups = 0;                      // workgroups (at most kTrainMaxGroups)
+};
+int train_tile_rows(int width);
+int64_t train_zws_floats(int width, int nh);
+hipError_t mlp_train_grads(int width, const TrainArgs& a, hipStream_t s);
+// Per Adam segment: the packed copies of the parameter to refresh (NULL: none).
+struct PackSeg {
+  float* grad = nullptr;               // the gradient buffer (written with the sums)
+  void* hi = nullptr;                  // packed forward order (BF16), nchunks of 16 columns
+  void* lo = nullptr;                  // its low parts (first layer)
+  void* tr = nullptr;                  // packed transposed order
+  int nchunks = 0, tchunks = 0;
+  float* bias = nullptr;               // contiguous hidden-layer biases
+};
+hipError_t mlp_train_update(const AdamSeg* segs, const PackSeg* pk, int nseg, int64_t total, const float* part,
+                            int groups, int64_t pstride, float* loss, int adam, float lr, float b1, float b2,
+                            float eps, float c1, float c2, hipStream_t s);
 // sums[0..ld) += column sums of x [n][ld], sums[ld..2ld) += sums of squares
 // (FP64); clear: zero sums first.
 hipError_t mlp_moments(const float* x, int64_t n, int ld, double* sums, bool clear, hipStream_t s);

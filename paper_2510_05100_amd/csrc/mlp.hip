@@ -569,13 +569,21 @@ __global__ __launch_bounds__(256) void log_ratio_k(const double* __restrict__ w_
   y[i] = o != 0.0 ? float(log(w_new[i] / o)) : 0.0f;
 }
 
-// A-operand order of the fused kernel: block b of 32 output rows, chunk c of
-// 16 inputs, lane l, slot s holds W[32 b + l % 32][16 c + 8 (s / 4) + 4 (l / 32) + s % 4]
+// A-operand order of the fused kernels: block b of 32 output rows, chunk c
+// of 16 inputs, lane l, slot s holds W[32 b + l % 32][16 c + 8 (s / 4) + 4 (l / 32) + s % 4]
 // (the order in which a wave's accumulators come out, so one layer's output
 // is the next layer's B operand without moving data between lanes).  hi is
 // the BF16 rounding of W, lo (optional) the BF16 rounding of the remainder.
+// transposed: the matrix packed is W^T (element (row, col) = w[col][row]).
+__host__ __device__ __forceinline__ int64_t pack_pos(int row, int col, int nchunks) {
+  const int o = col & 15;
+  const int lane = (row & 31) + 32 * ((o & 7) >> 2), slot = 4 * (o >> 3) + (o & 3);
+  return ((int64_t(row >> 5) * nchunks + (col >> 4)) * 64 + lane) * 8 + slot;
+}
+
 __global__ __launch_bounds__(256) void pack_k(const float* __restrict__ w, int ld, int rows_used, int cols_used,
-                                              int nblocks, int nchunks, bf16* __restrict__ hi, bf16* __restrict__ lo) {
+                                              int nblocks, int nchunks, bf16* __restrict__ hi, bf16* __restrict__ lo,
+                                              int transposed) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= int64_t(nblocks) * nchunks * 512) return;
   const int s = int(t & 7), l = int((t >> 3) & 63);
@@ -583,7 +591,8 @@ __global__ __launch_bounds__(256) void pack_k(const float* __restrict__ w, int l
   const int c = int(q % nchunks), b = int(q / nchunks);
   const int row = 32 * b + (l & 31);
   const int col = 16 * c + 8 * (s >> 2) + 4 * (l >> 5) + (s & 3);
-  const float v = (row < rows_used && col < cols_used) ? w[size_t(row) * ld + col] : 0.0f;
+  float v = 0.0f;
+  if (row < rows_used && col < cols_used) v = transposed ? w[size_t(col) * ld + row] : w[size_t(row) * ld + col];
   const bf16 vh = bf16(v);
   hi[t] = vh;
   if (lo) lo[t] = bf16(v - float(vh));
@@ -809,6 +818,491 @@ __global__ __launch_bounds__(256, W == 128 ? 4 : 1) void infer_k(const InferArgs
   infer_rows<W, NPART, KIND>(a, q, e0);
 }
 
+// ------------------------------------------------------- fused training step
+// One step in two launches instead of several per layer.  train_k: per
+// workgroup, row tiles of R rows in groups of 32 (lanes l and l + 32 on row
+// l % 32, as in the fused inference kernel); the NF waves of a row group
+// split every layer's 32-feature output blocks between them (FB blocks
+// each), so that each wave's chain of dependent steps is a fraction of the
+// whole network's.  Per tile:
+//   - the rows' inputs: the epoch's pairs (shuffled position -> event and
+//     card -> standardised features) or given input rows, and their targets;
+//   - forward: each wave its blocks of each layer (the fused inference
+//     kernel's arithmetic), the layer's activations exchanged through LDS,
+//     the pre-activations kept in a per-wave workspace; the heads summed
+//     over the waves in a fixed order;
+//   - the heads' loss gradient (the loss of loss_grad), then backward: each
+//     wave its blocks of each layer's input gradient, a transposed product
+//     on the packed W^T with BF16 gradients (as the layered path rounds
+//     them), times SiLU'(z);
+//   - each layer's weight gradient G^T H over the tile's rows on the matrix
+//     cores, both operands staged in LDS with rows contiguous (the K order of
+//     the product): BF16 G and H for the hidden layers, as the layered path;
+//     split BF16 (hi.hi + hi.lo + lo.hi, about 2^-16) for the first layer's
+//     FP32 inputs.  Biases and the two FP32 heads: sums over rows on the VALU
+//     of FP32 values (gradients as hi + lo BF16 parts, 2^-17).
+// The sums go to this workgroup's slot of part (added over its tiles in tile
+// order).  train_update_k adds the slots in workgroup order: deterministic.
+template <int W>
+struct TrainShape {
+  static constexpr int NB = W / 32, NC = W / 16;
+  static constexpr int FB = W == 128 ? 1 : 2;       // 32-feature blocks per wave
+  static constexpr int NF = NB / FB;                // waves per row group
+  static constexpr int RG = W == 128 ? 4 : 2;       // row groups per workgroup
+  static constexpr int NWV = NF * RG;               // waves per workgroup (16 or 8)
+  static constexpr int R = 32 * RG;                 // rows per tile
+  static constexpr int S = R + 8;                   // LDS row stride: consecutive rows start 4 banks apart
+};
+
+int train_tile_rows(int width) { return width == 128 ? TrainShape<128>::R : TrainShape<256>::R; }
+// per workgroup: each wave's pre-activations of its blocks, every layer
+int64_t train_zws_floats(int width, int nh) {
+  const int per = width == 128 ? TrainShape<128>::NWV * TrainShape<128>::FB : TrainShape<256>::NWV * TrainShape<256>::FB;
+  return int64_t(per) * (nh + 2) * 16 * 64;              // + the first layer's inputs (16 words per lane)
+}
+
+// feature of accumulator element i of block b in lane half h
+__device__ __forceinline__ int acc_feat(int b, int i, int h) { return 32 * b + 8 * (i >> 2) + 4 * h + (i & 3); }
+
+__device__ __forceinline__ void split_bf16(float v, bf16& hi, bf16& lo) {
+  hi = bf16(v);
+  lo = bf16(v - float(hi));
+}
+
+// sum over r < R of a[r] * (hi[r] + lo[r]) (a NULL: of hi[r] + lo[r]), in row order
+template <int R>
+__device__ __forceinline__ float row_sum(const float* a, const bf16* hi, const bf16* lo) {
+  float s = 0.0f;
+#pragma unroll 2
+  for (int r0 = 0; r0 < R; r0 += 8) {
+    const bf16x8_t vh = *reinterpret_cast<const bf16x8_t*>(hi + r0);
+    const bf16x8_t vl = *reinterpret_cast<const bf16x8_t*>(lo + r0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const float v = float(vh[k]) + float(vl[k]);
+      s = a ? fmaf(a[r0 + k], v, s) : s + v;
+    }
+  }
+  return s;
+}
+
+// chunk c of a row's features (LDS [feature][row] layout) as a B operand:
+// slot s holds feature 16 c + 8 (s / 4) + 4 h + s % 4, the order in which
+// the accumulators of the producing layer come out
+template <int S>
+__device__ __forceinline__ bf16x8_t gather_chunk(const bf16 (*m)[S], int c, int h, int rl) {
+  bf16x8_t v;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) v[s] = m[16 * c + 8 * (s >> 2) + 4 * h + (s & 3)][rl];
+  return v;
+}
+
+// A pointer (launder: wave-uniform; vlaunder: any value) the compiler must
+// take as changed here: loads through it, and per-lane address arithmetic on
+// it, stay inside the row-tile loop instead of being hoisted out of it (every
+// layer's weights and addresses held across the loop would not fit in
+// registers).
+template <class P>
+__device__ __forceinline__ P launder(P p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+template <class V>
+__device__ __forceinline__ V vlaunder(V v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// two BF16 values in one 32-bit word (a in the low half) and back
+__device__ __forceinline__ unsigned int pack_bf16x2(bf16 a, bf16 b) {
+  return unsigned(__builtin_bit_cast(unsigned short, a)) | (unsigned(__builtin_bit_cast(unsigned short, b)) << 16);
+}
+__device__ __forceinline__ bf16 bf16_lo(unsigned int v) { return __builtin_bit_cast(bf16, (unsigned short)(v & 0xffffu)); }
+__device__ __forceinline__ bf16 bf16_hi(unsigned int v) { return __builtin_bit_cast(bf16, (unsigned short)(v >> 16)); }
+
+// this workgroup's first tile writes its slot, later tiles add to it
+__device__ __forceinline__ void put(float* p, float v, bool first) { *p = first ? v : *p + v; }
+
+template <int W, int NPART, int KIND, bool XROWS>
+__global__ __launch_bounds__(64 * TrainShape<W>::NWV, 1) void train_k(const TrainArgs a) {
+  using T = TrainShape<W>;
+  constexpr int NB = T::NB, NC = T::NC, FB = T::FB, NF = T::NF, NWV = T::NWV, R = T::R, S = T::S;
+  __shared__ __attribute__((aligned(16))) bf16 ah_s[W][S];   // layer inputs (hi) [feature][row]
+  __shared__ __attribute__((aligned(16))) bf16 al_s[W][S];   // their low parts (first layer, heads)
+  __shared__ __attribute__((aligned(16))) bf16 gh_s[W][S];   // gradients (hi)
+  __shared__ __attribute__((aligned(16))) bf16 gl_s[W][S];   // their low parts
+  __shared__ float hpart[NF][R][2];                         // the waves' partial heads
+  __shared__ float ghead[2][R];
+  __shared__ float wloss[T::RG];
+  const int lane = threadIdx.x & 63, h = lane >> 5;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));   // wave-uniform
+  const int rg = wv / NF, fw = wv % NF;                     // row group, feature wave
+  const int rl = 32 * rg + (lane & 31);
+  const int nh = a.nh;
+  const bf16x8_t* w0h_ = static_cast<const bf16x8_t*>(a.w0hi);
+  const bf16x8_t* w0l_ = static_cast<const bf16x8_t*>(a.w0lo);
+  const bf16x8_t* wh_ = static_cast<const bf16x8_t*>(a.wh);
+  const bf16x8_t* wht_ = static_cast<const bf16x8_t*>(a.wht);
+  float* const zw_ = a.zws + (size_t(blockIdx.x) * NWV + wv) * size_t(nh + 2) * FB * 16 * 64;
+  float* part = a.part + size_t(blockIdx.x) * a.pstride;
+  const int head = nh + 1;
+  float loss_acc = 0.0f;
+
+  for (int tile = int(blockIdx.x); tile < a.tiles; tile += int(gridDim.x)) {
+    const bool first = tile == int(blockIdx.x);
+    const int lv = vlaunder(lane);
+    const bf16x8_t* w0h = launder(w0h_) + lv;          // per-lane pointers (packed slots)
+    const bf16x8_t* w0l = launder(w0l_) + lv;
+    const bf16x8_t* wh = launder(wh_) + lv;
+    const bf16x8_t* wht = launder(wht_) + lv;
+    const float* b0 = launder(a.b0);
+    const float* bh = launder(a.bh);
+    const float* whead = launder(a.whead);
+    const float* bhead = launder(a.bhead);
+    float* zw = launder(zw_) + lv;                        // this lane's column of the workspace
+    const int64_t r = int64_t(tile) * R + rl;
+    const bool valid = r < a.n;
+    float f[kMlpMaxIn];
+    float yv;
+    if constexpr (XROWS) {
+      const int64_t rr = r < a.rows ? r : a.rows - 1;
+#pragma unroll
+      for (int k = 0; k < kMlpMaxIn; ++k) f[k] = a.x[rr * kMlpMaxIn + k];
+      yv = a.y[rr];
+    } else {
+      const int64_t rr = valid ? r : a.n - 1;
+      const int64_t j = shuffled(a.sh, a.pos0 + rr);
+      const int64_t e = j % a.nevt;
+      const int c = int(j / a.nevt);
+      double p[NPART * 4];
+      load_event<NPART>(a.mom, e, p);
+      const float card[3] = {a.cpar[3 * c], a.cpar[3 * c + 1], a.cpar[3 * c + 2]};
+      feature_row<NPART, KIND>(a.fm, p, card, f);
+      standardise(f, a.mean, a.istd);
+      yv = a.ygrid[j];
+    }
+    // this lane's half of the inputs, as the fused inference kernel takes it
+    const unsigned int pick = h ? ~0u : 0u;
+    bf16x8_t xh[2], xl[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int k = 16 * c + 8 * (s >> 2) + (s & 3);
+        const unsigned int u0 = __float_as_uint(f[k]), u1 = __float_as_uint(f[k + 4]);
+        bf16 vh, vl;
+        split_bf16(__uint_as_float(u0 ^ ((u0 ^ u1) & pick)), vh, vl);
+        xh[c][s] = vh;
+        xl[c][s] = vl;
+      }
+
+    if (fw == 0) {                                        // kept for the first layer's weight gradient
+      float* xs = zw + size_t(nh + 1) * FB * 16 * 64;
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int s = 0; s < 8; s += 2) {
+          xs[(c * 8 + s) * 64] = __uint_as_float(pack_bf16x2(xh[c][s], xh[c][s + 1]));
+          xs[(c * 8 + s + 1) * 64] = __uint_as_float(pack_bf16x2(xl[c][s], xl[c][s + 1]));
+        }
+    }
+
+    // ---------------------------------------------------------- forward
+#pragma unroll
+    for (int u = 0; u < FB; ++u) {
+      const int b = fw * FB + u;
+      f32x16_t acc;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[i] = b0[acc_feat(b, i, h)];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const bf16x8_t wa = w0h[(b * 2 + c) * 64];
+        const bf16x8_t wb = w0l[(b * 2 + c) * 64];
+        acc = mfma_bf16(wa, xh[c], acc);
+        acc = mfma_bf16(wa, xl[c], acc);
+        acc = mfma_bf16(wb, xh[c], acc);
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        zw[(u * 16 + i) * 64] = acc[i];
+        ah_s[acc_feat(b, i, h)][rl] = bf16(silu(acc[i]));
+      }
+    }
+    __syncthreads();
+    float mu = 0.0f, sg = 0.0f;
+    float zl[FB][16];                                     // the last hidden layer's pre-activations
+    for (int q = 0; q < nh; ++q) {
+      const bool last = q + 1 == nh;
+      const bf16x8_t* wl = wh + size_t(q) * NB * NC * 64;
+      const float* bl = bh + size_t(q) * W;
+      float* zq = zw + size_t(q + 1) * FB * 16 * 64;
+      f32x16_t acc[FB];
+#pragma unroll
+      for (int u = 0; u < FB; ++u)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[u][i] = bl[acc_feat(fw * FB + u, i, h)];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {                      // input chunk by chunk from LDS
+        const bf16x8_t xc = gather_chunk<S>(ah_s, c, h, rl);
+#pragma unroll
+        for (int u = 0; u < FB; ++u) acc[u] = mfma_bf16(wl[((fw * FB + u) * NC + c) * 64], xc, acc[u]);
+      }
+      bf16x8_t nxt[FB][2];
+#pragma unroll
+      for (int u = 0; u < FB; ++u)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          zq[(u * 16 + i) * 64] = acc[u][i];
+          zl[u][i] = acc[u][i];
+          nxt[u][i >> 3][i & 7] = bf16(silu(acc[u][i]));
+        }
+      if (last) {                                         // the last hidden layer feeds the FP32 heads
+#pragma unroll
+        for (int u = 0; u < FB; ++u)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int fo = acc_feat(fw * FB + u, i, h);
+            const float v = silu(zl[u][i]);
+            mu = fmaf(v, whead[fo], mu);
+            sg = fmaf(v, whead[W + fo], sg);
+          }
+        break;
+      }
+      __syncthreads();                                    // every wave has read this layer's inputs
+#pragma unroll
+      for (int u = 0; u < FB; ++u)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) ah_s[acc_feat(fw * FB + u, i, h)][rl] = nxt[u][i >> 3][i & 7];
+      __syncthreads();
+    }
+    mu += __shfl_xor(mu, 32);
+    sg += __shfl_xor(sg, 32);
+    if (lane < 32) {
+      hpart[fw][rl][0] = mu;
+      hpart[fw][rl][1] = sg;
+    }
+    __syncthreads();                                      // partial heads written; the inputs read
+    mu = 0.0f;
+    sg = 0.0f;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      mu += hpart[k][rl][0];
+      sg += hpart[k][rl][1];
+    }
+    mu += bhead[0];
+    sg += bhead[1];
+
+    // ------------------------------------------------ loss and its gradient
+    float g0 = 0.0f, g1 = 0.0f, lrow = 0.0f;
+    if (valid) {
+      const float s = fmaxf(sg, -15.0f);               // log-error head clamped as loss_grad does
+      const float res = (yv - a.ym) / a.ys - mu;
+      const float e2 = __expf(-2.0f * s);
+      const float inv = 1.0f / float(a.n);
+      g0 = -res * inv;
+      g1 = sg > -15.0f ? a.lambda * (1.0f - res * res * e2) * inv : 0.0f;
+      lrow = 0.5f * res * res + a.lambda * (0.5f * res * res * e2 + s);
+    }
+    if (fw == 0) {
+      float lw = lane < 32 ? lrow : 0.0f;
+      for (int off = 32; off > 0; off >>= 1) lw += __shfl_down(lw, off);
+      if (lane == 0) wloss[rg] = lw;
+      if (lane < 32) {
+        ghead[0][rl] = g0;
+        ghead[1][rl] = g1;
+      }
+    }
+    // the heads' FP32 input (hi / lo) and the gradient of the last hidden
+    // layer's pre-activation (hi / lo), this wave's blocks
+#pragma unroll
+    for (int u = 0; u < FB; ++u)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int fo = acc_feat(fw * FB + u, i, h);
+        const float z = zl[u][i];
+        split_bf16(silu(z), ah_s[fo][rl], al_s[fo][rl]);
+        split_bf16((g0 * whead[fo] + g1 * whead[W + fo]) * silu_grad(z), gh_s[fo][rl], gl_s[fo][rl]);
+      }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float t = 0.0f;
+      for (int k = 0; k < T::RG; ++k) t += wloss[k];
+      loss_acc += t;
+    }
+    // heads: dW[j][f] = sum_r g_j h_f, db[j] = sum_r g_j
+    for (int idx = int(threadIdx.x); idx < 2 * W; idx += NWV * 64) {
+      const int j = idx / W, fc = idx % W;
+      put(part + a.off_w[head] + size_t(j) * W + fc, row_sum<R>(ghead[j], ah_s[fc], al_s[fc]), first);
+    }
+    if (threadIdx.x < 2) {
+      float s = 0.0f;
+      for (int k = 0; k < R; ++k) s += ghead[threadIdx.x][k];
+      put(part + a.off_b[head] + threadIdx.x, s, first);
+    }
+
+    // ------------------------------------------------- hidden layers, backward
+    // LDS holds G of layer l (hi / lo); per layer: H of its input to LDS, the
+    // weight-gradient tiles and bias sums, then this wave's blocks of the
+    // input gradient (bf16(G) W) SiLU'(z), a transposed product on W^T, into
+    // LDS as the next layer's G.
+    for (int l = nh; l >= 1; --l) {
+      const float* zp = zw + size_t(l - 1) * FB * 16 * 64;     // pre-activation entering layer l
+      float zv[FB][16];
+#pragma unroll
+      for (int u = 0; u < FB; ++u)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) zv[u][i] = zp[(u * 16 + i) * 64];
+      __syncthreads();                                          // the previous sums are done with LDS
+#pragma unroll
+      for (int u = 0; u < FB; ++u)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) ah_s[acc_feat(fw * FB + u, i, h)][rl] = bf16(silu(zv[u][i]));
+      __syncthreads();
+      for (int t = wv; t < NB * NB; t += NWV) {
+        const int ob = t / NB, ib = t % NB;
+        f32x16_t acc = {};
+#pragma unroll
+        for (int k0 = 0; k0 < R; k0 += 16) {
+          const bf16x8_t av = *reinterpret_cast<const bf16x8_t*>(&gh_s[32 * ob + (lane & 31)][k0 + 8 * h]);
+          const bf16x8_t bv = *reinterpret_cast<const bf16x8_t*>(&ah_s[32 * ib + (lane & 31)][k0 + 8 * h]);
+          acc = mfma_bf16(av, bv, acc);
+        }
+        float* pw = part + a.off_w[l] + size_t(32 * ib + (lane & 31));
+#pragma unroll
+        for (int i = 0; i < 16; ++i) put(pw + size_t(32 * ob + 8 * (i >> 2) + 4 * h + (i & 3)) * W, acc[i], first);
+      }
+      for (int o = int(threadIdx.x); o < W; o += NWV * 64)
+        put(part + a.off_b[l] + o, row_sum<R>(nullptr, gh_s[o], gl_s[o]), first);
+      float gn[FB][16];
+      {
+        const bf16x8_t* wt = wht + size_t(l - 1) * NB * NC * 64;
+        f32x16_t acc[FB] = {};
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {                    // this row's G chunk by chunk from LDS
+          const bf16x8_t gc = gather_chunk<S>(gh_s, c, h, rl);
+#pragma unroll
+          for (int u = 0; u < FB; ++u) acc[u] = mfma_bf16(wt[((fw * FB + u) * NC + c) * 64], gc, acc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < FB; ++u)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) gn[u][i] = acc[u][i] * silu_grad(zv[u][i]);
+      }
+      __syncthreads();                                          // every read of this layer's G is done
+#pragma unroll
+      for (int u = 0; u < FB; ++u)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int fo = acc_feat(fw * FB + u, i, h);
+          split_bf16(gn[u][i], gh_s[fo][rl], gl_s[fo][rl]);
+        }
+    }
+
+    // --------------------------------------------------------- first layer
+    if (fw == 0) {
+      const float* xs = zw + size_t(nh + 1) * FB * 16 * 64;
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int s = 0; s < 8; s += 2) {
+          const unsigned int ph = __float_as_uint(xs[(c * 8 + s) * 64]), pl = __float_as_uint(xs[(c * 8 + s + 1) * 64]);
+          const int k = 16 * c + 8 * (s >> 2) + 4 * h + (s & 3);
+          ah_s[k][rl] = bf16_lo(ph);
+          ah_s[k + 1][rl] = bf16_hi(ph);
+          al_s[k][rl] = bf16_lo(pl);
+          al_s[k + 1][rl] = bf16_hi(pl);
+        }
+    }
+    __syncthreads();
+    for (int ob = wv; ob < NB; ob += NWV) {
+      f32x16_t acc = {};
+#pragma unroll
+      for (int k0 = 0; k0 < R; k0 += 16) {
+        const bf16x8_t ga = *reinterpret_cast<const bf16x8_t*>(&gh_s[32 * ob + (lane & 31)][k0 + 8 * h]);
+        const bf16x8_t gb = *reinterpret_cast<const bf16x8_t*>(&gl_s[32 * ob + (lane & 31)][k0 + 8 * h]);
+        const bf16x8_t xa = *reinterpret_cast<const bf16x8_t*>(&ah_s[lane & 31][k0 + 8 * h]);
+        const bf16x8_t xb = *reinterpret_cast<const bf16x8_t*>(&al_s[lane & 31][k0 + 8 * h]);
+        acc = mfma_bf16(ga, xa, acc);
+        acc = mfma_bf16(ga, xb, acc);
+        acc = mfma_bf16(gb, xa, acc);
+      }
+      float* pw = part + a.off_w[0] + (lane & 31);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) put(pw + size_t(32 * ob + 8 * (i >> 2) + 4 * h + (i & 3)) * kMlpMaxIn, acc[i], first);
+    }
+    for (int o = int(threadIdx.x); o < W; o += NWV * 64)
+      put(part + a.off_b[0] + o, row_sum<R>(nullptr, gh_s[o], gl_s[o]), first);
+    __syncthreads();                                            // LDS free for the next tile
+  }
+  if (threadIdx.x == 0) part[a.total] = loss_acc;
+}
+
+// Per parameter element: the workgroups' sums in workgroup order into the
+// gradient buffer; with adam, the step of adam_all and every copy of the new
+// value (operand copies, packed forward and transposed orders, contiguous
+// hidden biases).  Element total: the loss sum.  Padding elements get a zero
+// gradient and stay zero.
+__global__ __launch_bounds__(256) void train_update_k(const AdamSeg* __restrict__ segs, const PackSeg* __restrict__ pk,
+                                                      int nseg, int64_t total, const float* __restrict__ part,
+                                                      int groups, int64_t pstride, float* __restrict__ loss, int adam,
+                                                      float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int64_t gi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gi > total) return;
+  if (gi == total) {
+    float s = 0.0f;
+    for (int g = 0; g < groups; ++g) s += part[size_t(g) * pstride + total];
+    *loss = s;
+    return;
+  }
+  int k = 0;
+  while (k + 1 < nseg && gi >= segs[k + 1].begin) ++k;
+  const AdamSeg sg = segs[k];
+  const PackSeg pq = pk[k];
+  const int64_t i = gi - sg.begin;
+  const int r = int(i / sg.cols), c = int(i % sg.cols);
+  const bool used = r < sg.mask_rows && c < sg.mask_cols;
+  // the slots' loads in groups of eight ahead of their additions (in slot order)
+  float gv = 0.0f;
+  if (used) {
+    int g = 0;
+    for (; g + 8 <= groups; g += 8) {
+      float v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = part[size_t(g + k) * pstride + gi];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) gv += v[k];
+    }
+    for (; g < groups; ++g) gv += part[size_t(g) * pstride + gi];
+  }
+  pq.grad[i] = gv;
+  if (!adam) return;
+  float wi = 0.0f;
+  if (used) {
+    const float mi = b1 * sg.m[i] + (1.0f - b1) * gv;
+    const float vi = b2 * sg.v[i] + (1.0f - b2) * gv * gv;
+    sg.m[i] = mi;
+    sg.v[i] = vi;
+    wi = sg.w[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    sg.w[i] = wi;
+  }
+  if (sg.bf16_out) {
+    if (sg.wt) static_cast<bf16*>(sg.wt)[i] = bf16(wi);
+    if (sg.wtt) static_cast<bf16*>(sg.wtt)[size_t(c) * sg.rows + r] = bf16(wi);
+  } else {
+    if (sg.wt) static_cast<float*>(sg.wt)[i] = wi;
+    if (sg.wtt) static_cast<float*>(sg.wtt)[size_t(c) * sg.rows + r] = wi;
+  }
+  if (pq.hi) {
+    const int64_t t = pack_pos(r, c, pq.nchunks);
+    bf16 vh, vl;
+    split_bf16(wi, vh, vl);
+    static_cast<bf16*>(pq.hi)[t] = vh;
+    if (pq.lo) static_cast<bf16*>(pq.lo)[t] = vl;
+  }
+  if (pq.tr) static_cast<bf16*>(pq.tr)[pack_pos(c, r, pq.tchunks)] = bf16(wi);
+  if (pq.bias) pq.bias[c] = wi;
+}
+
 // ----------------------------------------------------------------- launchers
 static unsigned blocks_for(int64_t n, int b = 256) { return unsigned((n + b - 1) / b); }
 
@@ -989,9 +1483,9 @@ hipError_t mlp_gate(const float* z, int ld, int64_t n, float ym, float ys, float
 }
 
 hipError_t mlp_pack(const float* w, int ld, int rows_used, int cols_used, int nblocks, int nchunks, void* hi,
-                    void* lo, hipStream_t s) {
+                    void* lo, hipStream_t s, bool transposed) {
   hipLaunchKernelGGL(pack_k, dim3(blocks_for(int64_t(nblocks) * nchunks * 512)), dim3(256), 0, s, w, ld, rows_used,
-                     cols_used, nblocks, nchunks, static_cast<bf16*>(hi), static_cast<bf16*>(lo));
+                     cols_used, nblocks, nchunks, static_cast<bf16*>(hi), static_cast<bf16*>(lo), int(transposed));
   return hipGetLastError();
 }
 
@@ -1029,6 +1523,43 @@ hipError_t mlp_infer(int width, const InferArgs& a, hipStream_t s) {
   if (width == 128) return infer_launch<128>(a, s);
   if (width == 256) return infer_launch<256>(a, s);
   return hipErrorInvalidValue;
+}
+
+template <int W>
+static hipError_t train_launch(const TrainArgs& a, hipStream_t s) {
+  const dim3 g(unsigned(a.groups)), b(64 * TrainShape<W>::NWV);
+  if (a.x)
+    hipLaunchKernelGGL((train_k<W, 4, kFeatRaw, true>), g, b, 0, s, a);
+  else if (a.fm.npart == 4 && a.fm.kind == kFeatRaw)
+    hipLaunchKernelGGL((train_k<W, 4, kFeatRaw, false>), g, b, 0, s, a);
+  else if (a.fm.npart == 4)
+    hipLaunchKernelGGL((train_k<W, 4, kFeatPhys, false>), g, b, 0, s, a);
+  else if (a.fm.npart == 5 && a.fm.kind == kFeatRaw)
+    hipLaunchKernelGGL((train_k<W, 5, kFeatRaw, false>), g, b, 0, s, a);
+  else if (a.fm.npart == 5)
+    hipLaunchKernelGGL((train_k<W, 5, kFeatPhys, false>), g, b, 0, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t mlp_train_grads(int width, const TrainArgs& a, hipStream_t s) {
+  if (a.n <= 0 || a.nh < 1 || a.nh > kMlpMaxHidden || a.groups < 1 || a.groups > kTrainMaxGroups ||
+      a.tiles < a.groups || int64_t(a.tiles) * train_tile_rows(width) < a.n || (a.x && (!a.y || a.rows < 1)) ||
+      (!a.x && (!a.mom || !a.cpar || !a.ygrid || a.nevt < 1)))
+    return hipErrorInvalidValue;
+  if (width == 128) return train_launch<128>(a, s);
+  if (width == 256) return train_launch<256>(a, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t mlp_train_update(const AdamSeg* segs, const PackSeg* pk, int nseg, int64_t total, const float* part,
+                            int groups, int64_t pstride, float* loss, int adam, float lr, float b1, float b2,
+                            float eps, float c1, float c2, hipStream_t s) {
+  if (!segs || !pk || nseg < 1 || total < 1 || groups < 1 || pstride <= total) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(train_update_k, dim3(blocks_for(total + 1)), dim3(256), 0, s, segs, pk, nseg, total, part, groups,
+                     pstride, loss, adam, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
 }
 
 }  // namespace rwgt

@@ -168,6 +168,10 @@ int rwgt_mlp::pack() {
     const Layer& ly = layers[l];
     char* dst = static_cast<char*>(phid) + size_t(l - 1) * nb * nc * kPackBytes;
     e = rwgt::mlp_pack(ly.w, ly.in, ly.out_used, ly.in_used, nb, nc, dst, nullptr, stream);
+    if (e == hipSuccess && phid_t) {
+      char* dst_t = static_cast<char*>(phid_t) + size_t(l - 1) * nb * nc * kPackBytes;
+      e = rwgt::mlp_pack(ly.w, ly.in, ly.in_used, ly.out_used, nb, nc, dst_t, nullptr, stream, true);
+    }
     if (e == hipSuccess)
       e = hipMemcpyAsync(pbias + size_t(l - 1) * width, ly.b, size_t(width) * 4, hipMemcpyDeviceToDevice, stream);
   }
@@ -217,6 +221,8 @@ rwgt_mlp::~rwgt_mlp() {
   for (void* p : work) hipFree(p);
   for (void* p : twork) hipFree(p);
   for (void* p : params) hipFree(p);
+  if (tr_part) hipFree(tr_part);
+  if (tr_zws) hipFree(tr_zws);
 }
 
 extern "C" {
@@ -295,6 +301,7 @@ int rwgt_mlp_create(int32_t n_in, int32_t width, int32_t depth, int32_t n_out, i
     dalloc(&m->p0lo, nb * 2 * kPackBytes);
     dalloc(&m->phid, size_t(nh) * nb * nc * kPackBytes);
     dalloc(reinterpret_cast<void**>(&m->pbias), size_t(nh) * width * 4);
+    if (n_out == 2) dalloc(&m->phid_t, size_t(nh) * nb * nc * kPackBytes);   // fused training
   }
   // the Adam segment table: each layer's W (operand-type copies W, W^T) and
   // bias, in layer order, as the per-tensor calls take them
@@ -315,6 +322,33 @@ int rwgt_mlp_create(int32_t n_in, int32_t width, int32_t depth, int32_t n_out, i
       m->adam_segs = static_cast<rwgt::AdamSeg*>(tab);
       m->adam_nseg = int(segs.size());
       m->adam_total = begin;
+    }
+    // the fused training step's copies of each segment: packed first layer
+    // (hi / lo), packed hidden W and W^T, contiguous hidden biases
+    if (e == hipSuccess && m->phid_t) {
+      const int L = int(m->layers.size()), nb = width / 32, nc = width / 16;
+      std::vector<rwgt::PackSeg> pk(segs.size());
+      for (int l = 0; l < L; ++l) {
+        rwgt::PackSeg& pw = pk[size_t(2 * l)];
+        rwgt::PackSeg& pb = pk[size_t(2 * l + 1)];
+        pw.grad = m->layers[size_t(l)].gw;
+        pb.grad = m->layers[size_t(l)].gb;
+        if (l == 0) {
+          pw.hi = m->p0hi;
+          pw.lo = m->p0lo;
+          pw.nchunks = 2;
+        } else if (l + 1 < L) {
+          const size_t off = size_t(l - 1) * nb * nc * kPackBytes;
+          pw.hi = static_cast<char*>(m->phid) + off;
+          pw.tr = static_cast<char*>(m->phid_t) + off;
+          pw.nchunks = pw.tchunks = nc;
+          pb.bias = m->pbias + size_t(l - 1) * width;
+        }
+      }
+      void* ptab = nullptr;
+      dalloc(&ptab, pk.size() * sizeof(rwgt::PackSeg));
+      if (e == hipSuccess) e = hipMemcpy(ptab, pk.data(), pk.size() * sizeof(rwgt::PackSeg), hipMemcpyHostToDevice);
+      if (e == hipSuccess) m->pack_segs = static_cast<rwgt::PackSeg*>(ptab);
     }
   }
   if (e == hipSuccess && m->refresh_copies() != RWGT_OK) e = hipErrorUnknown;
@@ -618,9 +652,19 @@ int rwgt_mlp_predict(rwgt_mlp* m, const double* momenta, int32_t npart, const in
 int rwgt_mlp_train_step(rwgt_mlp* m, const void* x, const float* y, int64_t n, float lr, float* loss_out) {
   if (!m || !x || !y || n < 1) return RWGT_EINVAL;
   const int64_t rows = pad64(n);
-  int rc = m->forward(x, rows);
-  if (rc == RWGT_OK) rc = m->backward(y, n, rows);
-  if (rc == RWGT_OK && lr > 0.0f) rc = m->update(lr);
+  int rc = RWGT_OK;
+  if (m->fused_train()) {
+    rwgt::TrainArgs a;
+    a.x = static_cast<const float*>(x);
+    a.y = y;
+    a.n = n;
+    a.rows = rows;
+    rc = m->train_fused(a, lr);
+  } else {
+    rc = m->forward(x, rows);
+    if (rc == RWGT_OK) rc = m->backward(y, n, rows);
+    if (rc == RWGT_OK && lr > 0.0f) rc = m->update(lr);
+  }
   if (rc == RWGT_OK && loss_out) {
     hipError_t e = hipMemcpyAsync(loss_out, m->loss, 4, hipMemcpyDeviceToDevice, m->stream);
     if (e != hipSuccess) return m->hip_fail(e, "copy loss");

@@ -32,8 +32,15 @@ struct rwgt_mlp {
   hipStream_t stream = nullptr;
   // fused inference: packed weights (valid while !pack_dirty)
   void *p0hi = nullptr, *p0lo = nullptr, *phid = nullptr;
+  void* phid_t = nullptr;                                 // hidden layers' W^T, packed (fused training)
   float* pbias = nullptr;
   bool pack_dirty = true;
+  // fused training step: per-segment packed copies, per-workgroup gradient
+  // sums and pre-activation workspace
+  rwgt::PackSeg* pack_segs = nullptr;
+  float *tr_part = nullptr, *tr_zws = nullptr;
+  int tr_groups = 0;                                      // workgroup slots allocated
+  int64_t tr_pstride = 0;
   // batch workspace
   int64_t bcap = 0;
   const void* x_in = nullptr;                             // the current batch's input rows (FP32)
@@ -80,6 +87,11 @@ struct rwgt_mlp {
   int backward(const float* y, int64_t n_valid, int64_t rows);
   int update(float lr);
   int ensure_train(int64_t batch, int64_t probes);
+  // eligible for the fused training step (fused inference weights, two heads)
+  bool fused_train() const { return phid_t && pack_segs && n_out == 2; }
+  // one fused step over the rows described by rows_in (x / y, or the pairs
+  // of a grid); lr > 0: with the Adam step, else gradients and loss only
+  int train_fused(const rwgt::TrainArgs& rows_in, float lr);
   // heads (mu_y, s_y) [n][2] of rows (ev, cd), fused kernel or layer by layer
   int predict_rows(const double* mom, const int32_t* ev, const int32_t* cd, const float* cpar, int64_t n,
                    float* heads);

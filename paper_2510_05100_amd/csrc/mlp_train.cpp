@@ -66,6 +66,72 @@ int rwgt_mlp::ensure_train(int64_t batch, int64_t probes) {
   return e == hipSuccess ? RWGT_OK : hip_fail(e, "clear training batch");
 }
 
+int rwgt_mlp::train_fused(const rwgt::TrainArgs& rows_in, float lr) {
+  int rc = pack();
+  if (rc != RWGT_OK) return rc;
+  const int L = int(layers.size()), nh = L - 2;
+  const int R = rwgt::train_tile_rows(width);
+  const int64_t tiles = (rows_in.n + R - 1) / R;
+  if (rows_in.n < 1 || tiles > INT32_MAX) return fail(RWGT_EINVAL, "bad row count");
+  const int groups = int(std::min<int64_t>(tiles, rwgt::kTrainMaxGroups));
+  const int64_t pstride = (adam_total + 1 + 63) / 64 * 64;
+  if (groups > tr_groups || pstride != tr_pstride) {
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (tr_part) hipFree(tr_part);
+    if (tr_zws) hipFree(tr_zws);
+    tr_part = tr_zws = nullptr;
+    tr_groups = 0;
+    e = hipMalloc(&tr_part, size_t(groups) * size_t(pstride) * 4);
+    if (e == hipSuccess) e = hipMalloc(&tr_zws, size_t(groups) * size_t(rwgt::train_zws_floats(width, nh)) * 4);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(fused training workspace)");
+    tr_groups = groups;
+    tr_pstride = pstride;
+  }
+  rwgt::TrainArgs a = rows_in;
+  a.fm = fm;
+  a.mean = mean;
+  a.istd = istd;
+  a.w0hi = p0hi;
+  a.w0lo = p0lo;
+  a.b0 = layers[0].b;
+  a.wh = phid;
+  a.wht = phid_t;
+  a.bh = pbias;
+  a.nh = nh;
+  a.whead = layers[size_t(L - 1)].w;
+  a.bhead = layers[size_t(L - 1)].b;
+  a.lambda = lambda;
+  a.ym = ym;
+  a.ys = ys;
+  a.zws = tr_zws;
+  a.part = tr_part;
+  a.pstride = pstride;
+  a.total = adam_total;
+  int64_t begin = 0;                     // segment order of the Adam table: W then b per layer
+  for (int l = 0; l < L; ++l) {
+    a.off_w[l] = begin;
+    begin += int64_t(layers[size_t(l)].out) * layers[size_t(l)].in;
+    a.off_b[l] = begin;
+    begin += layers[size_t(l)].out;
+  }
+  a.tiles = int(tiles);
+  a.groups = groups;
+  hipError_t e = rwgt::mlp_train_grads(width, a, stream);
+  if (e != hipSuccess) return hip_fail(e, "fused training step");
+  const int adam = lr > 0.0f ? 1 : 0;
+  float c1 = 0.0f, c2 = 0.0f;
+  if (adam) {
+    ++t;
+    c1 = 1.0f / (1.0f - std::pow(b1, float(t)));
+    c2 = 1.0f / (1.0f - std::pow(b2, float(t)));
+  }
+  e = rwgt::mlp_train_update(adam_segs, pack_segs, adam_nseg, adam_total, tr_part, groups, pstride, loss, adam, lr,
+                             b1, b2, eps, c1, c2, stream);
+  if (e != hipSuccess) return hip_fail(e, "fused training update");
+  return RWGT_OK;                        // the packed copies were refreshed with the parameters
+}
+
 int rwgt_mlp::predict_rows(const double* mom, const int32_t* ev, const int32_t* cd, const float* cpar, int64_t n,
                            float* heads) {
   if (fused()) return infer(mom, ev, cd, cpar, n, heads, nullptr, nullptr, nullptr, nullptr, 0.0f);
@@ -133,6 +199,9 @@ int rwgt_mlp_train(rwgt_mlp* m, const double* momenta, int32_t npart, int64_t ne
     m->has_sched = true;
   }
   const int ld = m->layers[0].in;
+  // one fused step per batch (rows straight from the grid) where the network
+  // and feature map allow it; else the layered step on gathered rows
+  const bool fused = m->fused_train() && m->fused();
   std::vector<float> probe(static_cast<size_t>(probes));
   const int64_t first = m->epoch;
   for (int64_t ep = first; ep < epoch_end; ++ep) {
@@ -142,14 +211,26 @@ int rwgt_mlp_train(rwgt_mlp* m, const double* momenta, int32_t npart, int64_t ne
     for (int64_t b = 0; b < per_epoch; ++b) {
       const double frac = double(m->step) / double(std::max<int64_t>(1, nsteps - 1));
       const float lr = float(double(cfg->lr) * std::pow(double(cfg->lr_final) / double(cfg->lr), frac));
-      e = rwgt::mlp_gather_pairs(sh, b * batch, batch, nevt, y, m->tr_ev, m->tr_cd, m->tr_y, m->stream);
-      if (e == hipSuccess)
-        e = rwgt::mlp_features(m->fm, momenta, m->tr_ev, m->tr_cd, card_params, m->mean, m->istd, m->tr_x, batch,
-                               rows, ld, m->stream);
-      if (e != hipSuccess) return m->hip_fail(e, "training batch");
-      rc = m->forward(m->tr_x, rows);
-      if (rc == RWGT_OK) rc = m->backward(m->tr_y, batch, rows);
-      if (rc == RWGT_OK) rc = m->update(lr);
+      if (fused) {
+        rwgt::TrainArgs a;
+        a.sh = sh;
+        a.pos0 = b * batch;
+        a.nevt = nevt;
+        a.mom = momenta;
+        a.cpar = card_params;
+        a.ygrid = y;
+        a.n = batch;
+        rc = m->train_fused(a, lr);
+      } else {
+        e = rwgt::mlp_gather_pairs(sh, b * batch, batch, nevt, y, m->tr_ev, m->tr_cd, m->tr_y, m->stream);
+        if (e == hipSuccess)
+          e = rwgt::mlp_features(m->fm, momenta, m->tr_ev, m->tr_cd, card_params, m->mean, m->istd, m->tr_x, batch,
+                                 rows, ld, m->stream);
+        if (e != hipSuccess) return m->hip_fail(e, "training batch");
+        rc = m->forward(m->tr_x, rows);
+        if (rc == RWGT_OK) rc = m->backward(m->tr_y, batch, rows);
+        if (rc == RWGT_OK) rc = m->update(lr);
+      }
       if (rc != RWGT_OK) return rc;
       if (b % kProbeEvery == 0) {
         e = hipMemcpyAsync(m->tr_loss + np, m->loss, 4, hipMemcpyDeviceToDevice, m->stream);
