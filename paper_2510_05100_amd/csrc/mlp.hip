@@ -869,19 +869,35 @@ __device__ __forceinline__ void split_bf16(float v, bf16& hi, bf16& lo) {
   lo = bf16(v - float(hi));
 }
 
-// sum over r < R of a[r] * (hi[r] + lo[r]) (a NULL: of hi[r] + lo[r]), in row order
-template <int R>
-__device__ __forceinline__ float row_sum(const float* a, const bf16* hi, const bf16* lo) {
+// Sums over the R rows of nout outputs, by every thread of the workgroup: G
+// consecutive threads per output (G a power of two up to 8, as many as the
+// threads allow), each over R / G consecutive rows in order, combined by a
+// fixed butterfly over the G lanes.  part8(o, r0) is output o's sum over
+// rows r0 .. r0 + 7; emit(o, s) receives each total once.
+template <int R, int NT, class P, class E>
+__device__ __forceinline__ void group_sums(int nout, P part8, E emit) {
+  int G = 1;
+  while (G < 8 && G * 8 < R && nout * G * 2 <= NT) G *= 2;
+  const int span = R / G;
+  for (int base = 0; base < nout * G; base += NT) {       // uniform over the workgroup
+    const int t = base + int(threadIdx.x), o = t / G, g = t % G;
+    float s = 0.0f;
+    if (o < nout)
+      for (int r0 = g * span; r0 < (g + 1) * span; r0 += 8) s += part8(o, r0);
+    for (int m = 1; m < G; m <<= 1) s += __shfl_xor(s, m);
+    if (o < nout && g == 0) emit(o, s);
+  }
+}
+
+// sum over 8 rows from r0 of hi + lo (a non-NULL: weighted by a[r])
+__device__ __forceinline__ float sum8(const float* a, const bf16* hi, const bf16* lo, int r0) {
+  const bf16x8_t vh = *reinterpret_cast<const bf16x8_t*>(hi + r0);
+  const bf16x8_t vl = *reinterpret_cast<const bf16x8_t*>(lo + r0);
   float s = 0.0f;
-#pragma unroll 2
-  for (int r0 = 0; r0 < R; r0 += 8) {
-    const bf16x8_t vh = *reinterpret_cast<const bf16x8_t*>(hi + r0);
-    const bf16x8_t vl = *reinterpret_cast<const bf16x8_t*>(lo + r0);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const float v = float(vh[k]) + float(vl[k]);
-      s = a ? fmaf(a[r0 + k], v, s) : s + v;
-    }
+  for (int k = 0; k < 8; ++k) {
+    const float v = float(vh[k]) + float(vl[k]);
+    s = a ? fmaf(a[r0 + k], v, s) : s + v;
   }
   return s;
 }
@@ -1129,22 +1145,28 @@ __global__ __launch_bounds__(64 * TrainShape<W>::NWV, 1) void train_k(const Trai
       for (int k = 0; k < T::RG; ++k) t += wloss[k];
       loss_acc += t;
     }
-    // heads: dW[j][f] = sum_r g_j h_f, db[j] = sum_r g_j
-    for (int idx = int(threadIdx.x); idx < 2 * W; idx += NWV * 64) {
-      const int j = idx / W, fc = idx % W;
-      put(part + a.off_w[head] + size_t(j) * W + fc, row_sum<R>(ghead[j], ah_s[fc], al_s[fc]), first);
-    }
-    if (threadIdx.x < 2) {
-      float s = 0.0f;
-      for (int k = 0; k < R; ++k) s += ghead[threadIdx.x][k];
-      put(part + a.off_b[head] + threadIdx.x, s, first);
-    }
+    // heads: dW[j][f] = sum_r g_j h_f (outputs 0 .. 2W-1), db[j] = sum_r g_j (outputs 2W, 2W+1)
+    group_sums<R, NWV * 64>(
+        2 * W + 2,
+        [&](int o, int r0) {
+          if (o >= 2 * W) {
+            float s = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s += ghead[o - 2 * W][r0 + k];
+            return s;
+          }
+          return sum8(ghead[o / W], ah_s[o % W], al_s[o % W], r0);
+        },
+        [&](int o, float v) {
+          put(part + (o < 2 * W ? a.off_w[head] + o : a.off_b[head] + (o - 2 * W)), v, first);
+        });
 
     // ------------------------------------------------- hidden layers, backward
     // LDS holds G of layer l (hi / lo); per layer: H of its input to LDS, the
     // weight-gradient tiles and bias sums, then this wave's blocks of the
     // input gradient (bf16(G) W) SiLU'(z), a transposed product on W^T, into
     // LDS as the next layer's G.
+    unsigned int xs_w[16];                                      // the first layer's inputs, packed
     for (int l = nh; l >= 1; --l) {
       const float* zp = zw + size_t(l - 1) * FB * 16 * 64;     // pre-activation entering layer l
       float zv[FB][16];
@@ -1171,8 +1193,9 @@ __global__ __launch_bounds__(64 * TrainShape<W>::NWV, 1) void train_k(const Trai
 #pragma unroll
         for (int i = 0; i < 16; ++i) put(pw + size_t(32 * ob + 8 * (i >> 2) + 4 * h + (i & 3)) * W, acc[i], first);
       }
-      for (int o = int(threadIdx.x); o < W; o += NWV * 64)
-        put(part + a.off_b[l] + o, row_sum<R>(nullptr, gh_s[o], gl_s[o]), first);
+      group_sums<R, NWV * 64>(
+          W, [&](int o, int r0) { return sum8(nullptr, gh_s[o], gl_s[o], r0); },
+          [&](int o, float v) { put(part + a.off_b[l] + o, v, first); });
       float gn[FB][16];
       {
         const bf16x8_t* wt = wht + size_t(l - 1) * NB * NC * 64;
@@ -1188,6 +1211,11 @@ __global__ __launch_bounds__(64 * TrainShape<W>::NWV, 1) void train_k(const Trai
 #pragma unroll
           for (int i = 0; i < 16; ++i) gn[u][i] = acc[u][i] * silu_grad(zv[u][i]);
       }
+      if (l == 1 && fw == 0) {                                  // loaded early for the first layer
+        const float* xs = zw + size_t(nh + 1) * FB * 16 * 64;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) xs_w[k] = __float_as_uint(xs[k * 64]);
+      }
       __syncthreads();                                          // every read of this layer's G is done
 #pragma unroll
       for (int u = 0; u < FB; ++u)
@@ -1200,12 +1228,11 @@ __global__ __launch_bounds__(64 * TrainShape<W>::NWV, 1) void train_k(const Trai
 
     // --------------------------------------------------------- first layer
     if (fw == 0) {
-      const float* xs = zw + size_t(nh + 1) * FB * 16 * 64;
 #pragma unroll
       for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int s = 0; s < 8; s += 2) {
-          const unsigned int ph = __float_as_uint(xs[(c * 8 + s) * 64]), pl = __float_as_uint(xs[(c * 8 + s + 1) * 64]);
+          const unsigned int ph = xs_w[c * 8 + s], pl = xs_w[c * 8 + s + 1];
           const int k = 16 * c + 8 * (s >> 2) + 4 * h + (s & 3);
           ah_s[k][rl] = bf16_lo(ph);
           ah_s[k + 1][rl] = bf16_hi(ph);
@@ -1230,8 +1257,9 @@ __global__ __launch_bounds__(64 * TrainShape<W>::NWV, 1) void train_k(const Trai
 #pragma unroll
       for (int i = 0; i < 16; ++i) put(pw + size_t(32 * ob + 8 * (i >> 2) + 4 * h + (i & 3)) * kMlpMaxIn, acc[i], first);
     }
-    for (int o = int(threadIdx.x); o < W; o += NWV * 64)
-      put(part + a.off_b[0] + o, row_sum<R>(nullptr, gh_s[o], gl_s[o]), first);
+    group_sums<R, NWV * 64>(
+        W, [&](int o, int r0) { return sum8(nullptr, gh_s[o], gl_s[o], r0); },
+        [&](int o, float v) { put(part + a.off_b[0] + o, v, first); });
     __syncthreads();                                            // LDS free for the next tile
   }
   if (threadIdx.x == 0) part[a.total] = loss_acc;
@@ -1246,6 +1274,15 @@ __global__ __launch_bounds__(256) void train_update_k(const AdamSeg* __restrict_
                                                       int nseg, int64_t total, const float* __restrict__ part,
                                                       int groups, int64_t pstride, float* __restrict__ loss, int adam,
                                                       float lr, float b1, float b2, float eps, float c1, float c2) {
+  // the segment tables in LDS: the lookup below reads them in a dependent
+  // chain, which from global memory costs a round trip per segment
+  __shared__ AdamSeg s_seg[2 * kTrainMaxLayers];
+  __shared__ PackSeg s_pk[2 * kTrainMaxLayers];
+  for (int k = int(threadIdx.x); k < nseg; k += int(blockDim.x)) {
+    s_seg[k] = segs[k];
+    s_pk[k] = pk[k];
+  }
+  __syncthreads();
   const int64_t gi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (gi > total) return;
   if (gi == total) {
@@ -1255,24 +1292,22 @@ __global__ __launch_bounds__(256) void train_update_k(const AdamSeg* __restrict_
     return;
   }
   int k = 0;
-  while (k + 1 < nseg && gi >= segs[k + 1].begin) ++k;
-  const AdamSeg sg = segs[k];
-  const PackSeg pq = pk[k];
+  while (k + 1 < nseg && gi >= s_seg[k + 1].begin) ++k;
+  const AdamSeg sg = s_seg[k];
+  const PackSeg pq = s_pk[k];
   const int64_t i = gi - sg.begin;
   const int r = int(i / sg.cols), c = int(i % sg.cols);
   const bool used = r < sg.mask_rows && c < sg.mask_cols;
-  // the slots' loads in groups of eight ahead of their additions (in slot order)
+  // the slots' loads in batches of 32 ahead of their additions (in slot order)
   float gv = 0.0f;
   if (used) {
-    int g = 0;
-    for (; g + 8 <= groups; g += 8) {
-      float v[8];
+    for (int g = 0; g < groups; g += 32) {
+      float v[32];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = part[size_t(g + k) * pstride + gi];
+      for (int k = 0; k < 32; ++k) v[k] = g + k < groups ? part[size_t(g + k) * pstride + gi] : 0.0f;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) gv += v[k];
+      for (int k = 0; k < 32; ++k) gv += v[k];
     }
-    for (; g < groups; ++g) gv += part[size_t(g) * pstride + gi];
   }
   pq.grad[i] = gv;
   if (!adam) return;
@@ -1556,7 +1591,8 @@ hipError_t mlp_train_grads(int width, const TrainArgs& a, hipStream_t s) {
 hipError_t mlp_train_update(const AdamSeg* segs, const PackSeg* pk, int nseg, int64_t total, const float* part,
                             int groups, int64_t pstride, float* loss, int adam, float lr, float b1, float b2,
                             float eps, float c1, float c2, hipStream_t s) {
-  if (!segs || !pk || nseg < 1 || total < 1 || groups < 1 || pstride <= total) return hipErrorInvalidValue;
+  if (!segs || !pk || nseg < 1 || nseg > 2 * kTrainMaxLayers || total < 1 || groups < 1 || pstride <= total)
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(train_update_k, dim3(blocks_for(total + 1)), dim3(256), 0, s, segs, pk, nseg, total, part, groups,
                      pstride, loss, adam, lr, b1, b2, eps, c1, c2);
   return hipGetLastError();
