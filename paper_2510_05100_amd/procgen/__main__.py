@@ -8,6 +8,7 @@ PROCESSES = {
     "ee_mumu": "e+ e- > mu+ mu-",
     "uu_eeg": "u u~ > e+ e- g",
     "gg_ttgg": "g g > t t~ g g",
+    "gg_tttt": "g g > t t~ t t~",
 }
 
 

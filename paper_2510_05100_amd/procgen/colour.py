@@ -16,6 +16,7 @@ from fractions import Fraction
 from functools import lru_cache
 
 NC = 3
+X = "x"          # the generator of a gluon joining two quark lines (contracted by fierz)
 
 
 def leaf(a):
@@ -122,4 +123,58 @@ def colour_matrix(basis):
         for j, sp in enumerate(basis):
             word = tuple(reversed(s)) + tuple(sp)
             out[i][j] = trace_product(_canon([word]))
+    return out
+
+
+# ------------------------------------------------------------ two lines
+def fierz(ca, cb, main, second, sign=1):
+    """Colour of a product of two lines' strings joined by one gluon: ca on
+    the main line (row, column), cb on the second, each holding X once.
+    sum_x (U t^x V)_{i j} (P t^x Q)_{k l}
+        = 1/2 (U Q)_{i l} (P V)_{k j} - 1/(2N) (U V)_{i j} (P Q)_{k l}.
+    Returned times 2N (integer coefficients, times sign), keyed by (column
+    joined to the main row, string on the main row, string on the second
+    row)."""
+    out = {}
+    for sa, va in ca.items():
+        ia = sa.index(X)
+        u, v = sa[:ia], sa[ia + 1:]
+        for sb, vb in cb.items():
+            ib = sb.index(X)
+            p, q = sb[:ib], sb[ib + 1:]
+            for key, c in (((second[1], u + q, p + v), NC), ((main[1], u + v, p + q), -1)):
+                out[key] = out.get(key, 0) + sign * va * vb * c
+    return {k: v for k, v in out.items() if v != 0}
+
+
+FIERZ_SCALE = 2 * NC     # fierz returns colour factors times this
+
+
+def colour_matrix_two_lines(basis, rows, cols):
+    """C[b, b'] = sum over all indices of conj(B_b) B_b' for basis elements
+    (column joined to rows[0], string on rows[0], string on rows[1]): the
+    index loops closed by following each quark line from its row to its
+    column in B_b' and back through the conjugate of B_b."""
+    n = len(basis)
+    out = [[Fraction(0)] * n for _ in range(n)]
+    for i, (p, s0, s1) in enumerate(basis):
+        col_of = {rows[0]: p, rows[1]: cols[1] if p == cols[0] else cols[0]}
+        row_at = {v: k for k, v in col_of.items()}
+        conj = {rows[0]: tuple(reversed(s0)), rows[1]: tuple(reversed(s1))}
+        for j, (pp, t0, t1) in enumerate(basis):
+            colp = {rows[0]: pp, rows[1]: cols[1] if pp == cols[0] else cols[0]}
+            strp = {rows[0]: t0, rows[1]: t1}
+            loops, seen = [], set()
+            for start in rows:
+                if start in seen:
+                    continue
+                word, r = (), start
+                while r not in seen:
+                    seen.add(r)
+                    word += strp[r]
+                    back = row_at[colp[r]]          # the row B_b joins to that column
+                    word += conj[back]
+                    r = back
+                loops.append(word)
+            out[i][j] = trace_product(_canon(loops))
     return out

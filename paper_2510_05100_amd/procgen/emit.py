@@ -35,7 +35,7 @@ def _nsf(leg: Leg) -> int:
 def good_helicities(d: Diagrams) -> List[int]:
     legs = d.process.legs
     n = len(legs)
-    lines = [d.process.line(f) for f in {l.field for l in legs if l.is_fermion}]
+    lines = [d.process.line(f) for f in {l.field for l in legs if l.is_fermion} if FERMIONS[f][3] is None]
     good = []
     for hel in range(1 << n):
         h = [1 if (hel >> (n - 1 - i)) & 1 else -1 for i in range(n)]
@@ -58,6 +58,13 @@ class Emitter:
         self.count = {"ixx": 0, "oxx": 0, "vxx": 0, "ffv_in": 0, "ffv_out": 0, "ffv_vec0": 0,
                       "ffv_vecm": 0, "vvv_vec": 0, "vvvv_vec": 0, "ffv_amp": 0, "pair_w": 0}
         self.n = 0
+        self.two = d.term_lines is not None
+        self.line = (d.bleg.idx, d.fleg.idx)     # main line of the amplitude being emitted
+
+    def lkey(self, kind, seq, line):
+        """Cache key of a line current; the line is part of it when the
+        process has two coloured lines."""
+        return (kind, seq, line) if self.two else (kind, seq)
 
     def new(self, prefix):
         self.n += 1
@@ -126,6 +133,17 @@ class Emitter:
         key = ("glu", t)
         if key in self.cache:
             return self.cache[key]
+        if t[0] == "line":
+            # the gluon a second line emits: row and column currents of that
+            # line on either side of the emission vertex, joined
+            line = (t[1], t[2])
+            fo, fi = self.bcur(t[3], line), self.fcur(t[4], line)
+            q = self.block_k(("glu", t))
+            name = self.new("v")
+            self.emit(f"const Vec<R> {name} = ffv_vec0_v<R>({fo}, {fi}, cd.gqq, {q});")
+            self.count["ffv_vec0"] += 1
+            self.cache[key] = name
+            return name
         name = self.new("g")
         if t[0] == "v3":
             j1, j2 = self.gluon(t[1]), self.gluon(t[2])
@@ -174,16 +192,18 @@ class Emitter:
         return v, "c", f"cd.zL[{s}], cd.zR[{s}]"
 
     # main-line currents ---------------------------------------------------
-    def fcur(self, seq):
+    def fcur(self, seq, line=None):
         """Column spinor: Fcur(A_j..A_k) = S(q) Gamma(A_j) Fcur(A_{j+1}..A_k)."""
+        line = line or self.line
+        fleg = self.d.process.legs[line[1]]
         if not seq:
-            return self.ext(self.d.fleg)
-        key = ("F", seq)
+            return self.ext(fleg)
+        key = self.lkey("F", seq, line)
         if key in self.cache:
             return self.cache[key]
-        inner = self.fcur(seq[1:])
+        inner = self.fcur(seq[1:], line)
         v, kind, k = self.attach(seq[0])
-        legs = [self.d.fleg.idx] + [l for b in seq for l in self.block_legs(b)]
+        legs = [fleg.idx] + [l for b in seq for l in self.block_legs(b)]
         q = self.ksum(tuple((1, l) for l in legs))
         name = self.new("f")
         self.emit(f"const Spinor<R> {name} = ffv_in_{kind}<R>({inner}, {v}, {k}, {q}, {_mass(self.d.main)});")
@@ -191,16 +211,18 @@ class Emitter:
         self.cache[key] = name
         return name
 
-    def bcur(self, seq):
+    def bcur(self, seq, line=None):
         """Row spinor: Bcur(A_1..A_j) = Bcur(A_1..A_{j-1}) Gamma(A_j) S(q)."""
+        line = line or self.line
+        bleg = self.d.process.legs[line[0]]
         if not seq:
-            return self.ext(self.d.bleg)
-        key = ("B", seq)
+            return self.ext(bleg)
+        key = self.lkey("B", seq, line)
         if key in self.cache:
             return self.cache[key]
-        inner = self.bcur(seq[:-1])
+        inner = self.bcur(seq[:-1], line)
         v, kind, k = self.attach(seq[-1])
-        legs = [self.d.bleg.idx] + [l for b in seq for l in self.block_legs(b)]
+        legs = [bleg.idx] + [l for b in seq for l in self.block_legs(b)]
         q = self.ksum(tuple((-1, l) for l in legs))
         name = self.new("b")
         self.emit(f"const Spinor<R> {name} = ffv_out_{kind}<R>({inner}, {v}, {k}, {q}, {_mass(self.d.main)});")
@@ -208,18 +230,9 @@ class Emitter:
         self.cache[key] = name
         return name
 
-    def missing(self, seq, m):
-        """Number of main-line currents a split at m would newly build."""
-        n = 0
-        for j in range(1, m + 1):
-            n += ("B", seq[:j]) not in self.cache
-        for j in range(m + 1, len(seq)):
-            n += ("F", seq[j:]) not in self.cache
-        return n
-
     def wpair(self, bseq, fseq):
         """W = X + Y of a (row, column) pair shared by several amplitudes."""
-        key = ("W", bseq, fseq)
+        key = ("W", bseq, fseq) + ((self.line,) if self.two else ())
         if key in self.cache:
             return self.cache[key]
         fo, fi = self.bcur(bseq), self.fcur(fseq)
@@ -258,7 +271,13 @@ class Emitter:
 def colour_matrix_ints(d: Diagrams):
     if not FERMIONS[d.main][2]:
         return [[1]], 1                       # colourless main line: no colour sum
-    cm = col.colour_matrix(d.basis)
+    if d.term_lines is not None:
+        rows = sorted(l.idx for l in d.process.legs if l.field == d.main and l.kind == "B")
+        cols = sorted(l.idx for l in d.process.legs if l.field == d.main and l.kind == "F")
+        s2 = Fraction(d.colour_scale * d.colour_scale)
+        cm = [[x / s2 for x in row] for row in col.colour_matrix_two_lines(d.basis, rows, cols)]
+    else:
+        cm = col.colour_matrix(d.basis)
     den = 1
     for row in cm:
         for x in row:
@@ -280,20 +299,29 @@ def node_deps(em: "Emitter", key):
         t = key[1]
         if t[0] == "leaf":
             return [("ext", t[1])]
+        if t[0] == "line":
+            line = (t[1], t[2])
+            b = ("B", t[3], line) if t[3] else ("ext", line[0])
+            f = ("F", t[4], line) if t[4] else ("ext", line[1])
+            return [b, f]
         kids = t[1:] if t[0] == "v3" else t[2:]
         return [("ext", c[1]) if c[0] == "leaf" else ("glu", c) for c in kids]
     if kind == "pair":
         sb, sf = d.process.line(key[2])
         return [("ext", sb.idx), ("ext", sf.idx)]
     if kind == "W":
-        b = ("B", key[1]) if key[1] else ("ext", d.bleg.idx)
-        f = ("F", key[2]) if key[2] else ("ext", d.fleg.idx)
+        line = key[3] if len(key) > 3 else (d.bleg.idx, d.fleg.idx)
+        extra = key[3:]
+        b = ("B", key[1]) + extra if key[1] else ("ext", line[0])
+        f = ("F", key[2]) + extra if key[2] else ("ext", line[1])
         return [b, f]
     seq = key[1]
+    line = key[2] if len(key) > 2 else (d.bleg.idx, d.fleg.idx)
+    extra = key[2:]
     if kind == "F":
-        inner = ("F", seq[1:]) if len(seq) > 1 else ("ext", d.fleg.idx)
+        inner = ("F", seq[1:]) + extra if len(seq) > 1 else ("ext", line[1])
         return [inner, attach_key(seq[0])]
-    inner = ("B", seq[:-1]) if len(seq) > 1 else ("ext", d.bleg.idx)
+    inner = ("B", seq[:-1]) + extra if len(seq) > 1 else ("ext", line[0])
     return [inner, attach_key(seq[-1])]
 
 
@@ -308,6 +336,10 @@ def _vector_middle(blk):
     return blk[0] == "glu" or blk[1] == "a"
 
 
+def term_line(d: Diagrams, t):
+    return d.term_lines[t] if d.term_lines is not None else (d.bleg.idx, d.fleg.idx)
+
+
 def plan_splits(d: Diagrams):
     """Split point per amplitude term and whether its (row, column) pair is
     shared.  First, pairs (Bcur(A_1..A_{m-1}), Fcur(A_{m+1}..)) that several
@@ -318,11 +350,12 @@ def plan_splits(d: Diagrams):
     from collections import Counter
     options = []
     counts = Counter()
-    for seq, _ in d.terms:
+    two = d.term_lines is not None
+    for t, (seq, _) in enumerate(d.terms):
         opts = {}
         for m in range(len(seq)):
             if _vector_middle(seq[m]):
-                opts[(seq[:m], seq[m + 1:])] = m
+                opts[(seq[:m], seq[m + 1:]) + ((term_line(d, t),) if two else ())] = m
         options.append(opts)
         counts.update(opts.keys())
     splits = [None] * len(d.terms)
@@ -341,28 +374,32 @@ def plan_splits(d: Diagrams):
         if splits[t] is None:
             continue
         m = splits[t]
-        have.update(("B", seq[:j]) for j in range(1, m + 1))
-        have.update(("F", seq[j:]) for j in range(m + 1, len(seq)))
+        x = (term_line(d, t),) if two else ()
+        have.update(("B", seq[:j]) + x for j in range(1, m + 1))
+        have.update(("F", seq[j:]) + x for j in range(m + 1, len(seq)))
     for t, (seq, _) in enumerate(d.terms):
         if splits[t] is not None:
             continue
         k = len(seq)
+        x = (term_line(d, t),) if two else ()
 
         def missing(m):
-            n = sum(("B", seq[:j]) not in have for j in range(1, m + 1))
-            return n + sum(("F", seq[j:]) not in have for j in range(m + 1, k))
+            n = sum(("B", seq[:j]) + x not in have for j in range(1, m + 1))
+            return n + sum(("F", seq[j:]) + x not in have for j in range(m + 1, k))
         m = min(range(k), key=lambda m: (missing(m), abs(m - (k - 1) / 2)))
-        have.update(("B", seq[:j]) for j in range(1, m + 1))
-        have.update(("F", seq[j:]) for j in range(m + 1, k))
+        have.update(("B", seq[:j]) + x for j in range(1, m + 1))
+        have.update(("F", seq[j:]) + x for j in range(m + 1, k))
         splits[t] = m
     return splits, shared
 
 
-def term_roots(d: Diagrams, seq, m, shared=False):
+def term_roots(d: Diagrams, seq, m, shared=False, line=None):
+    line = line or (d.bleg.idx, d.fleg.idx)
+    x = (line,) if d.term_lines is not None else ()
     if shared:
-        return [("W", seq[:m], seq[m + 1:]), attach_key(seq[m])]
-    b = ("B", seq[:m]) if m > 0 else ("ext", d.bleg.idx)
-    f = ("F", seq[m + 1:]) if m + 1 < len(seq) else ("ext", d.fleg.idx)
+        return [("W", seq[:m], seq[m + 1:]) + x, attach_key(seq[m])]
+    b = ("B", seq[:m]) + x if m > 0 else ("ext", line[0])
+    f = ("F", seq[m + 1:]) + x if m + 1 < len(seq) else ("ext", line[1])
     return [b, f, attach_key(seq[m])]
 
 
@@ -381,9 +418,9 @@ def schedule(em: "Emitter", splits, shared):
         return closure[key]
 
     term_nodes = []
-    for (seq, _), m, sh in zip(d.terms, splits, shared):
+    for t, ((seq, _), m, sh) in enumerate(zip(d.terms, splits, shared)):
         s = set()
-        for r in term_roots(d, seq, m, sh):
+        for r in term_roots(d, seq, m, sh, term_line(d, t)):
             s |= clos(r)
         term_nodes.append(frozenset(s))
     uses = {}
@@ -486,6 +523,7 @@ def emit_body(d: Diagrams, groups: int):
             em.emit("term_fence();")
             em.emit("{  // next group: currents are rebuilt from here on")
         seq, colour = d.terms[t]
+        em.line = term_line(d, t)
         em.amplitude(seq, colour, splits[t], shared[t])
     em.emit("}")
     return em
@@ -506,8 +544,14 @@ def generate(d: Diagrams, groups: int | None = None) -> str:
     out = []
     out.append(f"// Generated by paper_2510_05100_amd.procgen for '{name}'. Do not edit.")
     out.append(f"// {d.n_diagrams} Feynman diagrams, {len(d.terms)} amplitude terms, {ncol} colour flows.")
-    out.append("// Colour basis (gluon leg ids on the main line, row end first): "
-               + " ".join("(" + ",".join(map(str, b)) + ")" for b in d.basis))
+    if d.term_lines is not None:
+        out.append("// Colour basis (column leg joined to the first quark; gluon leg ids on the first and the"
+                   " second quark's string, row end first): "
+                   + " ".join(f"[{b[0]}; ({','.join(map(str, b[1]))}) ({','.join(map(str, b[2]))})]" for b in d.basis))
+        out.append(f"// Colour coefficients times {d.colour_scale}; the colour matrix is divided accordingly.")
+    else:
+        out.append("// Colour basis (gluon leg ids on the main line, row end first): "
+                   + " ".join("(" + ",".join(map(str, b)) + ")" for b in d.basis))
     out.append("#pragma once")
     out.append('#include "helas.h"')
     out.append('#include "card.h"')
