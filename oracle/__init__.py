@@ -19,6 +19,10 @@ order the same section gives for the reweighting step):
   Berends-Giele recursion, colour matrix by brute-force summation over
   Gell-Mann matrices (``qcd_bg``, ``colour``).  This is a different algorithm
   from the diagram-by-diagram device path.
+* g g -> t t~ t t~ (pure QCD): colour-dressed Berends-Giele recursion with
+  every external colour index left open and explicit Dirac matrices, the two
+  assignments of antitops to tops added with the Fermi sign
+  (``qcd_dressed``); again not diagram by diagram.
 
 Parity is pinned (``tests/test_oracle_*.py``) by closed forms, invariants,
 brute force and exact scaling laws; see each module for what pins it.

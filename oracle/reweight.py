@@ -14,9 +14,9 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import ee_mumu, qcd_bg, uu_eeg
+from . import ee_mumu, qcd_bg, qcd_dressed, uu_eeg
 
-ME2 = {"ee_mumu": ee_mumu.me2, "uu_eeg": uu_eeg.me2, "gg_ttgg": qcd_bg.me2}
+ME2 = {"ee_mumu": ee_mumu.me2, "uu_eeg": uu_eeg.me2, "gg_ttgg": qcd_bg.me2, "gg_tttt": qcd_dressed.me2_gg_tttt}
 
 
 def me2(process: str, p: np.ndarray, card) -> np.ndarray:

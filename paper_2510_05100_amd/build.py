@@ -19,7 +19,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librwgt.so")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "proc_ee_mumu.hip", "proc_uu_eeg.hip", "proc_gg_ttgg.hip", "batch.hip", "mlp.hip", "mlp_abi.cpp", "mlp_train.cpp", "rwgt_abi.cpp", "lhe.cpp"]
+SOURCES = ["kernels.hip", "proc_ee_mumu.hip", "proc_uu_eeg.hip", "proc_gg_ttgg.hip", "proc_gg_tttt.hip", "batch.hip", "mlp.hip", "mlp_abi.cpp", "mlp_train.cpp", "rwgt_abi.cpp", "lhe.cpp"]
 
 # -packed-fp32-ops: no v_pk_{add,mul,fma}_f32 in generated code.
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-I" + CSRC,

@@ -9,7 +9,7 @@
 
 namespace rwgt {
 
-enum { kProcEeMumu = 0, kProcUuEeg = 1, kProcGgTtgg = 2 };
+enum { kProcEeMumu = 0, kProcUuEeg = 1, kProcGgTtgg = 2, kProcGgTttt = 3 };
 enum { kPrecFP64 = 0, kPrecMixedFP16 = 1, kPrecMixedBF16 = 2 };
 constexpr int kMeBlock = 256;
 
@@ -87,6 +87,7 @@ double process_flops(int proc);
 RWGT_DECLARE_PROCESS(ee_mumu)
 RWGT_DECLARE_PROCESS(uu_eeg)
 RWGT_DECLARE_PROCESS(gg_ttgg)
+RWGT_DECLARE_PROCESS(gg_tttt)
 #undef RWGT_DECLARE_PROCESS
 
 }  // namespace rwgt

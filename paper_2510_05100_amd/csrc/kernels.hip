@@ -288,6 +288,7 @@ hipError_t launch_me(int proc, int precision, const double* soa, int64_t nevt, c
     case kProcEeMumu: return launch_me_ee_mumu(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, s);
     case kProcUuEeg: return launch_me_uu_eeg(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, s);
     case kProcGgTtgg: return launch_me_gg_ttgg(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, s);
+    case kProcGgTttt: return launch_me_gg_tttt(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, s);
   }
   return hipErrorInvalidValue;
 }
@@ -300,6 +301,8 @@ hipError_t launch_me_guarded(int proc, int precision, const double* soa, int64_t
     case kProcUuEeg: return launch_me_guarded_uu_eeg(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, g, s);
     case kProcGgTtgg:
       return launch_me_guarded_gg_ttgg(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, g, s);
+    case kProcGgTttt:
+      return launch_me_guarded_gg_tttt(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, g, s);
   }
   return hipErrorInvalidValue;
 }
@@ -309,6 +312,7 @@ void process_constants(int proc, int* npart, int* ngood, int* ncol, int* ndiag) 
     case kProcEeMumu: constants_ee_mumu(npart, ngood, ncol, ndiag); break;
     case kProcUuEeg: constants_uu_eeg(npart, ngood, ncol, ndiag); break;
     case kProcGgTtgg: constants_gg_ttgg(npart, ngood, ncol, ndiag); break;
+    case kProcGgTttt: constants_gg_tttt(npart, ngood, ncol, ndiag); break;
     default: *npart = *ngood = *ncol = *ndiag = 0;
   }
 }
@@ -318,6 +322,7 @@ double process_flops(int proc) {
     case kProcEeMumu: return flops_ee_mumu();
     case kProcUuEeg: return flops_uu_eeg();
     case kProcGgTtgg: return flops_gg_ttgg();
+    case kProcGgTttt: return flops_gg_tttt();
   }
   return 0.0;
 }

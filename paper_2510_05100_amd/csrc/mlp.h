@@ -156,13 +156,14 @@ int train_tile_rows(int width);
 int64_t train_zws_floats(int width, int nh);
 hipError_t mlp_train_grads(int width, const TrainArgs& a, hipStream_t s);
 // Per Adam segment: the packed copies of the parameter to refresh (NULL: none).
+// Plain data (copied to LDS by the update kernel); value-initialise on the host.
 struct PackSeg {
-  float* grad = nullptr;               // the gradient buffer (written with the sums)
-  void* hi = nullptr;                  // packed forward order (BF16), nchunks of 16 columns
-  void* lo = nullptr;                  // its low parts (first layer)
-  void* tr = nullptr;                  // packed transposed order
-  int nchunks = 0, tchunks = 0;
-  float* bias = nullptr;               // contiguous hidden-layer biases
+  float* grad;                         // the gradient buffer (written with the sums)
+  void* hi;                            // packed forward order (BF16), nchunks of 16 columns
+  void* lo;                            // its low parts (first layer)
+  void* tr;                            // packed transposed order
+  int nchunks, tchunks;
+  float* bias;                         // contiguous hidden-layer biases
 };
 hipError_t mlp_train_update(const AdamSeg* segs, const PackSeg* pk, int nseg, int64_t total, const float* part,
                             int groups, int64_t pstride, float* loss, int adam, float lr, float b1, float b2,

@@ -1,0 +1,59 @@
+// Matrix-element kernels for the generated process gg_tttt (FP64 and mixed).
+#include "generated/gen_gg_tttt.h"
+#include "me_kernel.h"
+#include "opcount.h"
+
+namespace rwgt {
+
+RWGT_PROCESS_TRAITS(gg_tttt)
+
+hipError_t launch_me_gg_tttt(int precision, const double* soa, int64_t nevt, const CardPair* cards, int ncards,
+                            const double* w_in, double* w_out, double* me_out, hipStream_t s) {
+  return launch_me_prec<Proc_gg_tttt>(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, s);
+}
+
+hipError_t launch_me_guarded_gg_tttt(int precision, const double* soa, int64_t nevt, const CardPair* cards,
+                                    int ncards, const double* w_in, double* w_out, double* me_out,
+                                    const GuardArgs& g, hipStream_t s) {
+  return launch_me_guarded_t<Proc_gg_tttt>(precision, soa, nevt, cards, ncards, w_in, w_out, me_out, g, s);
+}
+
+void constants_gg_tttt(int* npart, int* ngood, int* ncol, int* ndiag) {
+  *npart = gen_gg_tttt::NPART;
+  *ngood = gen_gg_tttt::NGOOD;
+  *ncol = gen_gg_tttt::NCOL;
+  *ndiag = gen_gg_tttt::NDIAG;
+}
+
+// Floating-point operations of one |M|^2 (all kept helicities, colour sums,
+// average), counted by running the generated code on the host with OpCnt at a
+// representative point (beams along +-z, final state in generic directions).
+double flops_gg_tttt() {
+  constexpr int N = gen_gg_tttt::NPART;
+  static const double pts[6][4] = {{500.0, 0.0, 0.0, 500.0}, {500.0, 0.0, 0.0, -500.0},
+                                   {300.0, 110.0, -150.0, 90.0}, {250.0, -60.0, 120.0, -170.0},
+                                   {260.0, -30.0, 20.0, 90.0}, {190.0, -20.0, 10.0, -10.0}};
+  OpCnt P[N][4];
+  for (int a = 0; a < N; ++a)
+    for (int mu = 0; mu < 4; ++mu) P[a][mu] = pts[a][mu];
+  Card<OpCnt, OpCnt> cd;
+  cd.gqq = 1.2;
+  cd.g3 = 1.2;
+  cd.g4 = 1.44;
+  for (int f = 0; f < 4; ++f) {
+    cd.a[f] = 0.3;
+    cd.zL[f] = 0.2;
+    cd.zR[f] = 0.1;
+  }
+  cd.mz = 91.0;
+  cd.wz = 2.5;
+  cd.mt = 173.0;
+  OpCounter::flops = 0;
+  cx<OpCnt> j[gen_gg_tttt::NCOL];
+  gen_gg_tttt::jamps<OpCnt, OpCnt>(P, gen_gg_tttt::GOOD_HOST[0], cd, j);
+  (void)gen_gg_tttt::colour_sum<OpCnt>(j);
+  const double per_hel = double(OpCounter::flops) + 1.0;   // + accumulate into the sum
+  return per_hel * gen_gg_tttt::NGOOD + 1.0;                 // + average factor
+}
+
+}  // namespace rwgt

@@ -50,6 +50,8 @@ const std::vector<ProcessDef>& processes() {
        {"SMINPUTS 1", "SMINPUTS 3", "RWGTEW 1", "MASS 23", "DECAY 23"}, {}},
       {"g g > t t~ g g", rwgt::kProcGgTtgg, 6,
        {"SMINPUTS 3", "MASS 6"}, {"SMINPUTS 3", "MASS 6"}, {"MASS 6"}},
+      {"g g > t t~ t t~", rwgt::kProcGgTttt, 6,
+       {"SMINPUTS 3", "MASS 6"}, {"SMINPUTS 3", "MASS 6"}, {"MASS 6"}},
   };
   return defs;
 }
@@ -578,7 +580,7 @@ int rwgt_eval_factored(rwgt_ctx* c, const double* momenta, int64_t nevt, const d
     if (nevt == 0) return RWGT_OK;
     if (!momenta || !w_in || !w_out) return c->fail(RWGT_EINVAL, "NULL device pointer");
     const int id = c->def->id;
-    const bool ew = id != rwgt::kProcGgTtgg;
+    const bool ew = id == rwgt::kProcEeMumu || id == rwgt::kProcUuEeg;
     const int f1 = id == rwgt::kProcUuEeg ? 2 : 0;         // u or e line
     const int f2 = id == rwgt::kProcUuEeg ? 0 : 1;         // e or mu line
     const int ia = 2, ib = 3;                              // the outgoing lepton pair

@@ -15,7 +15,7 @@ import numpy as np
 
 from . import _abi
 
-PROCESSES = ("e+ e- > mu+ mu-", "u u~ > e+ e- g", "g g > t t~ g g")
+PROCESSES = ("e+ e- > mu+ mu-", "u u~ > e+ e- g", "g g > t t~ g g", "g g > t t~ t t~")
 # The reweighting card's "change fptype": d is FP64 and f single-precision
 # amplitudes (the library's mixed mode).  The paper's default m keeps the
 # amplitudes in FP64 and only the colour algebra in FP32; it runs here as FP64

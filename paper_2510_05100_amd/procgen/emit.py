@@ -506,7 +506,7 @@ def refine_order(order, term_nodes, iters=30000, seed=20251005):
 # Groups of amplitude terms per helicity.  Between groups every current is
 # forgotten and rebuilt on demand (from opaque momentum reads, so nothing is
 # carried across): fewer currents live at once for some recomputation.
-GROUPS = {"gg_ttgg": 3}
+GROUPS = {"gg_ttgg": 3, "gg_tttt": 2}
 
 
 def emit_body(d: Diagrams, groups: int):

@@ -23,6 +23,7 @@ PROCESSES = {
     "ee_mumu": "e+ e- > mu+ mu-",
     "uu_eeg": "u u~ > e+ e- g",
     "gg_ttgg": "g g > t t~ g g",
+    "gg_tttt": "g g > t t~ t t~",
 }
 
 # Names of the per-card parameters each process depends on, in the order of a
@@ -31,6 +32,7 @@ PARAM_LAYOUT = {
     "ee_mumu": ("SMINPUTS 1", "RWGTEW 1", "MASS 23", "DECAY 23"),
     "uu_eeg": ("SMINPUTS 1", "SMINPUTS 3", "RWGTEW 1", "MASS 23", "DECAY 23"),
     "gg_ttgg": ("SMINPUTS 3", "MASS 6"),
+    "gg_tttt": ("SMINPUTS 3", "MASS 6"),
 }
 
 CHUNK = 1 << 16
@@ -77,7 +79,7 @@ NEW_UU = dataclasses.replace(ORIG_EW, MZ=91.5, WZ=2.6, sw2=0.2312)
 ORIG_QCD = Card(aS=0.118, MT=173.0)
 NEW_QCD = dataclasses.replace(ORIG_QCD, aS=0.130)
 
-SEED_EVENTS = {"ee_mumu": 1000, "uu_eeg": 1001, "gg_ttgg": 1002}
+SEED_EVENTS = {"ee_mumu": 1000, "uu_eeg": 1001, "gg_ttgg": 1002, "gg_tttt": 1003}
 SEED_BATCH_COUNTS = 2000
 SEED_SUR_TRAIN = 3000
 SEED_SUR_HELDOUT = 3001
@@ -165,7 +167,18 @@ def gg_ttgg_events(n: int, seed: int = SEED_EVENTS["gg_ttgg"], mt: float = 173.0
     return np.concatenate(out)[:n]
 
 
-GENERATORS = {"ee_mumu": ee_mumu_events, "uu_eeg": uu_eeg_events, "gg_ttgg": gg_ttgg_events}
+def gg_tttt_events(n: int, seed: int = SEED_EVENTS["gg_tttt"], mt: float = 173.0) -> np.ndarray:
+    """g (+z) g (-z) -> t t~ t t~; sqrt(s_hat) uniform in [800, 2500] GeV,
+    massive 4-body RAMBO (four times mt); no cuts (every final particle is
+    massive)."""
+    rng = np.random.default_rng(seed)
+    sqrt_s = rng.uniform(800.0, 2500.0, n)
+    fin = rambo_massive(rng, n, [mt, mt, mt, mt], sqrt_s)
+    return np.concatenate([_beams(sqrt_s), fin], axis=1)
+
+
+GENERATORS = {"ee_mumu": ee_mumu_events, "uu_eeg": uu_eeg_events, "gg_ttgg": gg_ttgg_events,
+              "gg_tttt": gg_tttt_events}
 
 
 def events(process: str, n: int, seed: int | None = None) -> np.ndarray:

@@ -3,7 +3,8 @@ through the C ABI binding."""
 import numpy as np
 import pytest
 
-PROCESS_TEXT = {"ee_mumu": "e+ e- > mu+ mu-", "uu_eeg": "u u~ > e+ e- g", "gg_ttgg": "g g > t t~ g g"}
+PROCESS_TEXT = {"ee_mumu": "e+ e- > mu+ mu-", "uu_eeg": "u u~ > e+ e- g", "gg_ttgg": "g g > t t~ g g",
+                "gg_tttt": "g g > t t~ t t~"}
 
 
 def torch_cuda():
