@@ -144,8 +144,9 @@ def mixed_errors(rw, torch, p, p_dev, w_dev, rows, x, f, sample=200):
 
 
 def workload_leg(rw, torch, proc, orig, new, n, steps, warmup, oracle_sample):
-    """One of the electroweak workloads at its own size (e+ e- -> mu+ mu-, 1e4
-    events, or u u~ -> e+ e- g, 1e6 events, one new card), FP64 and mixed:
+    """One of the other workloads at its own size (e+ e- -> mu+ mu-, 1e4
+    events; u u~ -> e+ e- g, 1e6 events; g g -> t t~ t t~, 1e6 events; one new
+    card), FP64 and mixed:
     reweighted events/s of the same timed rwgt_eval step as the headline,
     errors of w' and |M|^2 against the oracle on an evenly spaced sample, the
     mixed w' against the FP64 path on every event, and the FLOP rate of the
@@ -462,7 +463,8 @@ def main():
     if not a.no_workloads:
         line["workloads"] = {}
         for key, proc, orig, new, n, sample in (("ee_mumu_1e4", "ee_mumu", synth.ORIG_EW, synth.NEW_EE, 10_000, 10_000),
-                                                ("uu_eeg_1e6", "uu_eeg", synth.ORIG_EW, synth.NEW_UU, 1_000_000, 1000)):
+                                                ("uu_eeg_1e6", "uu_eeg", synth.ORIG_EW, synth.NEW_UU, 1_000_000, 1000),
+                                                ("gg_tttt_1e6", "gg_tttt", synth.ORIG_QCD, synth.NEW_QCD, 1_000_000, 6)):
             line["workloads"][key] = workload_leg(rw, torch, proc, orig, new, n, steps=a.steps, warmup=a.warmup,
                                                   oracle_sample=sample)
             log(f"{key}: fp64 {line['workloads'][key]['fp64']['value']:.3g}, mixed "
