@@ -190,12 +190,21 @@ const char *rwgt_create_error(void);
 /* Process constants: particles, helicity combinations kept, colour flows, diagrams. */
 int rwgt_process_info(const rwgt_ctx *ctx, int32_t *npart, int32_t *nhel_kept, int32_t *ncol, int32_t *ndiag);
 
-/* Floating-point operations of one |M|^2 evaluation (all helicities kept,
- * colour sums, averaging) as written in the kernels, counted by running the
- * same generated code on the host with an operation-counting scalar.  One
- * rwgt_eval over nevt events and nsets cards performs (1 + nsets) * nevt of
- * them.  Used to express measured throughput as FLOP/s against the peak. */
+/* Floating-point operations of one |M|^2 evaluation as the plain sum over
+ * every kept helicity (colour sums and averaging included), counted by
+ * running the generated amplitude code on the host with an
+ * operation-counting scalar.  One rwgt_eval over nevt events and nsets cards
+ * computes (1 + nsets) * nevt of them.  Used to express measured throughput
+ * as FLOP/s against the peak (the algorithmic rate). */
 int rwgt_flops(const rwgt_ctx *ctx, double *flops_per_me2);
+
+/* The same count for the helicities the kernels actually evaluate.  For the
+ * pure-QCD processes (g g > t t~ g g, g g > t t~ t t~) reversing every
+ * helicity leaves |M_h|^2 unchanged (parity of QCD), so of the
+ * helicity-summed |M|^2 (MadtRex section, Usage) one helicity of each
+ * reversed pair is evaluated and counted twice: half of rwgt_flops.
+ * Otherwise equal to rwgt_flops.  Gives the executed rate. */
+int rwgt_flops_executed(const rwgt_ctx *ctx, double *flops_per_me2);
 
 /* Reweighted cross sections and their errors for nsets cards (teaRex section):
  *   sigma'_k  = norm * sum_i w'_ki,

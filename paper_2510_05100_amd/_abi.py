@@ -40,6 +40,7 @@ SIGNATURES = {
     "rwgt_create_error": (ctypes.c_char_p, []),
     "rwgt_process_info": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int32)] * 4),
     "rwgt_flops": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "rwgt_flops_executed": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "rwgt_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "rwgt_kernel_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
                                           ctypes.POINTER(ctypes.c_float)]),
@@ -360,6 +361,14 @@ def rwgt_process_info(ctx):
 def rwgt_flops(ctx):
     out = ctypes.c_double()
     rc = load().rwgt_flops(ctx, ctypes.byref(out))
+    if rc != 0:
+        _raise(rc, ctx)
+    return out.value
+
+
+def rwgt_flops_executed(ctx):
+    out = ctypes.c_double()
+    rc = load().rwgt_flops_executed(ctx, ctypes.byref(out))
     if rc != 0:
         _raise(rc, ctx)
     return out.value

@@ -49,6 +49,7 @@ __device__ __forceinline__ void hel_group_event(const double* __restrict__ src, 
                                                 const CardPair& c1, const double* __restrict__ w_in,
                                                 double* __restrict__ w_out) {
   constexpr int G = PROC::NGOOD;
+  static_assert(PROC::NSUM == G, "every kept helicity is evaluated (no reversed-helicity weight)");
   double P[PROC::NPART][4];
 #pragma unroll
   for (int a = 0; a < PROC::NPART; ++a)

@@ -74,7 +74,7 @@ int nonfinite_blocks(int64_t n);
 hipError_t launch_nonfinite(const double* x, int64_t n, unsigned long long* part, hipStream_t s);
 
 void process_constants(int proc, int* npart, int* ngood, int* ncol, int* ndiag);
-double process_flops(int proc);
+double process_flops(int proc, bool executed);
 
 #define RWGT_DECLARE_PROCESS(NAME)                                                                        \
   hipError_t launch_me_##NAME(int precision, const double* soa, int64_t nevt, const CardPair* cards,     \
@@ -83,7 +83,7 @@ double process_flops(int proc);
                                       int ncards, const double* w_in, double* w_out, double* me_out,          \
                                       const GuardArgs& g, hipStream_t s);                                     \
   void constants_##NAME(int* npart, int* ngood, int* ncol, int* ndiag);                                 \
-  double flops_##NAME();
+  double flops_##NAME(bool executed);
 RWGT_DECLARE_PROCESS(ee_mumu)
 RWGT_DECLARE_PROCESS(uu_eeg)
 RWGT_DECLARE_PROCESS(gg_ttgg)

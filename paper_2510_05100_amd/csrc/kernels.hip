@@ -317,12 +317,12 @@ void process_constants(int proc, int* npart, int* ngood, int* ncol, int* ndiag) 
   }
 }
 
-double process_flops(int proc) {
+double process_flops(int proc, bool executed) {
   switch (proc) {
-    case kProcEeMumu: return flops_ee_mumu();
-    case kProcUuEeg: return flops_uu_eeg();
-    case kProcGgTtgg: return flops_gg_ttgg();
-    case kProcGgTttt: return flops_gg_tttt();
+    case kProcEeMumu: return flops_ee_mumu(executed);
+    case kProcUuEeg: return flops_uu_eeg(executed);
+    case kProcGgTtgg: return flops_gg_ttgg(executed);
+    case kProcGgTttt: return flops_gg_tttt(executed);
   }
   return 0.0;
 }

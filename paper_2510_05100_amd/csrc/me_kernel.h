@@ -20,6 +20,8 @@ namespace rwgt {
     static constexpr int NCOL = gen_##NAME::NCOL;                                              \
     static constexpr int NGOOD = gen_##NAME::NGOOD;                                            \
     static constexpr double AVERAGE = gen_##NAME::AVERAGE;                                     \
+    static constexpr int NSUM = gen_##NAME::NSUM;                                              \
+    static constexpr double SCALE = gen_##NAME::AVERAGE * gen_##NAME::HELW;                    \
     static constexpr int CDEN = gen_##NAME::CDEN;                                              \
     static __device__ __forceinline__ const int (&cnum())[NCOL][NCOL] { return gen_##NAME::CNUM; } \
     static __device__ __forceinline__ int good(int i) { return gen_##NAME::GOOD[i]; }         \
@@ -86,18 +88,21 @@ __device__ __forceinline__ cx<R> (&flows(cx<R> (&j)[NCOL]))[NCOL] { return j; }
 template <class PROC, class R>
 __device__ __forceinline__ double me2_event(const double (&P)[PROC::NPART][4], const Card<R>& cd) {
   double me = 0.0;
-  for (int ih = 0; ih < PROC::NGOOD; ++ih) {
+  for (int ih = 0; ih < PROC::NSUM; ++ih) {
     cx<R> jamp[PROC::NCOL];
     PROC::template jamps<R>(P, PROC::good(ih), cd, jamp);
     me += double(PROC::template colour_sum<R>(jamp));
   }
-  return me * PROC::AVERAGE;
+  return me * PROC::SCALE;
 }
 
 // LDS of the matrix-core colour sum (one region per wave), or nothing.
 template <class CT> struct ColourLdsOf { typedef ColourLds<CT> type; };
 template <> struct ColourLdsOf<void> { typedef char type; };
 
+// Helicities: the first NSUM of the kept ones, weighted by HELW (for pure QCD
+// one of each pair with every helicity reversed, whose |M_h|^2 are equal,
+// weight 2; otherwise all of them, weight 1); SCALE = AVERAGE * HELW.
 // Waves per event group: the helicity sum of a many-flow process is split
 // between the HS waves of a 64 HS-lane workgroup (consecutive blocks of
 // helicities, each wave-uniform, added through LDS per card): HS times the
@@ -130,8 +135,8 @@ __global__ __launch_bounds__(kMeBlock) void me_kernel(const double* __restrict__
   constexpr bool kMfma = !std::is_void<CT>::value;
   constexpr int HS = hel_split<PROC>(), B = me_block<PROC>();
   constexpr int EPB = HS > 1 ? 64 : B;                        // events per workgroup
-  constexpr int NH = PROC::NGOOD / HS;                        // helicities per wave
-  static_assert(PROC::NGOOD % HS == 0 && EPB % 64 == 0, "helicity split");
+  constexpr int NH = PROC::NSUM / HS;                         // helicities per wave
+  static_assert(PROC::NSUM % HS == 0 && EPB % 64 == 0, "helicity split");
   static_assert(!GUARD || sizeof(R) == 4, "the guard watches single-precision amplitudes");
   // which helicities: wave-uniform, kept in a scalar register so that the
   // helicity of each loop trip stays uniform too
@@ -217,7 +222,7 @@ __global__ __launch_bounds__(kMeBlock) void me_kernel(const double* __restrict__
       const double kk = coh > 0.0 ? inco / coh : (inco > 0.0 ? __builtin_inf() : 0.0);
       kappa = kk > kappa || !(kk == kk) ? kk : kappa;
     }
-    me *= PROC::AVERAGE;
+    me *= PROC::SCALE;                           // average (and the reversed helicities)
     if (!valid || half != 0) continue;
     if (me_out) me_out[int64_t(k) * nevt + i] = me;
     if (w_out) {
@@ -240,10 +245,10 @@ static __global__ void zero_count_kernel(unsigned int* c) { *c = 0u; }
 
 // Double-precision re-evaluation of the events rows[0 .. *nrows) of a
 // many-flow process, one wave per event (grid-stride over the list), one lane
-// per kept helicity: each lane evaluates its helicity's |M_h|^2 (flows in
-// LDS) under every card, and lane 0 adds the lanes' values in me_kernel's
-// order (the first half of the helicities in sequence, the second half in
-// sequence, then their sum).  The per-helicity code is me_kernel's, but with
+// per evaluated helicity (the first NSUM kept ones): each lane evaluates its
+// helicity's |M_h|^2 (flows in LDS) under every card, and lane 0 adds the
+// lanes' values in me_kernel's order (the first half of the helicities in
+// sequence, the second half in sequence, then their sum).  The per-helicity code is me_kernel's, but with
 // the helicity per lane instead of per wave the compiler may round a last bit
 // differently (measured: within 1 ulp of me_kernel's result).
 // A short list keeps the chip busy for one helicity's evaluation per card,
@@ -254,7 +259,7 @@ __global__ __launch_bounds__(64) void me_wave_kernel(const double* __restrict__ 
                                                      const double* __restrict__ w_in, double* __restrict__ w_out,
                                                      double* __restrict__ me_out, const int32_t* __restrict__ rows,
                                                      const unsigned int* __restrict__ nrows) {
-  constexpr int NG = PROC::NGOOD;
+  constexpr int NG = PROC::NSUM;
   static_assert(NG <= 64 && hel_split<PROC>() == 2 && NG % 2 == 0, "one wave holds an event's helicities");
   __shared__ cx<double> lds_jamp[PROC::NCOL * 64];
   const int lane = int(threadIdx.x);
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(64) void me_wave_kernel(const double* __restrict__ 
       for (int h = NG / 2; h < NG; ++h) m1 += __shfl(hm, h);
       double me = m0;
       me += m1;
-      me *= PROC::AVERAGE;
+      me *= PROC::SCALE;
       if (lane == 0) {
         if (me_out) me_out[int64_t(k) * nevt + i] = me;
         if (w_out) {

@@ -25,10 +25,12 @@ void constants_ee_mumu(int* npart, int* ngood, int* ncol, int* ndiag) {
   *ndiag = gen_ee_mumu::NDIAG;
 }
 
-// Floating-point operations of one |M|^2 (all kept helicities, colour sums,
-// average), counted by running the generated code on the host with OpCnt at a
-// representative point (beams along +-z, final state in generic directions).
-double flops_ee_mumu() {
+// Floating-point operations of one |M|^2 (helicities, colour sums, average),
+// counted by running the generated code on the host with OpCnt at a
+// representative point (beams along +-z, final state in generic directions):
+// executed = false, the plain sum over every kept helicity; true, the
+// helicities the kernels evaluate (NSUM, with the reversed ones as a weight).
+double flops_ee_mumu(bool executed) {
   constexpr int N = gen_ee_mumu::NPART;
   static const double pts[6][4] = {{500.0, 0.0, 0.0, 500.0}, {500.0, 0.0, 0.0, -500.0},
                                    {300.0, 110.0, -150.0, 90.0}, {250.0, -60.0, 120.0, -170.0},
@@ -53,7 +55,7 @@ double flops_ee_mumu() {
   gen_ee_mumu::jamps<OpCnt, OpCnt>(P, gen_ee_mumu::GOOD_HOST[0], cd, j);
   (void)gen_ee_mumu::colour_sum<OpCnt>(j);
   const double per_hel = double(OpCounter::flops) + 1.0;   // + accumulate into the sum
-  return per_hel * gen_ee_mumu::NGOOD + 1.0;                 // + average factor
+  return per_hel * (executed ? gen_ee_mumu::NSUM : gen_ee_mumu::NGOOD) + 1.0;   // + average factor
 }
 
 }  // namespace rwgt

@@ -25,10 +25,12 @@ void constants_uu_eeg(int* npart, int* ngood, int* ncol, int* ndiag) {
   *ndiag = gen_uu_eeg::NDIAG;
 }
 
-// Floating-point operations of one |M|^2 (all kept helicities, colour sums,
-// average), counted by running the generated code on the host with OpCnt at a
-// representative point (beams along +-z, final state in generic directions).
-double flops_uu_eeg() {
+// Floating-point operations of one |M|^2 (helicities, colour sums, average),
+// counted by running the generated code on the host with OpCnt at a
+// representative point (beams along +-z, final state in generic directions):
+// executed = false, the plain sum over every kept helicity; true, the
+// helicities the kernels evaluate (NSUM, with the reversed ones as a weight).
+double flops_uu_eeg(bool executed) {
   constexpr int N = gen_uu_eeg::NPART;
   static const double pts[6][4] = {{500.0, 0.0, 0.0, 500.0}, {500.0, 0.0, 0.0, -500.0},
                                    {300.0, 110.0, -150.0, 90.0}, {250.0, -60.0, 120.0, -170.0},
@@ -53,7 +55,7 @@ double flops_uu_eeg() {
   gen_uu_eeg::jamps<OpCnt, OpCnt>(P, gen_uu_eeg::GOOD_HOST[0], cd, j);
   (void)gen_uu_eeg::colour_sum<OpCnt>(j);
   const double per_hel = double(OpCounter::flops) + 1.0;   // + accumulate into the sum
-  return per_hel * gen_uu_eeg::NGOOD + 1.0;                 // + average factor
+  return per_hel * (executed ? gen_uu_eeg::NSUM : gen_uu_eeg::NGOOD) + 1.0;   // + average factor
 }
 
 }  // namespace rwgt

@@ -983,7 +983,13 @@ int rwgt_cancellation(rwgt_ctx* ctx, const double* momenta, int64_t nevt, const 
 
 int rwgt_flops(const rwgt_ctx* ctx, double* flops_per_me2) {
   if (!ctx || !flops_per_me2) return RWGT_EINVAL;
-  *flops_per_me2 = rwgt::process_flops(ctx->def->id);
+  *flops_per_me2 = rwgt::process_flops(ctx->def->id, false);
+  return RWGT_OK;
+}
+
+int rwgt_flops_executed(const rwgt_ctx* ctx, double* flops_per_me2) {
+  if (!ctx || !flops_per_me2) return RWGT_EINVAL;
+  *flops_per_me2 = rwgt::process_flops(ctx->def->id, true);
   return RWGT_OK;
 }
 

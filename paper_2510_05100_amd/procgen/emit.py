@@ -2,6 +2,8 @@
 
 For each process the generated header defines, in namespace rwgt::gen_<name>:
   NPART, NCOL, NHEL, NGOOD, GOOD[] (helicities kept), AVERAGE,
+  NSUM, HELW (helicities the kernels evaluate: the first NSUM of GOOD, each
+  weighted by HELW),
   CNUM[NCOL][NCOL] (integer colour-matrix numerators), CDEN,
   jamps<R>(P, hel, card, jamp)  -- colour-flow amplitudes J for one helicity,
   colour_sum<R>(jamp)           -- J^dagger C J (real), with C = CNUM / CDEN.
@@ -9,6 +11,15 @@ Helicity hel is a bit pattern, bit (NPART-1-i) set meaning helicity +1 for
 particle i.  Helicities that vanish identically by the chirality of a
 massless fermion line (a vector coupling keeps chirality along the line) are
 dropped at generation time.
+
+Helicity parity.  With only vector couplings, real coupling constants and
+real propagators (pure QCD: no photon or Z exchange, no widths), reversing
+every helicity turns each external wavefunction into the complex conjugate
+of the original one up to a phase, so every colour-flow amplitude becomes
+the conjugate of the original times one common phase, and the colour sum
+J^dagger C J (C real) is unchanged: |M_h|^2 = |M_~h|^2 for every event.  For
+such processes GOOD lists one helicity of each reversed pair first (particle
+0 at -1) and the kernels evaluate those NSUM = NGOOD / 2 with weight 2.
 """
 from __future__ import annotations
 
@@ -47,6 +58,26 @@ def good_helicities(d: Diagrams) -> List[int]:
         if ok:
             good.append(hel)
     return good
+
+
+def parity_symmetric(d: Diagrams) -> bool:
+    """Pure QCD: no electroweak boson exchanged (chiral Z couplings and the Z
+    width break the relation between reversed helicities) and no lepton."""
+    return not d.pairs and all(not l.is_fermion or FERMIONS[l.field][2] for l in d.process.legs)
+
+
+def summed_helicities(d: Diagrams, good: List[int]):
+    """(GOOD in kernel order, NSUM, HELW): for a parity-symmetric process the
+    representatives of the reversed pairs (particle 0 at helicity -1) first."""
+    if not parity_symmetric(d):
+        return good, len(good), 1.0
+    n = len(d.process.legs)
+    full = (1 << n) - 1
+    kept = set(good)
+    assert all((full ^ h) in kept for h in good), "kept helicities not closed under reversal"
+    first = [h for h in good if not (h >> (n - 1)) & 1]
+    rest = [h for h in good if (h >> (n - 1)) & 1]
+    return first + rest, len(first), 2.0
 
 
 class Emitter:
@@ -538,7 +569,7 @@ def generate(d: Diagrams, groups: int | None = None) -> str:
     groups = groups or GROUPS.get(d.process.name, 1)
     em_g = emit_body(d, groups) if groups > 1 else em
     num, den = colour_matrix_ints(d)
-    good = good_helicities(d)
+    good, nsum, helw = summed_helicities(d, good_helicities(d))
     ncol = len(d.basis)
 
     out = []
@@ -564,6 +595,11 @@ def generate(d: Diagrams, groups: int | None = None) -> str:
     out.append(f"constexpr int NDIAG = {d.n_diagrams};")
     out.append(f"constexpr int NAMP = {len(d.terms)};")
     out.append(f"constexpr double AVERAGE = {d.process.average!r};")
+    if helw != 1.0:
+        out.append("// Pure QCD: reversing every helicity leaves |M_h|^2 unchanged; the first NSUM")
+        out.append("// kept helicities are one of each reversed pair, weighted by HELW.")
+    out.append(f"constexpr int NSUM = {nsum};")
+    out.append(f"constexpr double HELW = {helw!r};")
     out.append(f"constexpr int CDEN = {den};")
     out.append(f"static __constant__ int GOOD[NGOOD] = {{{', '.join(map(str, good))}}};")
     out.append(f"constexpr int GOOD_HOST[NGOOD] = {{{', '.join(map(str, good))}}};")

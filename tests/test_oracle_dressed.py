@@ -18,6 +18,16 @@ of g g -> t t~ t t~.
    by its momentum gives zero, per colour component, for each pairing alone
    and for their signed sum), Lorentz invariance, Bose symmetry of the
    gluons, symmetry under exchanging the two tops, exact alpha_s^4 scaling.
+4. Helicity reversal, the relation the device kernels of the pure-QCD
+   processes use to evaluate half of the helicities: with vector couplings,
+   real coupling constants and real propagators, reversing every helicity
+   conjugates each colour component of the amplitude up to one common phase,
+   so the colour-summed |M_h|^2 is unchanged (massive tops included).
+   Checked on g g -> t t~ g, g g -> t t~ g g and g g -> t t~ t t~ (both
+   pairings) per helicity, to 1e-13 of the helicity sum; and the control
+   that the relation does not hold with the chiral Z couplings and Z width of
+   u u~ -> e+ e- g (oracle/uu_eeg.py), where the generator keeps every
+   helicity.
 """
 
 import numpy as np
@@ -164,3 +174,48 @@ def test_gg_tttt_invariances_and_scaling():
     np.testing.assert_allclose(qd.me2_gg_tttt(p[:, [0, 1, 4, 3, 2, 5]], card), m0, rtol=1e-12)
     new = synth.NEW_QCD
     np.testing.assert_allclose(qd.me2_gg_tttt(p, new) / m0, (new.aS / card.aS) ** 4, rtol=1e-12)
+
+
+def _reversal_gap(p, legs, pairings, hels):
+    """Largest | |M_h|^2 - |M_~h|^2 | over hels, per event, and the sum over
+    hels of |M_h|^2 (colour-summed, per helicity)."""
+    gap = np.zeros(p.shape[0])
+    tot = np.zeros(p.shape[0])
+    for hel in hels:
+        a = qd.amplitude_for(p, legs, pairings, GS, hel)
+        b = qd.amplitude_for(p, legs, pairings, GS, tuple(-h for h in hel))
+        sa = np.sum(np.abs(a.reshape(p.shape[0], -1)) ** 2, axis=1)
+        sb = np.sum(np.abs(b.reshape(p.shape[0], -1)) ** 2, axis=1)
+        gap = np.maximum(gap, np.abs(sa - sb))
+        tot += sa + sb
+    return gap, tot
+
+
+def test_reversed_helicities_equal_in_qcd():
+    import itertools
+    p = _ggttg_events()
+    hels = [h for h in itertools.product((-1, 1), repeat=5) if h[0] == -1]
+    gap, tot = _reversal_gap(p, GGTTG, [(1.0, [(2, 3)])], hels)
+    assert np.all(tot > 0) and np.all(gap < 1e-13 * tot)
+    rng = np.random.default_rng(31)
+    p6 = _with_beams(synth.rambo_massive(rng, 2, [MT, MT, 0.0, 0.0], np.full(2, 1500.0)), 1500.0)
+    gg_ttgg = GGTTG + [L("g", False)]
+    hels6 = [(-1, 1, 1, -1, 1, 1), (-1, -1, 1, 1, -1, 1), (-1, 1, -1, -1, -1, -1), (-1, -1, -1, 1, 1, -1)]
+    gap, tot = _reversal_gap(p6, gg_ttgg, [(1.0, [(2, 3)])], hels6)
+    assert np.all(tot > 0) and np.all(gap < 1e-13 * tot)
+    p4 = _tttt_events(2, 32)
+    gap, tot = _reversal_gap(p4, qd.gg_tttt_legs(MT), qd.GG_TTTT_PAIRINGS, hels6)
+    assert np.all(tot > 0) and np.all(gap < 1e-13 * tot)
+
+
+def test_reversed_helicities_differ_with_z_exchange():
+    import itertools
+    from oracle import uu_eeg
+    from oracle.couplings import Couplings
+    p = synth.events("uu_eeg", 4, seed=33)
+    c = Couplings.from_card(synth.ORIG_EW)
+    hels = list(itertools.product((-1, 1), repeat=5))
+    m = {h: np.abs(uu_eeg.amplitude(p, c, h)) ** 2 for h in hels}
+    tot = sum(m.values())
+    gap = np.max([np.abs(m[h] - m[tuple(-x for x in h)]) for h in hels], axis=0)
+    assert np.all(gap > 0.05 * tot)
