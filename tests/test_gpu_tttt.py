@@ -124,3 +124,25 @@ def test_full_size_workload():
             wn, mh = out.cpu().numpy()[0], me.cpu().numpy()[0]
         assert rel_err(wn, np.full(n, RATIO)).max() < bar_w, prec
         assert rel_err(mh[idx], ref).max() < bar_me, prec
+
+
+def test_flop_counts_with_helicity_reversal():
+    """The pure-QCD processes evaluate one helicity of each reversed pair:
+    the executed count is half the plain sum over the 64 kept helicities (up
+    to the final averaging multiply); the electroweak processes evaluate every
+    kept helicity."""
+    import paper_2510_05100_amd as rw
+    from gpu_util import PROCESS_TEXT
+    torch_cuda()
+    for name, card, halved in (("gg_ttgg", synth.ORIG_QCD, True), ("gg_tttt", synth.ORIG_QCD, True),
+                               ("uu_eeg", synth.ORIG_EW, False), ("ee_mumu", synth.ORIG_EW, False)):
+        _case("flops", process=name)
+        with rw.Reweighter(PROCESS_TEXT[name], card.slha()) as r:
+            full, run = rw.rwgt_flops(r.ctx), rw.rwgt_flops_executed(r.ctx)
+            info = rw.rwgt_process_info(r.ctx)
+        assert full > 0 and run > 0
+        if halved:
+            assert info["nhel_kept"] == 64
+            assert abs((full - 1.0) / (run - 1.0) - 2.0) < 1e-12, (name, full, run)
+        else:
+            assert run == full, name
