@@ -90,6 +90,8 @@ class Emitter:
                       "ffv_vecm": 0, "vvv_vec": 0, "vvvv_vec": 0, "ffv_amp": 0, "pair_w": 0}
         self.n = 0
         self.two = d.term_lines is not None
+        self.fence_every = 1                     # a scheduling fence after every k-th term
+        self.nterms = 0
         self.line = (d.bleg.idx, d.fleg.idx)     # main line of the amplitude being emitted
 
     def lkey(self, kind, seq, line):
@@ -296,7 +298,9 @@ class Emitter:
                 expr = f"amp * cx<R>{{R({re}), R({im})}}"
             self.emit(f"jamp[{idx}] = jamp[{idx}] + {expr};")
         self.emit(f"note_amp(jamp, amp, {len(colour)});")
-        self.emit("term_fence();")
+        self.nterms += 1
+        if self.nterms % self.fence_every == 0:
+            self.emit("term_fence();")
 
 
 def colour_matrix_ints(d: Diagrams):
@@ -538,11 +542,16 @@ def refine_order(order, term_nodes, iters=30000, seed=20251005):
 # forgotten and rebuilt on demand (from opaque momentum reads, so nothing is
 # carried across): fewer currents live at once for some recomputation.
 GROUPS = {"gg_ttgg": 3, "gg_tttt": 2}
+# Terms between scheduling fences in the grouped (double-precision) body: the
+# scheduler may interleave the terms of one span; a fence after every term
+# and no fence at all both measured slower for g g -> t t~ g g.
+FENCE_EVERY = {"gg_ttgg": 20, "gg_tttt": 4}
 
 
-def emit_body(d: Diagrams, groups: int):
+def emit_body(d: Diagrams, groups: int, fence_every: int = 1):
     """Statements of the amplitude code with the terms split into groups."""
     em = Emitter(d)
+    em.fence_every = fence_every
     splits, shared = plan_splits(d)
     order = schedule(em, splits, shared)
     cuts = {round(g * len(order) / groups) for g in range(1, groups)}
@@ -567,7 +576,7 @@ def generate(d: Diagrams, groups: int | None = None) -> str:
     em = emit_body(d, 1)
     body = em.lines
     groups = groups or GROUPS.get(d.process.name, 1)
-    em_g = emit_body(d, groups) if groups > 1 else em
+    em_g = emit_body(d, groups, FENCE_EVERY.get(d.process.name, 1)) if groups > 1 else em
     num, den = colour_matrix_ints(d)
     good, nsum, helw = summed_helicities(d, good_helicities(d))
     ncol = len(d.basis)
