@@ -198,6 +198,19 @@ int rwgt_process_info(const rwgt_ctx *ctx, int32_t *npart, int32_t *nhel_kept, i
  * as FLOP/s against the peak (the algorithmic rate). */
 int rwgt_flops(const rwgt_ctx *ctx, double *flops_per_me2);
 
+/* Device bounds checks (test tooling, for callers that validate the
+ * library's index arithmetic).  The check build of the library
+ * (librwgt_check.so, compiled with -DRWGT_CHECK) compares every global-memory
+ * index of the matrix-element, ingest, cross-section, factored, running-alpha_s,
+ * non-finite-count, batched and card-per-event kernels with its array's extent;
+ * an index outside it is counted and its access redirected to a scratch sink.
+ * *enabled: 1 in the check build, 0 in the normal one (where *misses is 0).
+ * *misses: indices out of range since the previous call (the counters are
+ * cleared), summed over the kernels' translation units.  Reads device
+ * counters of the current device; call after the work has finished.
+ * Errors: RWGT_EINVAL (NULL argument), RWGT_EDEVICE (a counter copy failed). */
+int rwgt_bounds_check(int32_t *enabled, uint64_t *misses);
+
 /* The same count for the helicities the kernels actually evaluate.  For the
  * pure-QCD processes (g g > t t~ g g, g g > t t~ t t~) reversing every
  * helicity leaves |M_h|^2 unchanged (parity of QCD), so of the

@@ -20,7 +20,7 @@ from ._abi import (  # noqa: F401
 )
 from ._abi import (  # noqa: F401
     RWGT_FP64, RWGT_MIXED_BF16, RWGT_MIXED_FP16, RwgtError, load, rwgt_create, rwgt_destroy, rwgt_eval,
-    rwgt_flops, rwgt_flops_executed, rwgt_kernel_times, rwgt_me2, rwgt_original_params, rwgt_param_layout, rwgt_process_info,
+    rwgt_flops, rwgt_flops_executed, rwgt_bounds_check, rwgt_kernel_times, rwgt_me2, rwgt_original_params, rwgt_param_layout, rwgt_process_info,
     rwgt_set_profiling, rwgt_set_stream, rwgt_xsec, rwgt_eval_factored, rwgt_eval_alphas, rwgt_nonfinite,
 )
 from ._abi import (  # noqa: F401

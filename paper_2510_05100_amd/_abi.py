@@ -12,7 +12,9 @@ import os
 
 import numpy as np
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librwgt.so")
+# RWGT_LIBRARY=check selects the bounds-checked build (librwgt_check.so).
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                        "librwgt_check.so" if os.environ.get("RWGT_LIBRARY") == "check" else "librwgt.so")
 
 RWGT_FP64, RWGT_MIXED_FP16, RWGT_MIXED_BF16 = 0, 1, 2
 ERRORS = {-1: "RWGT_EINVAL", -2: "RWGT_EPROCESS", -3: "RWGT_ECARD", -4: "RWGT_EDEVICE",
@@ -41,6 +43,7 @@ SIGNATURES = {
     "rwgt_process_info": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int32)] * 4),
     "rwgt_flops": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "rwgt_flops_executed": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "rwgt_bounds_check": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint64)]),
     "rwgt_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "rwgt_kernel_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
                                           ctypes.POINTER(ctypes.c_float)]),
@@ -364,6 +367,16 @@ def rwgt_flops(ctx):
     if rc != 0:
         _raise(rc, ctx)
     return out.value
+
+
+def rwgt_bounds_check():
+    """(enabled, misses): whether this is the bounds-checked build, and the
+    out-of-range device indices counted since the previous call."""
+    en, n = ctypes.c_int32(), ctypes.c_uint64()
+    rc = load().rwgt_bounds_check(ctypes.byref(en), ctypes.byref(n))
+    if rc != 0:
+        _raise(rc, None)
+    return bool(en.value), int(n.value)
 
 
 def rwgt_flops_executed(ctx):

@@ -1,7 +1,10 @@
 """Build librwgt.so in-tree for gfx950: generate the per-process headers, then
-compile every translation unit with hipcc in parallel and link.
+compile every translation unit with hipcc in parallel and link.  With
+check=True, the bounds-checked variant librwgt_check.so (-DRWGT_CHECK: every
+global-memory index of the device kernels compared with its array's extent)
+from the same sources, into its own object folder.
 
-    python -m paper_2510_05100_amd.build [--jobs N] [--verbose]
+    python -m paper_2510_05100_amd.build [--jobs N] [--verbose] [--check]
 """
 from __future__ import annotations
 
@@ -17,6 +20,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librwgt.so")
+OBJ_CHECK = os.path.join(HERE, "_build_check")
+LIB_CHECK = os.path.join(HERE, "librwgt_check.so")
 ARCH = "gfx950"
 
 SOURCES = ["kernels.hip", "proc_ee_mumu.hip", "proc_uu_eeg.hip", "proc_gg_ttgg.hip", "proc_gg_tttt.hip", "batch.hip", "mlp.hip", "mlp_abi.cpp", "mlp_train.cpp", "rwgt_abi.cpp", "lhe.cpp"]
@@ -42,11 +47,11 @@ def _newest_input(src):
     return max(os.path.getmtime(p) for p in paths if os.path.exists(p))
 
 
-def _compile(src, verbose, incremental=False):
-    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+def _compile(src, verbose, incremental=False, check=False):
+    obj = os.path.join(OBJ_CHECK if check else OBJ, os.path.splitext(src)[0] + ".o")
     if incremental and os.path.exists(obj) and os.path.getmtime(obj) > _newest_input(src):
         return obj
-    cmd = [hipcc()] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc()] + HIP_FLAGS + (["-DRWGT_CHECK"] if check else []) + ["-c", os.path.join(CSRC, src), "-o", obj]
     t0 = time.time()
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
@@ -57,22 +62,23 @@ def _compile(src, verbose, incremental=False):
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False, check: bool = False) -> str:
     """Compile every source (or, with incremental=True, those whose inputs
-    changed) and link librwgt.so."""
+    changed) and link librwgt.so (check=True: librwgt_check.so)."""
     from .procgen.__main__ import main as procgen_main
     procgen_main(os.path.join(CSRC, "generated"))
-    os.makedirs(OBJ, exist_ok=True)
+    lib = LIB_CHECK if check else LIB
+    os.makedirs(OBJ_CHECK if check else OBJ, exist_ok=True)
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose, incremental), SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, verbose, incremental, check), SOURCES))
+    tmp = lib + ".tmp"
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr[-4000:]}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
@@ -80,7 +86,8 @@ if __name__ == "__main__":
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--incremental", action="store_true", help="recompile only changed translation units")
+    ap.add_argument("--check", action="store_true", help="the bounds-checked library librwgt_check.so")
     a = ap.parse_args()
     t = time.time()
-    print(build(a.jobs, a.verbose, a.incremental), f"({time.time() - t:.0f}s)")
+    print(build(a.jobs, a.verbose, a.incremental, a.check), f"({time.time() - t:.0f}s)")
     sys.exit(0)

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include "batch.h"
+#include "check.h"
 #include "generated/gen_ee_mumu.h"
 #include "generated/gen_uu_eeg.h"
 #include "me_kernel.h"
@@ -19,15 +20,15 @@ RWGT_PROCESS_TRAITS(uu_eeg)
 
 template <class R, class PROC>
 __device__ __forceinline__ void batch_event(const BatchSeg& sg, int64_t e, const CardPair& c0, const CardPair& c1) {
+  constexpr int W = PROC::NPART * 4;
   double P[PROC::NPART][4];
-  const double* src = sg.mom + e * (PROC::NPART * 4);
 #pragma unroll
   for (int a = 0; a < PROC::NPART; ++a)
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) P[a][mu] = src[a * 4 + mu];
+    for (int mu = 0; mu < 4; ++mu) P[a][mu] = RWGT_AT(sg.mom, e * W + a * 4 + mu, sg.nevt * W);
   const double m0 = me2_event<PROC, R>(P, pick<R>(c0));
   const double m1 = me2_event<PROC, R>(P, pick<R>(c1));
-  sg.w_out[e] = ((m0 == 0.0 ? 0.0 : 1.0 / m0) * sg.w_in[e]) * m1;
+  RWGT_AT(sg.w_out, e, sg.nevt) = ((m0 == 0.0 ? 0.0 : 1.0 / m0) * RWGT_AT(sg.w_in, e, sg.nevt)) * m1;
 }
 
 template <class R, class... PROCS>
@@ -45,16 +46,16 @@ __device__ __forceinline__ void batch_dispatch(int proc, const BatchSeg& sg, int
 // is the same to the bit) and writes w' = (w (1/|M|^2_0)) |M|^2_1.  Every lane
 // of the group must call it.
 template <class R, class PROC>
-__device__ __forceinline__ void hel_group_event(const double* __restrict__ src, int j, int lane0, const CardPair& c0,
-                                                const CardPair& c1, const double* __restrict__ w_in,
-                                                double* __restrict__ w_out) {
+__device__ __forceinline__ void hel_group_event(const double* __restrict__ mom, int64_t e, int64_t nevt, int j, int lane0,
+                                                const CardPair& c0, const CardPair& c1,
+                                                const double* __restrict__ w_in, double* __restrict__ w_out) {
   constexpr int G = PROC::NGOOD;
   static_assert(PROC::NSUM == G, "every kept helicity is evaluated (no reversed-helicity weight)");
   double P[PROC::NPART][4];
 #pragma unroll
   for (int a = 0; a < PROC::NPART; ++a)
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) P[a][mu] = src[a * 4 + mu];
+    for (int mu = 0; mu < 4; ++mu) P[a][mu] = RWGT_AT(mom, e * (PROC::NPART * 4) + a * 4 + mu, nevt * (PROC::NPART * 4));
   cx<R> jamp[PROC::NCOL];
   PROC::template jamps<R>(P, PROC::good(j % G), pick<R>(j < G ? c0 : c1), jamp);
   const double hm = double(PROC::template colour_sum<R>(jamp));
@@ -67,7 +68,7 @@ __device__ __forceinline__ void hel_group_event(const double* __restrict__ src, 
   if (j == 0) {
     m0 *= PROC::AVERAGE;
     m1 *= PROC::AVERAGE;
-    *w_out = ((m0 == 0.0 ? 0.0 : 1.0 / m0) * *w_in) * m1;
+    RWGT_AT(w_out, e, nevt) = ((m0 == 0.0 ? 0.0 : 1.0 / m0) * RWGT_AT(w_in, e, nevt)) * m1;
   }
 }
 
@@ -87,13 +88,13 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchSeg* __restrict__
     int lo = 0, hi = nseg - 1;                 // last segment with tile0 <= tile
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (segs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+      if (RWGT_AT(segs, mid, nseg).tile0 <= tile) lo = mid; else hi = mid - 1;
     }
-    const BatchSeg sg = segs[lo];
+    const BatchSeg sg = RWGT_AT(segs, lo, nseg);
     const int64_t e0 = (tile - sg.tile0) * tile_events;
     const int64_t e1 = e0 + tile_events < sg.nevt ? e0 + tile_events : sg.nevt;
     for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
-      batch_dispatch<R, PROCS...>(sg.proc, sg, e, cards[2 * lo], cards[2 * lo + 1]);
+      batch_dispatch<R, PROCS...>(sg.proc, sg, e, RWGT_AT(cards, 2 * lo, 2 * nseg), RWGT_AT(cards, 2 * lo + 1, 2 * nseg));
   }
 }
 
@@ -108,7 +109,7 @@ __device__ __forceinline__ void hel_tile(const BatchSeg& sg, int64_t e0, int64_t
   const int j = int(threadIdx.x) % G2;
   const int lane0 = int(threadIdx.x & 63) - j;
   for (int64_t e = e0 + threadIdx.x / G2; e < e1; e += blockDim.x / G2)
-    hel_group_event<R, PROC>(sg.mom + e * (PROC::NPART * 4), j, lane0, c0, c1, sg.w_in + e, sg.w_out + e);
+    hel_group_event<R, PROC>(sg.mom, e, sg.nevt, j, lane0, c0, c1, sg.w_in, sg.w_out);
 }
 
 // The persistent batch kernel with the helicity split: tiles claimed as in
@@ -127,13 +128,14 @@ __global__ __launch_bounds__(256) void batch_hel_kernel(const BatchSeg* __restri
     int lo = 0, hi = nseg - 1;                 // last segment with tile0 <= tile
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (segs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+      if (RWGT_AT(segs, mid, nseg).tile0 <= tile) lo = mid; else hi = mid - 1;
     }
-    const BatchSeg sg = segs[lo];
+    const BatchSeg sg = RWGT_AT(segs, lo, nseg);
     const int64_t e0 = (tile - sg.tile0) * tile_events;
     const int64_t e1 = e0 + tile_events < sg.nevt ? e0 + tile_events : sg.nevt;
     int idx = 0;
-    ((sg.proc == idx++ ? hel_tile<R, PROCS>(sg, e0, e1, cards[2 * lo], cards[2 * lo + 1]) : void()), ...);
+    ((sg.proc == idx++ ? hel_tile<R, PROCS>(sg, e0, e1, RWGT_AT(cards, 2 * lo, 2 * nseg), RWGT_AT(cards, 2 * lo + 1, 2 * nseg))
+                       : void()), ...);
   }
 }
 
@@ -177,13 +179,14 @@ __global__ __launch_bounds__(256) void exact_hel_kernel(const double* __restrict
   const int lane0 = int(threadIdx.x & 63) - j;             // the group's first lane in the wave
   const int64_t per_block = blockDim.x / G2;
   for (int64_t i = int64_t(blockIdx.x) * per_block + threadIdx.x / G2; i < n; i += int64_t(gridDim.x) * per_block) {
-    const int64_t e = list ? int64_t(list[i]) : i;
-    const int32_t k = card_index[e];
+    const int64_t e = list ? int64_t(RWGT_AT(list, i, n_all)) : i;
+    const int32_t k = RWGT_AT(card_index, e, n_all);
     if (k < 0 || k >= ncards) {
-      if (j == 0) w_out[e] = __builtin_nan("");
+      if (j == 0) RWGT_AT(w_out, e, n_all) = __builtin_nan("");
       continue;
     }
-    hel_group_event<R, PROC>(mom + e * (PROC::NPART * 4), j, lane0, cards[0], cards[1 + k], w_in + e, w_out + e);
+    hel_group_event<R, PROC>(mom, e, n_all, j, lane0, RWGT_AT(cards, 0, ncards + 1), RWGT_AT(cards, 1 + k, ncards + 1),
+                             w_in, w_out);
   }
 }
 

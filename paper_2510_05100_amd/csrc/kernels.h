@@ -58,9 +58,10 @@ struct FactorCard {
 
 // w_out[k-1][i] for cards fc[1..ncards) against fc[0] from the probe |M|^2
 // (ew: [4][nevt] class probes and the resonant pair (ia, ib); else [1][nevt]).
-hipError_t launch_factored(bool ew, const double* soa, int64_t nevt, int ia, int ib, const double* probe, double mzp,
-                           double wzp, const FactorCard* fc, int ncards, const double* w_in, double* w_out,
-                           hipStream_t s);
+// soa: [npart * 4][nevt].
+hipError_t launch_factored(bool ew, const double* soa, int npart, int64_t nevt, int ia, int ib, const double* probe,
+                           double mzp, double wzp, const FactorCard* fc, int ncards, const double* w_in,
+                           double* w_out, hipStream_t s);
 
 // w_out[k][i] *= (alpha_k(mu_i)/alpha_k)^p (alpha_0/alpha_0(i))^p (per-event strong coupling).
 hipError_t launch_alphas(double* w_out, int64_t nevt, int nsets, const double* alphas_orig, const double* scales,

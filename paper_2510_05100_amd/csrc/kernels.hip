@@ -8,6 +8,7 @@
 
 #include <cstdint>
 
+#include "check.h"
 #include "kernels.h"
 
 namespace rwgt {
@@ -23,12 +24,11 @@ __global__ __launch_bounds__(256) void ingest_kernel(const double* __restrict__ 
   __shared__ double tile[kIngestEvents][W + 1];
   const int64_t e0 = int64_t(blockIdx.x) * kIngestEvents;
   const int64_t nloc = (nevt - e0) < kIngestEvents ? (nevt - e0) : kIngestEvents;
-  const double* src = aos + e0 * W;
-  for (int t = threadIdx.x; t < nloc * W; t += blockDim.x) tile[t / W][t % W] = src[t];
+  for (int t = threadIdx.x; t < nloc * W; t += blockDim.x) tile[t / W][t % W] = RWGT_AT(aos, e0 * W + t, nevt * W);
   __syncthreads();
   for (int t = threadIdx.x; t < kIngestEvents * W; t += blockDim.x) {
     const int c = t / kIngestEvents, e = t % kIngestEvents;
-    if (e < nloc) soa[int64_t(c) * nevt + e0 + e] = tile[e][c];
+    if (e < nloc) RWGT_AT(soa, int64_t(c) * nevt + e0 + e, nevt * W) = tile[e][c];
   }
 }
 
@@ -62,12 +62,13 @@ __global__ __launch_bounds__(kXsecBlock) void xsec_pass1(const double* __restric
                                                          double* __restrict__ part) {
   __shared__ double sh[2][kXsecBlock];
   const int k = blockIdx.y;
-  const double* wo = w_out + int64_t(k) * nevt;
+  const int64_t nw = int64_t(gridDim.y) * nevt;            // w_out: [nsets][nevt], nsets = gridDim.y
   double v[2] = {0.0, 0.0};
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nevt; i += int64_t(gridDim.x) * blockDim.x) {
-    const double x = wo[i];
+    const double x = RWGT_AT(w_out, int64_t(k) * nevt + i, nw);
+    const double wi = RWGT_AT(w_in, i, nevt);
     v[0] += x;
-    v[1] += w_in[i] != 0.0 ? x / w_in[i] : 0.0;
+    v[1] += wi != 0.0 ? x / wi : 0.0;
   }
   block_sum<2>(sh, v, part + (int64_t(k) * gridDim.x + blockIdx.x) * 2);
 }
@@ -78,13 +79,14 @@ __global__ __launch_bounds__(64) void xsec_mean(const double* __restrict__ part,
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nsets) return;
   double s1 = 0.0, r = 0.0;
+  const int64_t np = int64_t(nsets) * nblocks * 2;
   for (int b = 0; b < nblocks; ++b) {
-    s1 += part[(int64_t(k) * nblocks + b) * 2];
-    r += part[(int64_t(k) * nblocks + b) * 2 + 1];
+    s1 += RWGT_AT(part, (int64_t(k) * nblocks + b) * 2, np);
+    r += RWGT_AT(part, (int64_t(k) * nblocks + b) * 2 + 1, np);
   }
-  sums[k * 3 + 0] = s1;
-  sums[k * 3 + 1] = r;
-  sums[k * 3 + 2] = s1 / double(nevt);
+  RWGT_AT(sums, k * 3 + 0, nsets * 3) = s1;
+  RWGT_AT(sums, k * 3 + 1, nsets * 3) = r;
+  RWGT_AT(sums, k * 3 + 2, nsets * 3) = s1 / double(nevt);
 }
 
 // Pass 2: block partials of sum (w' - m)^2 -> part2[k][block].
@@ -93,11 +95,11 @@ __global__ __launch_bounds__(kXsecBlock) void xsec_pass2(const double* __restric
                                                          double* __restrict__ part2) {
   __shared__ double sh[1][kXsecBlock];
   const int k = blockIdx.y;
-  const double* wo = w_out + int64_t(k) * nevt;
-  const double m = sums[k * 3 + 2];
+  const int64_t nw = int64_t(gridDim.y) * nevt;
+  const double m = RWGT_AT(sums, k * 3 + 2, int64_t(gridDim.y) * 3);
   double v[1] = {0.0};
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nevt; i += int64_t(gridDim.x) * blockDim.x) {
-    const double d = wo[i] - m;
+    const double d = RWGT_AT(w_out, int64_t(k) * nevt + i, nw) - m;
     v[0] += d * d;
   }
   block_sum<1>(sh, v, part2 + int64_t(k) * gridDim.x + blockIdx.x);
@@ -109,19 +111,19 @@ __global__ __launch_bounds__(64) void xsec_final(const double* __restrict__ sums
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nsets) return;
   double s2 = 0.0;
-  for (int b = 0; b < nblocks; ++b) s2 += part2[int64_t(k) * nblocks + b];
+  for (int b = 0; b < nblocks; ++b) s2 += RWGT_AT(part2, int64_t(k) * nblocks + b, int64_t(nsets) * nblocks);
   const double n = double(nevt);
-  const double xs = norm * sums[k * 3 + 0];
-  double err = dsigma * (sums[k * 3 + 1] / n) + sigma * sqrt(s2 / n);
+  const double xs = norm * RWGT_AT(sums, k * 3 + 0, nsets * 3);
+  double err = dsigma * (RWGT_AT(sums, k * 3 + 1, nsets * 3) / n) + sigma * sqrt(s2 / n);
   double fallback = 0.0;
   if (!(err > 0.0) || isinf(err)) {
     const double a = xs / sigma, b = sigma / xs;
     err = dsigma * (a > b ? a : b);
     fallback = 1.0;
   }
-  out[k * 3 + 0] = xs;
-  out[k * 3 + 1] = err;
-  out[k * 3 + 2] = fallback;
+  RWGT_AT(out, k * 3 + 0, nsets * 3) = xs;
+  RWGT_AT(out, k * 3 + 1, nsets * 3) = err;
+  RWGT_AT(out, k * 3 + 2, nsets * 3) = fallback;
 }
 
 hipError_t launch_xsec(const double* w_in, const double* w_out, int64_t nevt, int nsets, double sigma, double dsigma,
@@ -149,7 +151,8 @@ hipError_t launch_xsec(const double* w_in, const double* w_out, int64_t nevt, in
 // change alpha_s only): |M|^2 = g |M|^2_probe with g = (g_s / g_s,0)^8.
 // Card 0 is the original card; w_out[k-1][i] = (w_in[i] / |M|^2_0) |M|^2_k.
 template <bool EW>
-__global__ __launch_bounds__(256) void factored_kernel(const double* __restrict__ soa, int64_t nevt, int ia, int ib,
+__global__ __launch_bounds__(256) void factored_kernel(const double* __restrict__ soa, int64_t nsoa, int64_t nevt,
+                                                       int ia, int ib,
                                                        const double* __restrict__ probe, double mzp, double wzp,
                                                        const FactorCard* __restrict__ fc, int ncards,
                                                        const double* __restrict__ w_in, double* __restrict__ w_out) {
@@ -161,16 +164,16 @@ __global__ __launch_bounds__(256) void factored_kernel(const double* __restrict_
     double pa[4], pb[4];
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
-      pa[mu] = soa[int64_t(ia * 4 + mu) * nevt + i];
-      pb[mu] = soa[int64_t(ib * 4 + mu) * nevt + i];
+      pa[mu] = RWGT_AT(soa, int64_t(ia * 4 + mu) * nevt + i, nsoa);
+      pb[mu] = RWGT_AT(soa, int64_t(ib * 4 + mu) * nevt + i, nsoa);
     }
     s = 2.0 * (pa[0] * pb[0] - pa[1] * pb[1] - pa[2] * pb[2] - pa[3] * pb[3]);
     const double xp = s - mzp * mzp, yp = mzp * wzp;
     const double dp = xp * xp + yp * yp;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) W[c] = probe[int64_t(c) * nevt + i] * dp;
+    for (int c = 0; c < 4; ++c) W[c] = RWGT_AT(probe, int64_t(c) * nevt + i, 4 * nevt) * dp;
   } else {
-    W[0] = probe[i];
+    W[0] = RWGT_AT(probe, i, nevt);
   }
   auto me2 = [&](const FactorCard& k) {
     if constexpr (EW) {
@@ -188,22 +191,24 @@ __global__ __launch_bounds__(256) void factored_kernel(const double* __restrict_
       return k.g * W[0];
     }
   };
-  const double m0 = me2(fc[0]);
-  const double norm = m0 != 0.0 ? w_in[i] * (1.0 / m0) : 0.0;
-  for (int k = 1; k < ncards; ++k) w_out[int64_t(k - 1) * nevt + i] = norm * me2(fc[k]);
+  const double m0 = me2(RWGT_AT(fc, 0, ncards));
+  const double norm = m0 != 0.0 ? RWGT_AT(w_in, i, nevt) * (1.0 / m0) : 0.0;
+  for (int k = 1; k < ncards; ++k)
+    RWGT_AT(w_out, int64_t(k - 1) * nevt + i, int64_t(ncards - 1) * nevt) = norm * me2(RWGT_AT(fc, k, ncards));
 }
 
-hipError_t launch_factored(bool ew, const double* soa, int64_t nevt, int ia, int ib, const double* probe, double mzp,
-                           double wzp, const FactorCard* fc, int ncards, const double* w_in, double* w_out,
-                           hipStream_t s) {
+hipError_t launch_factored(bool ew, const double* soa, int npart, int64_t nevt, int ia, int ib, const double* probe,
+                           double mzp, double wzp, const FactorCard* fc, int ncards, const double* w_in,
+                           double* w_out, hipStream_t s) {
   if (nevt <= 0) return hipSuccess;
   const unsigned blocks = unsigned((nevt + 255) / 256);
+  const int64_t nsoa = int64_t(npart) * 4 * nevt;
   if (ew)
-    hipLaunchKernelGGL(factored_kernel<true>, dim3(blocks), dim3(256), 0, s, soa, nevt, ia, ib, probe, mzp, wzp, fc,
-                       ncards, w_in, w_out);
+    hipLaunchKernelGGL(factored_kernel<true>, dim3(blocks), dim3(256), 0, s, soa, nsoa, nevt, ia, ib, probe, mzp, wzp,
+                       fc, ncards, w_in, w_out);
   else
-    hipLaunchKernelGGL(factored_kernel<false>, dim3(blocks), dim3(256), 0, s, soa, nevt, ia, ib, probe, mzp, wzp, fc,
-                       ncards, w_in, w_out);
+    hipLaunchKernelGGL(factored_kernel<false>, dim3(blocks), dim3(256), 0, s, soa, nsoa, nevt, ia, ib, probe, mzp, wzp,
+                       fc, ncards, w_in, w_out);
   return hipGetLastError();
 }
 
@@ -224,16 +229,16 @@ __global__ __launch_bounds__(256) void alphas_kernel(double* __restrict__ w_out,
                                                      double mref2) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= nevt) return;
-  const double mu = scales[i];
-  const double a0 = alphas_orig ? alphas_orig[i] : run_alphas(as0, mu, b0, mref2);
+  const double mu = RWGT_AT(scales, i, nevt);
+  const double a0 = alphas_orig ? RWGT_AT(alphas_orig, i, nevt) : run_alphas(as0, mu, b0, mref2);
   const bool zero = a0 == 0.0;             // |M|^2 of the original is 0: w' = 0
   const double r0 = zero ? 0.0 : as0 / a0;
   for (int k = 0; k < nsets; ++k) {
-    const double ak = as_cards[k];
+    const double ak = RWGT_AT(as_cards, k, nsets);
     const double rk = ak != 0.0 ? run_alphas(ak, mu, b0, mref2) / ak : 1.0;
     double f = 1.0, x = rk * r0;
     for (int q = 0; q < p; ++q) f *= x;
-    double& w = w_out[int64_t(k) * nevt + i];
+    double& w = RWGT_AT(w_out, int64_t(k) * nevt + i, int64_t(nsets) * nevt);
     w = zero ? 0.0 : w * f;
   }
 }
@@ -254,11 +259,12 @@ __global__ __launch_bounds__(256) void nonfinite_kernel(const double* __restrict
   __shared__ unsigned long long wsum[4];
   unsigned long long c = 0;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) c += isfinite(x[i]) ? 0 : 1;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    c += isfinite(RWGT_AT(x, i, n)) ? 0 : 1;
   for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o);
   if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
   __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  if (threadIdx.x == 0) RWGT_AT(part, blockIdx.x, gridDim.x) = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
 int nonfinite_blocks(int64_t n) {

@@ -9,6 +9,7 @@
 #include <type_traits>
 
 #include "card.h"
+#include "check.h"
 #include "colour_mfma.h"
 #include "kernels.h"
 
@@ -153,13 +154,13 @@ __global__ __launch_bounds__(kMeBlock) void me_kernel(const double* __restrict__
   }
   const bool valid = r < nrows;
   const int64_t rr = valid ? r : nrows - 1;
-  const int64_t i = INDEXED ? int64_t(g.rows[rr]) : rr;      // the event of this lane
+  const int64_t i = INDEXED ? int64_t(RWGT_AT(g.rows, rr, nevt)) : rr;   // the event of this lane
   const int64_t ie = i;
   double P[PROC::NPART][4];
 #pragma unroll
   for (int a = 0; a < PROC::NPART; ++a)
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) P[a][mu] = soa[int64_t(a * 4 + mu) * nevt + ie];
+    for (int mu = 0; mu < 4; ++mu) P[a][mu] = RWGT_AT(soa, int64_t(a * 4 + mu) * nevt + ie, PROC::NPART * 4 * nevt);
 
   [[maybe_unused]] __shared__ cx<R> lds_jamp[jamp_in_lds<PROC, R>() ? PROC::NCOL * B : 1];
   [[maybe_unused]] __shared__ typename ColourLdsOf<CT>::type lds_colour[kMfma ? B / 64 : 1];
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(kMeBlock) void me_kernel(const double* __restrict__
   double norm = 0.0;
   [[maybe_unused]] double kappa = 0.0;
   for (int k = 0; k < ncards; ++k) {
-    const Card<R>& cd = pick<R>(cards[k]);
+    const Card<R>& cd = pick<R>(RWGT_AT(cards, k, ncards));
     double me = 0.0;
     [[maybe_unused]] double inco = 0.0, coh = 0.0;
     for (int ih = half * NH; ih < (half + 1) * NH; ++ih) {
@@ -224,19 +225,19 @@ __global__ __launch_bounds__(kMeBlock) void me_kernel(const double* __restrict__
     }
     me *= PROC::SCALE;                           // average (and the reversed helicities)
     if (!valid || half != 0) continue;
-    if (me_out) me_out[int64_t(k) * nevt + i] = me;
+    if (me_out) RWGT_AT(me_out, int64_t(k) * nevt + i, int64_t(ncards) * nevt) = me;
     if (w_out) {
       if (k == 0) {
-        norm = (me == 0.0 ? 0.0 : 1.0 / me) * w_in[i];
+        norm = (me == 0.0 ? 0.0 : 1.0 / me) * RWGT_AT(w_in, i, nevt);
       } else {
-        w_out[int64_t(k - 1) * nevt + i] = norm * me;
+        RWGT_AT(w_out, int64_t(k - 1) * nevt + i, int64_t(ncards - 1) * nevt) = norm * me;
       }
     }
   }
   if constexpr (GUARD) {
     if (valid && half == 0) {
-      if (g.kappa) g.kappa[i] = kappa;
-      if (g.flagged && !(kappa <= g.kmax)) g.flagged[atomicAdd(g.nflagged, 1u)] = int32_t(i);
+      if (g.kappa) RWGT_AT(g.kappa, i, nevt) = kappa;
+      if (g.flagged && !(kappa <= g.kmax)) RWGT_AT(g.flagged, atomicAdd(g.nflagged, 1u), nevt) = int32_t(i);
     }
   }
 }
@@ -266,16 +267,16 @@ __global__ __launch_bounds__(64) void me_wave_kernel(const double* __restrict__ 
   const int ih = lane < NG ? lane : NG - 1;
   const int64_t n = int64_t(*nrows);
   for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
-    const int64_t i = int64_t(rows[r]);
+    const int64_t i = int64_t(RWGT_AT(rows, r, nevt));
     double P[PROC::NPART][4];
 #pragma unroll
     for (int a = 0; a < PROC::NPART; ++a)
 #pragma unroll
-      for (int mu = 0; mu < 4; ++mu) P[a][mu] = soa[int64_t(a * 4 + mu) * nevt + i];
+      for (int mu = 0; mu < 4; ++mu) P[a][mu] = RWGT_AT(soa, int64_t(a * 4 + mu) * nevt + i, PROC::NPART * 4 * nevt);
     double norm = 0.0;
     for (int k = 0; k < ncards; ++k) {
       LdsJamp<double, PROC::NCOL, 64> jamp{lds_jamp + lane};
-      PROC::template jamps_grouped<double>(P, PROC::good(ih), cards[k].d, jamp);
+      PROC::template jamps_grouped<double>(P, PROC::good(ih), RWGT_AT(cards, k, ncards).d, jamp);
       const double hm = double(PROC::template colour_sum<double>(jamp));
       double m0 = 0.0, m1 = 0.0;
       for (int h = 0; h < NG / 2; ++h) m0 += __shfl(hm, h);
@@ -284,12 +285,12 @@ __global__ __launch_bounds__(64) void me_wave_kernel(const double* __restrict__ 
       me += m1;
       me *= PROC::SCALE;
       if (lane == 0) {
-        if (me_out) me_out[int64_t(k) * nevt + i] = me;
+        if (me_out) RWGT_AT(me_out, int64_t(k) * nevt + i, int64_t(ncards) * nevt) = me;
         if (w_out) {
           if (k == 0) {
-            norm = (me == 0.0 ? 0.0 : 1.0 / me) * w_in[i];
+            norm = (me == 0.0 ? 0.0 : 1.0 / me) * RWGT_AT(w_in, i, nevt);
           } else {
-            w_out[int64_t(k - 1) * nevt + i] = norm * me;
+            RWGT_AT(w_out, int64_t(k - 1) * nevt + i, int64_t(ncards - 1) * nevt) = norm * me;
           }
         }
       }

@@ -20,6 +20,9 @@
 
 #include "../../include/rwgt.h"
 #include "batch.h"
+#define RWGT_CHECK_REGISTRY_ONLY
+#include "check.h"
+#undef RWGT_CHECK_REGISTRY_ONLY
 #include "kernels.h"
 #include "mlp.h"
 #include "mlp_internal.h"
@@ -446,6 +449,19 @@ struct Staged {
 
 }  // namespace
 
+namespace rwgt {
+
+// Readers of the device bounds-check counters (check build only: every
+// checked translation unit registers one while the library loads).
+std::vector<BoundsReader>& bounds_readers() {
+  static std::vector<BoundsReader> readers;
+  return readers;
+}
+
+void register_bounds_reader(BoundsReader f) { bounds_readers().push_back(f); }
+
+}  // namespace rwgt
+
 extern "C" {
 
 int rwgt_create(const char* process, const char* param_card, int precision, rwgt_ctx** out) {
@@ -657,8 +673,8 @@ int rwgt_eval_factored(rwgt_ctx* c, const double* momenta, int64_t nevt, const d
       e = rwgt::launch_me(id, c->precision, c->soa, nevt, c->dcards, nprobe, nullptr, nullptr, c->fac_probe,
                           c->stream);
     if (e == hipSuccess)
-      e = rwgt::launch_factored(ew, c->soa, nevt, ia, ib, c->fac_probe, o.mz, o.wz, c->fac_cards, int(fc.size()), w_in,
-                                w_out, c->stream);
+      e = rwgt::launch_factored(ew, c->soa, c->def->npart, nevt, ia, ib, c->fac_probe, o.mz, o.wz, c->fac_cards,
+                                int(fc.size()), w_in, w_out, c->stream);
     if (e != hipSuccess) return c->hip_fail(e, "factored evaluation");
     return count_nonfinite(c, w_out, int64_t(nsets) * nevt);
   } catch (const std::exception& ex) {
@@ -984,6 +1000,20 @@ int rwgt_cancellation(rwgt_ctx* ctx, const double* momenta, int64_t nevt, const 
 int rwgt_flops(const rwgt_ctx* ctx, double* flops_per_me2) {
   if (!ctx || !flops_per_me2) return RWGT_EINVAL;
   *flops_per_me2 = rwgt::process_flops(ctx->def->id, false);
+  return RWGT_OK;
+}
+
+int rwgt_bounds_check(int32_t* enabled, uint64_t* misses) {
+  if (!enabled || !misses) return RWGT_EINVAL;
+  const auto& readers = rwgt::bounds_readers();
+  *enabled = readers.empty() ? 0 : 1;
+  uint64_t total = 0;
+  for (rwgt::BoundsReader f : readers) {
+    const unsigned long long v = f();
+    if (v == ~0ull) return RWGT_EDEVICE;
+    total += v;
+  }
+  *misses = total;
   return RWGT_OK;
 }
 

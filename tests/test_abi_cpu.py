@@ -40,6 +40,22 @@ def test_every_declared_symbol_exported(lib):
         assert name in _abi.SIGNATURES, name
 
 
+def test_check_build_exports_the_same_symbols(lib):
+    """The bounds-checked build (librwgt_check.so) exports the same boundary;
+    the normal build reports the checks compiled away (enabled 0, no misses,
+    without touching a device) and rejects NULL arguments."""
+    path = os.path.join(ROOT, "paper_2510_05100_amd", "librwgt_check.so")
+    if not os.path.exists(path):
+        pytest.skip("librwgt_check.so not built (python -m paper_2510_05100_amd.build --check)")
+    chk = ctypes.CDLL(path)
+    for name in declared_functions():
+        assert hasattr(chk, name), name
+    en, n = ctypes.c_int32(-1), ctypes.c_uint64(7)
+    assert lib.rwgt_bounds_check(ctypes.byref(en), ctypes.byref(n)) == 0
+    assert (en.value, n.value) == (0, 0)
+    assert lib.rwgt_bounds_check(None, ctypes.byref(n)) == -1
+
+
 def test_create_rejects_bad_arguments(lib):
     from paper_2510_05100_amd import _abi
     out = ctypes.c_void_p()
