@@ -34,7 +34,7 @@ PEAK_FP32_VALU_UNPACKED = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz wi
 # WRITE_SIZE counter passes (scaled by a copy kernel of known size); valid only
 # for the kernel sources they were taken on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "me_kernel_gg_ttgg_1e6_traffic.json")
-KERNEL_SOURCES = ["me_kernel.h", "kernels.h", "helas.h", "card.h", "colour_mfma.h", "proc_gg_ttgg.hip",
+KERNEL_SOURCES = ["me_kernel.h", "kernels.h", "helas.h", "card.h", "check.h", "colour_mfma.h", "proc_gg_ttgg.hip",
                   "generated/gen_gg_ttgg.h"]
 
 
