@@ -81,6 +81,33 @@ def build(jobs: int | None = None, verbose: bool = False, incremental: bool = Fa
     return lib
 
 
+def build_all(jobs: int | None = None, verbose: bool = False) -> tuple:
+    """Both libraries (librwgt.so and librwgt_check.so), their translation
+    units compiled in one pool, longest first."""
+    from .procgen.__main__ import main as procgen_main
+    procgen_main(os.path.join(CSRC, "generated"))
+    os.makedirs(OBJ, exist_ok=True)
+    os.makedirs(OBJ_CHECK, exist_ok=True)
+    slow = ["proc_gg_ttgg.hip", "proc_gg_tttt.hip", "mlp.hip"]             # the longest compiles start first
+    order = slow + [s for s in SOURCES if s not in slow]
+    tasks = [(s, c) for s in order for c in (False, True)]
+    jobs = jobs or (os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda t: _compile(t[0], verbose, False, t[1]), tasks))
+    out = []
+    for check in (False, True):
+        lib = LIB_CHECK if check else LIB
+        mine = [o for (s, c), o in zip(tasks, objs) if c == check]
+        tmp = lib + ".tmp"
+        cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + mine
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError(f"link failed:\n{res.stderr[-4000:]}")
+        os.replace(tmp, lib)
+        out.append(lib)
+    return tuple(out)
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
