@@ -1085,11 +1085,16 @@ std::string tune_cache_path() {
   return std::string(home ? home : "/tmp") + "/.rwgt_autotune";
 }
 
+// Key of a tuned schedule: the target, the HIP runtime version (a new ROCm
+// may schedule the same kernels differently), the family, precision, segment
+// count and event count (log2).
 std::string tune_key(const rwgt_batch* b, int nseg, int64_t events) {
   int lg = 0;
   while ((int64_t(1) << (lg + 1)) <= events) ++lg;
-  return "gfx950 family=" + std::to_string(b->family) + " prec=" + std::to_string(b->precision) +
-         " nseg=" + std::to_string(nseg) + " log2events=" + std::to_string(lg);
+  int rt = 0;
+  if (hipRuntimeGetVersion(&rt) != hipSuccess) rt = 0;
+  return "gfx950 hip=" + std::to_string(rt) + " family=" + std::to_string(b->family) +
+         " prec=" + std::to_string(b->precision) + " nseg=" + std::to_string(nseg) + " log2events=" + std::to_string(lg);
 }
 
 bool tune_lookup(const std::string& key, rwgt::BatchSchedule& out) {
