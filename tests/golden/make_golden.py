@@ -19,7 +19,8 @@ from oracle import reweight                    # noqa: E402
 
 CASES = (("ee_mumu", synth.ORIG_EW, synth.NEW_EE, 8),
          ("uu_eeg", synth.ORIG_EW, synth.NEW_UU, 8),
-         ("gg_ttgg", synth.ORIG_QCD, synth.NEW_QCD, 6))
+         ("gg_ttgg", synth.ORIG_QCD, synth.NEW_QCD, 6),
+         ("gg_tttt", synth.ORIG_QCD, synth.NEW_QCD, 3))
 
 
 def compute():
@@ -28,9 +29,8 @@ def compute():
     for proc, orig, new, n in CASES:
         p = synth.events(proc, n)
         w = [1.0] * n
-        me0 = reweight.me2(proc, p, orig)
-        me1 = reweight.me2(proc, p, new)
-        wn, _, _ = reweight.reweight(proc, p, w, orig, [new])
+        wn, me0, mk = reweight.reweight(proc, p, w, orig, [new])
+        me1 = mk[0]
         out["cases"].append({"process": proc, "events": n, "orig": orig.row(proc).tolist(),
                              "new": new.row(proc).tolist(), "me2_orig": [float(x) for x in me0],
                              "me2_new": [float(x) for x in me1], "w_new": [float(x) for x in wn[0]]})

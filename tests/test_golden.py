@@ -33,5 +33,5 @@ def test_stored_values_are_consistent():
         m0, m1, w = (np.array(c[k]) for k in ("me2_orig", "me2_new", "w_new"))
         assert np.all(m0 > 0) and np.all(m1 > 0)
         np.testing.assert_allclose(w, m1 / m0, rtol=1e-14)
-        if c["process"] == "gg_ttgg":                    # alpha_s only: (0.130/0.118)^4 on every event
+        if c["process"] in ("gg_ttgg", "gg_tttt"):       # alpha_s only: (0.130/0.118)^4 on every event
             np.testing.assert_allclose(w, (0.130 / 0.118) ** 4, rtol=1e-13)

@@ -227,8 +227,8 @@ def test_device_against_stored_oracle_values():
     with open(os.path.join(os.path.dirname(__file__), "golden", "me2_oracle.json")) as f:
         cases = json.load(f)["cases"]
     cards = {"ee_mumu": (synth.ORIG_EW, synth.NEW_EE), "uu_eeg": (synth.ORIG_EW, synth.NEW_UU),
-             "gg_ttgg": (synth.ORIG_QCD, synth.NEW_QCD)}
-    tol = {"ee_mumu": 1e-12, "uu_eeg": 1e-11, "gg_ttgg": 1e-10}
+             "gg_ttgg": (synth.ORIG_QCD, synth.NEW_QCD), "gg_tttt": (synth.ORIG_QCD, synth.NEW_QCD)}
+    tol = {"ee_mumu": 1e-12, "uu_eeg": 1e-11, "gg_ttgg": 1e-10, "gg_tttt": 1e-10}
     for c in cases:
         proc, n = c["process"], c["events"]
         orig, new = cards[proc]
