@@ -446,7 +446,10 @@ def main():
                 "frac": ach / peak, "traffic": measured_traffic(mode, a.events),
                 "kernel": "me_kernel<Proc_gg_ttgg>", "flops_per_launch": flops,
                 "executed_flops_per_launch": flops_exec, "executed_achieved": ach_exec / 1e12,
-                "executed_frac": ach_exec / peak}
+                "executed_frac": ach_exec / peak,
+                "flops_definition": "achieved/frac: the plain per-helicity sum over all 64 helicities (rwgt_flops); "
+                                    "executed_*: the 32 the kernel evaluates, one of each pair with every helicity "
+                                    "reversed, whose |M_h|^2 are equal in QCD (rwgt_flops_executed)"}
 
     main_mode = "fp64" if "fp64" in res else next(iter(res))
     m = res[main_mode]
