@@ -146,3 +146,31 @@ def test_flop_counts_with_helicity_reversal():
             assert abs((full - 1.0) / (run - 1.0) - 2.0) < 1e-12, (name, full, run)
         else:
             assert run == full, name
+
+
+@pytest.mark.parametrize("n", [1, 65, 127])
+def test_fp64_ragged_workgroups(n):
+    """A single event and partly filled last workgroups (64 events per
+    128-lane workgroup): the first and last events against the oracle."""
+    _case("gg_tttt_ragged", n=n)
+    p = synth.events("gg_tttt", n, seed=75)
+    idx = sorted({0, n - 1})
+    me = gpu_me2("gg_tttt", p, synth.ORIG_QCD, [synth.ORIG_QCD])[0]
+    assert np.all(np.isfinite(me)) and np.all(me > 0)
+    assert rel_err(me[idx], reweight.me2("gg_tttt", p[idx], synth.ORIG_QCD)).max() < 1e-10
+
+
+def test_several_cards_in_one_call():
+    """Five cards in one call (the two waves of each workgroup add their
+    helicity halves through LDS once per card): w'/w = (alpha_s'/0.118)^4
+    on every event for every card, the original card giving 1."""
+    import dataclasses
+    n = 300
+    _case("gg_tttt_cards", n=n)
+    p = synth.events("gg_tttt", n, seed=76)
+    alphas = (0.100, 0.118, 0.125, 0.130, 0.140)
+    cards = [dataclasses.replace(synth.ORIG_QCD, aS=a) for a in alphas]
+    w = np.linspace(0.5, 2.0, n)
+    wn = gpu_eval("gg_tttt", p, w, synth.ORIG_QCD, cards)
+    for k, a in enumerate(alphas):
+        assert np.max(np.abs(wn[k] / w / ((a / 0.118) ** 4) - 1)) < 1e-12, a
