@@ -46,8 +46,8 @@ __device__ __forceinline__ void batch_dispatch(int proc, const BatchSeg& sg, int
 // is the same to the bit) and writes w' = (w (1/|M|^2_0)) |M|^2_1.  Every lane
 // of the group must call it.
 template <class R, class PROC>
-__device__ __forceinline__ void hel_group_event(const double* __restrict__ mom, int64_t e, int64_t nevt, int j, int lane0,
-                                                const CardPair& c0, const CardPair& c1,
+__device__ __forceinline__ void hel_group_event(const double* __restrict__ mom, int64_t e, int64_t nevt, int j,
+                                                int lane0, const CardPair& c0, const CardPair& c1,
                                                 const double* __restrict__ w_in, double* __restrict__ w_out) {
   constexpr int G = PROC::NGOOD;
   static_assert(PROC::NSUM == G, "every kept helicity is evaluated (no reversed-helicity weight)");
@@ -55,7 +55,8 @@ __device__ __forceinline__ void hel_group_event(const double* __restrict__ mom, 
 #pragma unroll
   for (int a = 0; a < PROC::NPART; ++a)
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) P[a][mu] = RWGT_AT(mom, e * (PROC::NPART * 4) + a * 4 + mu, nevt * (PROC::NPART * 4));
+    for (int mu = 0; mu < 4; ++mu)
+      P[a][mu] = RWGT_AT(mom, e * (PROC::NPART * 4) + a * 4 + mu, nevt * (PROC::NPART * 4));
   cx<R> jamp[PROC::NCOL];
   PROC::template jamps<R>(P, PROC::good(j % G), pick<R>(j < G ? c0 : c1), jamp);
   const double hm = double(PROC::template colour_sum<R>(jamp));
@@ -93,8 +94,9 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchSeg* __restrict__
     const BatchSeg sg = RWGT_AT(segs, lo, nseg);
     const int64_t e0 = (tile - sg.tile0) * tile_events;
     const int64_t e1 = e0 + tile_events < sg.nevt ? e0 + tile_events : sg.nevt;
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
-      batch_dispatch<R, PROCS...>(sg.proc, sg, e, RWGT_AT(cards, 2 * lo, 2 * nseg), RWGT_AT(cards, 2 * lo + 1, 2 * nseg));
+    const CardPair& c0 = RWGT_AT(cards, 2 * lo, 2 * nseg);
+    const CardPair& c1 = RWGT_AT(cards, 2 * lo + 1, 2 * nseg);
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) batch_dispatch<R, PROCS...>(sg.proc, sg, e, c0, c1);
   }
 }
 
@@ -133,9 +135,10 @@ __global__ __launch_bounds__(256) void batch_hel_kernel(const BatchSeg* __restri
     const BatchSeg sg = RWGT_AT(segs, lo, nseg);
     const int64_t e0 = (tile - sg.tile0) * tile_events;
     const int64_t e1 = e0 + tile_events < sg.nevt ? e0 + tile_events : sg.nevt;
+    const CardPair& c0 = RWGT_AT(cards, 2 * lo, 2 * nseg);
+    const CardPair& c1 = RWGT_AT(cards, 2 * lo + 1, 2 * nseg);
     int idx = 0;
-    ((sg.proc == idx++ ? hel_tile<R, PROCS>(sg, e0, e1, RWGT_AT(cards, 2 * lo, 2 * nseg), RWGT_AT(cards, 2 * lo + 1, 2 * nseg))
-                       : void()), ...);
+    ((sg.proc == idx++ ? hel_tile<R, PROCS>(sg, e0, e1, c0, c1) : void()), ...);
   }
 }
 

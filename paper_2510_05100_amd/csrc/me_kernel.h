@@ -249,9 +249,10 @@ static __global__ void zero_count_kernel(unsigned int* c) { *c = 0u; }
 // per evaluated helicity (the first NSUM kept ones): each lane evaluates its
 // helicity's |M_h|^2 (flows in LDS) under every card, and lane 0 adds the
 // lanes' values in me_kernel's order (the first half of the helicities in
-// sequence, the second half in sequence, then their sum).  The per-helicity code is me_kernel's, but with
-// the helicity per lane instead of per wave the compiler may round a last bit
-// differently (measured: within 1 ulp of me_kernel's result).
+// sequence, the second half in sequence, then their sum).  The per-helicity
+// code is me_kernel's, but with the helicity per lane instead of per wave the
+// compiler may round a last bit differently (measured: within 1 ulp of
+// me_kernel's result).
 // A short list keeps the chip busy for one helicity's evaluation per card,
 // where one lane per event would take a whole helicity loop.
 template <class PROC>
