@@ -80,10 +80,13 @@ struct ColourMfma {
     for (int c = 0; c < NCOL; ++c) mx = fmaxf(mx, fmaxf(fabsf(jamp[c].re), fabsf(jamp[c].im)));
     const int e = mx > 0.0f ? 14 - ilogbf(mx) : 0;
     const float s = ldexpf(1.0f, e);
+#pragma unroll
     for (int c = 0; c < NCOL; ++c) {
       float x[2] = {jamp[c].re * s, jamp[c].im * s};
+#pragma unroll
       for (int p = 0; p < 2; ++p) {
         float r = x[p];
+#pragma unroll
         for (int t = 0; t < NT; ++t) {
           const T q = T(r);
           lds.v[p][t][l][c] = q;
@@ -94,22 +97,30 @@ struct ColourMfma {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // every loop unrolled: with the three BF16 terms the compiler otherwise
+    // keeps a loop here, and the guarded kernel spilled 175 registers (2 now)
     float part[2] = {0.0f, 0.0f};
+#pragma unroll
     for (int p = 0; p < 2; ++p) {
+#pragma unroll
       for (int tile = 0; tile < 2; ++tile) {
         f32x16 acc = {};
         const int ev = 32 * tile + (l & 31);
+#pragma unroll
         for (int ks = 0; ks < KSTEPS; ++ks)
+#pragma unroll
           for (int t = 0; t < NT; ++t) {
             const vec b = *reinterpret_cast<const vec*>(&lds.v[p][t][ev][16 * ks + 8 * (l >> 5)]);
             acc = MfmaT<T>::mfma(a[ks], b, acc);
           }
         // lane l holds Z[row][ev] for row = 8 (i/4) + 4 (l/32) + i%4
         float dot = 0.0f;
+#pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int row = 8 * (i >> 2) + 4 * (l >> 5) + (i & 3);
           if (row < NCOL) {
             float xr = 0.0f;
+#pragma unroll
             for (int t = 0; t < NT; ++t) xr += float(lds.v[p][t][ev][row]);
             dot += xr * acc[i];
           }
